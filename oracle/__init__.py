@@ -1,0 +1,184 @@
+"""CPU oracle for the generalized Bellman-Ford method — TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package.  It shares no code with the HIP library
+(paper_2001_06231_amd); both are fed by the input generators in `synth`.
+
+Contents
+  gbf_oracle.c   Algorithm 1 of the paper (Sect. IV-A), single-threaded C,
+                 plus the canonical policy / residual pass, a box decoder and
+                 an independent min-max Dijkstra for non-negative costs.
+  brute.py       Brute force from the definitions of Sect. III: the operator
+                 P, Kleene iteration, policy evaluation and enumeration of
+                 memoryless strategies (tiny problems only).
+  mlp_ref.py     fp64 reference of the frontier-ordering MLP.
+
+Parity status: every function here is pinned by a `-m "not gpu"` test
+(worked example of the paper, brute force, Dijkstra, classical
+Bellman-Ford, invariants); see tests/test_oracle_*.py.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gbf_oracle.c")
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+OK, NEGCYCLE = 0, 1
+HANDOVER, NONE = -1, -2
+INF_I32 = 2**31 - 1
+
+_lock = threading.Lock()
+_lib = None
+
+
+class Counters(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("pair_evals", ctypes.c_int64),
+                ("edge_relax", ctypes.c_int64), ("improvements", ctypes.c_int64),
+                ("saturations", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+def build() -> str:
+    """Compile the oracle with gcc (no fast-math, no FP contraction)."""
+    tmp = LIB_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                           "-shared", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC):
+                build()
+            L = ctypes.CDLL(LIB_PATH)
+            P = ctypes.c_void_p
+            i64 = ctypes.c_int64
+            for nm in ("oracle_solve_i32", "oracle_solve_f64", "oracle_solve_f32"):
+                f = getattr(L, nm)
+                f.argtypes = [i64, i64, P, P, P, P, P, i64, P, P, ctypes.POINTER(Counters), P, P]
+                f.restype = ctypes.c_int
+            for nm in ("oracle_policy_i32", "oracle_policy_f64", "oracle_policy_f32"):
+                f = getattr(L, nm)
+                f.argtypes = [i64, i64, P, P, P, P, P, P, P]
+                f.restype = i64
+            L.oracle_box_to_csr.argtypes = [P, i64, P, P, P]
+            L.oracle_box_to_csr.restype = i64
+            L.oracle_dijkstra_i32.argtypes = [i64, i64, P, P, P, P, P, P]
+            L.oracle_dijkstra_i32.restype = ctypes.c_int
+            _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _inputs(prob):
+    if prob.succ_ptr is None:
+        ptr, idx = box_to_csr(prob.dims, prob.box_packed())
+    else:
+        ptr = np.ascontiguousarray(prob.succ_ptr, dtype=np.int64)
+        idx = np.ascontiguousarray(prob.succ_idx, dtype=np.int32)
+    av = np.ascontiguousarray(prob.avoid, dtype=np.uint8)
+    return ptr, idx, av
+
+
+def _precision(prob, precision):
+    if prob.dtype == "i32":
+        return "i32"
+    return precision or "f64"
+
+
+def solve(prob, precision: str | None = None, max_rounds: int = 0) -> dict:
+    """Run Algorithm 1.  precision: 'i32' (int costs), 'f64' (default for
+    float costs: the definition in double precision) or 'f32' (one single
+    precision addition per backup).  Returns V, the Algorithm-1 mu, the
+    canonical policy, the residual count, the status and the counters."""
+    L = lib()
+    prec = _precision(prob, precision)
+    ptr, idx, av = _inputs(prob)
+    n, K = prob.n, prob.K
+    if prec == "i32":
+        g = np.ascontiguousarray(prob.g, dtype=np.int32)
+        G = np.ascontiguousarray(prob.G, dtype=np.int32)
+        W = np.empty(n, dtype=np.int32)
+        fs, fp = L.oracle_solve_i32, L.oracle_policy_i32
+    else:
+        g = np.ascontiguousarray(prob.g, dtype=np.float32)
+        G = np.ascontiguousarray(prob.G, dtype=np.float32)
+        W = np.empty(n, dtype=np.float64 if prec == "f64" else np.float32)
+        fs, fp = (L.oracle_solve_f64, L.oracle_policy_f64) if prec == "f64" else \
+                 (L.oracle_solve_f32, L.oracle_policy_f32)
+    mu = np.empty(n, dtype=np.int32)
+    c = Counters()
+    front = np.empty(n, dtype=np.int32)
+    flen = np.zeros(1, dtype=np.int64)
+    st = fs(n, K, _p(ptr), _p(idx), _p(g), _p(G), _p(av), int(max_rounds), _p(W), _p(mu), ctypes.byref(c),
+            _p(front), _p(flen))
+    if st < 0:
+        raise ValueError(f"oracle rejected the problem (status {st})")
+    pol = np.empty(n, dtype=np.int32)
+    bad = fp(n, K, _p(ptr), _p(idx), _p(g), _p(G), _p(av), _p(W), _p(pol))
+    return {"V": W, "mu": mu, "policy": pol, "residual": int(bad), "status": int(st),
+            "counters": c.as_dict(), "precision": prec, "frontier": front[:int(flen[0])].copy()}
+
+
+def residual(prob, V, precision: str | None = None):
+    """One application of P to V: returns (number of non-avoid states with
+    P(V)(x) != V(x) or avoid states with finite V, canonical policy)."""
+    L = lib()
+    prec = _precision(prob, precision)
+    ptr, idx, av = _inputs(prob)
+    if prec == "i32":
+        g = np.ascontiguousarray(prob.g, dtype=np.int32)
+        G = np.ascontiguousarray(prob.G, dtype=np.int32)
+        W = np.ascontiguousarray(V, dtype=np.int32)
+        f = L.oracle_policy_i32
+    else:
+        g = np.ascontiguousarray(prob.g, dtype=np.float32)
+        G = np.ascontiguousarray(prob.G, dtype=np.float32)
+        W = np.ascontiguousarray(V, dtype=np.float64 if prec == "f64" else np.float32)
+        f = L.oracle_policy_f64 if prec == "f64" else L.oracle_policy_f32
+    pol = np.empty(prob.n, dtype=np.int32)
+    bad = f(prob.n, prob.K, _p(ptr), _p(idx), _p(g), _p(G), _p(av), _p(W), _p(pol))
+    return int(bad), pol
+
+
+def box_to_csr(dims, box: np.ndarray):
+    """The oracle's own decoder of packed 8-byte boxes into CSR rows."""
+    L = lib()
+    d = np.ascontiguousarray(np.array(list(dims) + [1] * (4 - len(dims)), dtype=np.int32))
+    b = np.ascontiguousarray(box, dtype=np.uint64)
+    npairs = b.shape[0]
+    m = L.oracle_box_to_csr(_p(d), npairs, _p(b), None, None)
+    if m < 0:
+        raise ValueError("box outside the grid")
+    ptr = np.empty(npairs + 1, dtype=np.int64)
+    idx = np.empty(m, dtype=np.int32)
+    L.oracle_box_to_csr(_p(d), npairs, _p(b), _p(ptr), _p(idx))
+    return ptr, idx
+
+
+def dijkstra(prob) -> np.ndarray:
+    """Independent min-max Dijkstra (int32, non-negative running costs)."""
+    L = lib()
+    ptr, idx, av = _inputs(prob)
+    g = np.ascontiguousarray(prob.g, dtype=np.int32)
+    G = np.ascontiguousarray(prob.G, dtype=np.int32)
+    W = np.empty(prob.n, dtype=np.int32)
+    st = L.oracle_dijkstra_i32(prob.n, prob.K, _p(ptr), _p(idx), _p(g), _p(G), _p(av), _p(W))
+    if st != 0:
+        raise ValueError(f"dijkstra rejected the problem (status {st})")
+    return W
