@@ -1,0 +1,191 @@
+/*
+ * gbf — generalized Bellman-Ford solver for symbolic optimal control on
+ * AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * The library solves optimal control problems (X, U, F, G, g) as defined in
+ * Weber, Kreuzer, Knoll, "A generalized Bellman-Ford Algorithm for
+ * Application in Symbolic Optimal Control", Sect. III-C (Definition of an
+ * optimal control problem): a finite state set X = {0..n-1}, a finite input
+ * set U = {0..K-1}, a strict transition map F: X x U => X (every F(x,u) is
+ * non-empty, Sect. II / III-A), a terminal cost G: X -> R u {inf} and a
+ * running cost g.  Running costs are per pair, g(x,u), i.e. the cost does
+ * not depend on the successor y (the paper allows g(x,y,u); with per-pair
+ * costs the sup over y of g + W(y) is g(x,u) + max_y W(y)).
+ *
+ * It returns the value function V, the maximal fixed point of the dynamic
+ * programming operator
+ *     P(W)(x) = min{ G(x), min_u max_{y in F(x,u)} g(x,u) + W(y) }
+ * (Theorem on dynamic programming, Sect. III-C), computed by the frontier
+ * iteration of Algorithm 1 (Sect. IV-A), and a controller that realizes it.
+ *
+ * Conventions
+ *   - INF is INT32_MAX for int32 costs and +infinity for float costs.
+ *   - Pair (x,u) has id p = x*K + u.  State x of a grid with dims
+ *     (N0,N1,N2,N3) is x = x0 + N0*(x1 + N1*(x2 + N2*x3)).
+ *   - Avoid cells (optional byte mask) are states the controller must never
+ *     enter: their value is pinned to INF and no pair leading into them is
+ *     ever chosen.  A finite G on an avoid cell is rejected.
+ *   - Every call returns a status code (GBF_OK = 0, errors < 0); no call
+ *     throws or aborts.  gbf_last_error() returns a message for the last
+ *     failing call of the calling thread.
+ *   - All device work is ordered on the HIP stream given at load time.
+ *     Calls return after their work has completed.
+ *   - "Memory space" arguments say whether a pointer is host (GBF_HOST) or
+ *     device (GBF_DEVICE) memory of the current device.
+ */
+#ifndef GBF_H
+#define GBF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define GBF_OK 0
+/* The round cap was reached with a non-empty frontier (the second condition
+ * of the while loop of Algorithm 1).  V_out then holds the capped iterate,
+ * which is >= V but not certified to equal it.  On ordinary graphs this
+ * means a negative cycle; on hypergraphs it can also mean that more rounds
+ * are needed, see gbf_opts.max_rounds. */
+#define GBF_ENEGCYCLE 1
+#define GBF_EINVAL (-1)      /* invalid argument or problem */
+#define GBF_ENOMEM (-2)      /* device or host allocation failed */
+#define GBF_EHIP (-3)        /* a HIP runtime call failed */
+#define GBF_ENOTSOLVED (-4)  /* gbf_extract_policy before a successful solve */
+#define GBF_ETIMEOUT (-5)    /* a device-side bounded wait expired */
+
+/* ---- enums ------------------------------------------------------------ */
+#define GBF_I32 0 /* int32 costs and values */
+#define GBF_F32 1 /* float costs and values */
+
+#define GBF_CSR 0 /* explicit successor lists */
+#define GBF_BOX 1 /* implicit boxes: 8 bytes per pair, successors on the fly */
+
+#define GBF_HOST 0
+#define GBF_DEVICE 1
+
+#define GBF_ORDER_PLAIN 0   /* frontier rounds as in Algorithm 1 */
+#define GBF_ORDER_BUCKETS 1 /* frontier drained in ascending bucket key */
+
+#define GBF_MODE_AUTO 0
+#define GBF_MODE_HOSTLOOP 1   /* one launch sequence per round from the host */
+#define GBF_MODE_PERSISTENT 2 /* all rounds in one cooperative launch */
+
+/* policy sentinels (Algorithm 1 leaves mu(x) = U for such states) */
+#define GBF_HANDOVER (-1) /* V(x) = G(x): hand over now */
+#define GBF_NONE (-2)     /* V(x) = INF: no controller exists */
+
+/* ---- problem ------------------------------------------------------------
+ * The optimal control problem (X, U, F, G, g) of Sect. III-C.
+ * Arrays are read during gbf_load_graph only; the library keeps its own
+ * device copies, so the caller may free them on return.                   */
+typedef struct gbf_problem {
+    int64_t n_states;   /* |X| >= 1 */
+    int32_t n_inputs;   /* |U| = K >= 1 */
+    int32_t dtype;      /* GBF_I32 or GBF_F32: type of G, g and V */
+    int32_t encoding;   /* GBF_CSR or GBF_BOX */
+    int32_t memspace;   /* GBF_HOST or GBF_DEVICE: where the arrays live */
+    const void* G;      /* [n] terminal cost; INF = not a target */
+    const void* g;      /* [n*K] running cost of pair (x,u); INF = forbidden */
+    const uint8_t* avoid; /* [n] 1 = avoid cell, or NULL */
+    /* GBF_CSR: F(x,u) = { succ_idx[e] : succ_ptr[p] <= e < succ_ptr[p+1] }.
+     * Rows must be non-empty (strictness); total m < 2^31. */
+    const int64_t* succ_ptr; /* [n*K+1] */
+    const int32_t* succ_idx; /* [m], values in [0,n) */
+    /* GBF_BOX: the states form a grid with dims[0..3] (unused axes = 1,
+     * prod = n); F(x,u) is the box whose low corner is the cell
+     * (uint32)box[p] and whose extent on axis a is byte a of box[p] >> 32,
+     * i.e. the cells c with lo_a <= c_a <= lo_a + ext_a.  Boxes must lie in
+     * the grid.  This is the rectangular over-approximation of attainable
+     * sets used in Sect. V-B; successors are decoded on the fly and
+     * predecessors are searched in a window per input, which the loader
+     * derives from the boxes (a superset of pred, allowed by Sect. V-B). */
+    int32_t dims[4];
+    const uint64_t* box; /* [n*K] */
+} gbf_problem;
+
+/* ---- solve options --------------------------------------------------- */
+typedef struct gbf_opts {
+    int32_t order;          /* GBF_ORDER_PLAIN or GBF_ORDER_BUCKETS */
+    int32_t mode;           /* GBF_MODE_* */
+    const uint16_t* bucket_key; /* BUCKETS: [n] device array, key of state x;
+                                   only the processing order depends on it */
+    int64_t max_rounds;     /* round cap; 0 = n (the paper's i < |X|) */
+    int32_t block;          /* threads per block (multiple of 64); 0 = default */
+    int32_t grid;           /* blocks; 0 = default */
+    int32_t v_memspace;     /* where V_out lives: GBF_HOST or GBF_DEVICE */
+    int32_t profile;        /* 1 = time every relax launch with HIP events */
+    int32_t reserved[4];
+} gbf_opts;
+
+/* ---- statistics ------------------------------------------------------- */
+typedef struct gbf_stats {
+    int32_t status;         /* status of this solve */
+    int32_t fallback;       /* 1 = bucket order fell back to plain order */
+    int64_t rounds;         /* rounds executed (passes of the while loop) */
+    int64_t pair_evals;     /* pairs (x,u) whose successors were read */
+    int64_t edge_relax;     /* sum of |F(x,u)| over those pairs */
+    int64_t improvements;   /* successful strict decreases of V */
+    int64_t saturations;    /* int32 sums clamped at -INT32_MAX */
+    double solve_ms;        /* HIP-event time of the solve on its stream */
+    double relax_ms;        /* profile=1: summed time of the relax launches */
+    int64_t relax_launches; /* profile=1: number of relax launches timed */
+    int64_t device_bytes;   /* device memory held by the graph handle */
+    int32_t mode_used;      /* GBF_MODE_HOSTLOOP or GBF_MODE_PERSISTENT */
+    int32_t grid_used;
+    int32_t block_used;
+    int32_t reserved[3];
+} gbf_stats;
+
+typedef struct gbf_graph gbf_graph;
+
+/* Validates a problem, copies it to device memory owned by the handle and
+ * builds what the solver needs: the reverse adjacency pred (Sect. IV-A,
+ * pred(x,u) = { y : x in F(y,u) }) as a pair-level reverse CSR for
+ * GBF_CSR, or per-input predecessor windows for GBF_BOX; pairs that can
+ * never improve a value (g = INF, avoid source, or a successor in the avoid
+ * set) are pruned.  `hip_stream` is a hipStream_t (NULL = default stream)
+ * on which all later work of this handle is ordered.
+ * Errors: GBF_EINVAL (n or K <= 0, empty F(x,u), index or box outside the
+ * grid, NaN or -inf cost, finite G on an avoid cell, m >= 2^31),
+ * GBF_ENOMEM, GBF_EHIP.  On error *out is NULL. */
+int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph** out);
+
+/* Runs Algorithm 1 (Sect. IV-A) until the frontier is empty or the round
+ * cap is reached and writes V to V_out ([n] of the problem's dtype, in
+ * opts->v_memspace).  Also keeps V inside the handle for
+ * gbf_extract_policy.  `opts` may be NULL (defaults); `st` may be NULL.
+ * Returns GBF_OK, GBF_ENEGCYCLE (V_out holds the capped iterate),
+ * GBF_EINVAL (BUCKETS without a key), GBF_ETIMEOUT, GBF_EHIP. */
+int gbf_solve(gbf_graph* g, const gbf_opts* opts, void* V_out, gbf_stats* st);
+
+/* Canonical controller from the last solve (Algorithm 1's mu, made
+ * independent of processing order): policy[x] = the smallest input u with
+ * g(x,u) + max_{y in F(x,u)} V(y) = V(x) < G(x); GBF_HANDOVER if
+ * V(x) = G(x) < INF; GBF_NONE if V(x) = INF.  policy_out is [n] int32 in
+ * `memspace`.  If `residual` is non-NULL it receives the number of states
+ * where P(V)(x) != V(x) (0 certifies a fixed point).
+ * Errors: GBF_ENOTSOLVED, GBF_EHIP. */
+int gbf_extract_policy(gbf_graph* g, int32_t* policy_out, int32_t memspace, int64_t* residual);
+
+/* Solves `count` independent problems in one persistent launch (or one
+ * launch sequence per round), with one frontier spanning all of them.
+ * Results are identical to gbf_solve on each handle.  All handles must be
+ * on the same device and stream.  V_outs[i] receives instance i's values
+ * (in opts->v_memspace); st (may be NULL) is an array of `count` stats.
+ * Returns the worst status over the instances. */
+int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gbf_opts* opts,
+                    void* const* V_outs, gbf_stats* st);
+
+/* Releases a handle (NULL is allowed). */
+void gbf_free_graph(gbf_graph* g);
+
+/* Message for the last failing call of this thread ("" if none). */
+const char* gbf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GBF_H */

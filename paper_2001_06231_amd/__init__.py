@@ -1,0 +1,273 @@
+"""gbf — generalized Bellman-Ford for symbolic optimal control on MI355X.
+
+Thin ctypes binding of the C ABI in include/gbf.h (libgbf.so, built in-tree
+by ``paper_2001_06231_amd.build``).  It only marshals arguments: every step
+of the solve runs in the library's HIP kernels.  There is no CPU fallback;
+if the library is missing, importing a function raises.
+
+Names follow the paper (Weber, Kreuzer, Knoll, Sect. III-C and IV-A):
+a problem is (X, U, F, G, g), the solver returns the value function V and a
+controller (policy) that realizes it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgbf.so")
+
+# status codes and constants of include/gbf.h
+OK, ENEGCYCLE, EINVAL, ENOMEM, EHIP, ENOTSOLVED, ETIMEOUT = 0, 1, -1, -2, -3, -4, -5
+I32, F32 = 0, 1
+CSR, BOX = 0, 1
+HOST, DEVICE = 0, 1
+ORDER_PLAIN, ORDER_BUCKETS = 0, 1
+MODE_AUTO, MODE_HOSTLOOP, MODE_PERSISTENT = 0, 1, 2
+HANDOVER, NONE = -1, -2
+INF_I32 = 2**31 - 1
+
+_MODES = {"auto": MODE_AUTO, "hostloop": MODE_HOSTLOOP, "persistent": MODE_PERSISTENT}
+_ORDERS = {"plain": ORDER_PLAIN, "buckets": ORDER_BUCKETS}
+
+
+class GbfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gbf error {code}: {msg}")
+        self.code = code
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_int64), ("n_inputs", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("encoding", ctypes.c_int32), ("memspace", ctypes.c_int32), ("G", ctypes.c_void_p),
+                ("g", ctypes.c_void_p), ("avoid", ctypes.c_void_p), ("succ_ptr", ctypes.c_void_p),
+                ("succ_idx", ctypes.c_void_p), ("dims", ctypes.c_int32 * 4), ("box", ctypes.c_void_p)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("mode", ctypes.c_int32), ("bucket_key", ctypes.c_void_p),
+                ("max_rounds", ctypes.c_int64), ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("v_memspace", ctypes.c_int32), ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("fallback", ctypes.c_int32), ("rounds", ctypes.c_int64),
+                ("pair_evals", ctypes.c_int64), ("edge_relax", ctypes.c_int64),
+                ("improvements", ctypes.c_int64), ("saturations", ctypes.c_int64),
+                ("solve_ms", ctypes.c_double), ("relax_ms", ctypes.c_double),
+                ("relax_launches", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("mode_used", ctypes.c_int32), ("grid_used", ctypes.c_int32), ("block_used", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+    def as_dict(self):
+        return {k: (getattr(self, k) if k != "reserved" else None) for k, _ in self._fields_ if k != "reserved"}
+
+
+EXPORTS = ("gbf_load_graph", "gbf_solve", "gbf_extract_policy", "gbf_solve_batch", "gbf_free_graph",
+           "gbf_last_error")
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib():
+    """Loads libgbf.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing: build it with "
+                                  "`python -c 'import __graft_entry__ as e; e.build()'`")
+            L = ctypes.CDLL(LIB_PATH)
+            P = ctypes.c_void_p
+            L.gbf_load_graph.argtypes = [ctypes.POINTER(_Problem), P, ctypes.POINTER(P)]
+            L.gbf_load_graph.restype = ctypes.c_int
+            L.gbf_solve.argtypes = [P, ctypes.POINTER(_Opts), P, ctypes.POINTER(_Stats)]
+            L.gbf_solve.restype = ctypes.c_int
+            L.gbf_extract_policy.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+            L.gbf_extract_policy.restype = ctypes.c_int
+            L.gbf_solve_batch.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(_Opts),
+                                          ctypes.POINTER(P), P]
+            L.gbf_solve_batch.restype = ctypes.c_int
+            L.gbf_free_graph.argtypes = [P]
+            L.gbf_free_graph.restype = None
+            L.gbf_last_error.argtypes = []
+            L.gbf_last_error.restype = ctypes.c_char_p
+            _lib = L
+    return _lib
+
+
+def _err(L, code):
+    return GbfError(code, L.gbf_last_error().decode())
+
+
+def _ptr(a):
+    """Address and memory space of a numpy array or a torch tensor."""
+    if a is None:
+        return None, None
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("arrays must be C-contiguous")
+        return a.ctypes.data, HOST
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        return a.data_ptr(), (DEVICE if a.is_cuda else HOST)
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def current_stream():
+    """The current torch HIP stream as a raw handle (None = default)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+class Graph:
+    """A loaded problem (device-resident); see gbf_load_graph."""
+
+    def __init__(self, handle, n, K, dtype, keep):
+        self._h = handle
+        self.n, self.K, self.dtype = n, K, dtype
+        self._keep = keep
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().gbf_free_graph(self._h)
+            self._h = None
+
+    def _opts(self, order, mode, max_rounds, grid, profile, bucket_key, v_space):
+        o = _Opts()
+        o.order = _ORDERS[order]
+        o.mode = _MODES[mode]
+        o.max_rounds = int(max_rounds)
+        o.grid = int(grid)
+        o.profile = 1 if profile else 0
+        o.v_memspace = v_space
+        if bucket_key is not None:
+            o.bucket_key, sp = _ptr(bucket_key)
+            if sp != DEVICE:
+                raise ValueError("bucket_key must be a device tensor")
+        return o
+
+    def solve(self, V_out=None, *, order="plain", mode="auto", max_rounds=0, grid=0, profile=False,
+              bucket_key=None, check=True):
+        """Runs the solver; returns (status, stats dict, V_out).  V_out may be
+        a numpy array (host) or a torch tensor on the GPU; if None a numpy
+        array is allocated."""
+        L = lib()
+        if V_out is None:
+            V_out = np.empty(self.n, dtype=np.int32 if self.dtype == I32 else np.float32)
+        vp, vs = _ptr(V_out)
+        o = self._opts(order, mode, max_rounds, grid, profile, bucket_key, vs)
+        st = _Stats()
+        rc = L.gbf_solve(self._h, ctypes.byref(o), vp, ctypes.byref(st))
+        if rc < 0 or (check and rc not in (OK, ENEGCYCLE)):
+            raise _err(L, rc)
+        return rc, st.as_dict(), V_out
+
+    def policy(self, out=None):
+        """Canonical controller of the last solve and the fixed-point
+        residual count: (policy, residual)."""
+        L = lib()
+        if out is None:
+            out = np.empty(self.n, dtype=np.int32)
+        pp, ps = _ptr(out)
+        res = ctypes.c_int64(0)
+        rc = L.gbf_extract_policy(self._h, pp, ps, ctypes.byref(res))
+        if rc != OK:
+            raise _err(L, rc)
+        return out, int(res.value)
+
+
+def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=None, succ_idx=None,
+               dims=None, box=None, stream=None) -> Graph:
+    """gbf_load_graph.  Arrays are numpy (host) or torch tensors on the GPU
+    (all of one kind).  G/g are int32 or float32 bit patterns."""
+    L = lib()
+    p = _Problem()
+    p.n_states = int(n)
+    p.n_inputs = int(K)
+    p.dtype = I32 if dtype == "i32" else F32
+    p.encoding = CSR if encoding == "csr" else BOX
+    keep = []
+    spaces = set()
+
+    def put(field, arr, np_dtype):
+        if arr is None:
+            return
+        if isinstance(arr, np.ndarray):
+            arr = np.ascontiguousarray(arr, dtype=np_dtype)
+        keep.append(arr)
+        ptr, sp = _ptr(arr)
+        spaces.add(sp)
+        setattr(p, field, ptr)
+
+    vt = np.int32 if dtype == "i32" else np.float32
+    put("G", G, vt)
+    put("g", g, vt)
+    put("avoid", avoid, np.uint8)
+    if p.encoding == CSR:
+        put("succ_ptr", succ_ptr, np.int64)
+        put("succ_idx", succ_idx, np.int32)
+    else:
+        put("box", box, np.uint64)
+        d = list(dims) + [1] * (4 - len(dims))
+        for a in range(4):
+            p.dims[a] = int(d[a])
+    if len(spaces) > 1:
+        raise ValueError("problem arrays must all be host arrays or all device tensors")
+    p.memspace = spaces.pop() if spaces else HOST
+    h = ctypes.c_void_p()
+    rc = L.gbf_load_graph(ctypes.byref(p), stream, ctypes.byref(h))
+    if rc != OK:
+        raise _err(L, rc)
+    return Graph(h, int(n), int(K), p.dtype, None)
+
+
+def load_problem(prob, encoding="csr", stream=None) -> Graph:
+    """Loads an object with the fields of an optimal control problem
+    (n, K, dtype, G, g, avoid, succ_ptr/succ_idx or dims/box_packed())."""
+    if encoding == "csr":
+        return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="csr", avoid=prob.avoid,
+                          succ_ptr=prob.succ_ptr, succ_idx=prob.succ_idx, stream=stream)
+    return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="box", avoid=prob.avoid,
+                      dims=prob.dims, box=prob.box_packed(), stream=stream)
+
+
+def solve_batch(graphs: Sequence[Graph], V_outs=None, *, mode="auto", max_rounds=0, grid=0, profile=False,
+                check=True):
+    """gbf_solve_batch: one frontier over all instances.  Returns (worst
+    status, list of per-instance stats, V_outs)."""
+    L = lib()
+    cnt = len(graphs)
+    if V_outs is None:
+        V_outs = [np.empty(gr.n, dtype=np.int32 if gr.dtype == I32 else np.float32) for gr in graphs]
+    ptrs = [_ptr(v) for v in V_outs]
+    spaces = {sp for _, sp in ptrs}
+    if len(spaces) != 1:
+        raise ValueError("V_outs must all be host or all device")
+    o = _Opts()
+    o.mode = _MODES[mode]
+    o.max_rounds = int(max_rounds)
+    o.grid = int(grid)
+    o.profile = 1 if profile else 0
+    o.v_memspace = spaces.pop()
+    hs = (ctypes.c_void_p * cnt)(*[gr._h for gr in graphs])
+    vs = (ctypes.c_void_p * cnt)(*[p for p, _ in ptrs])
+    st = (_Stats * cnt)()
+    rc = L.gbf_solve_batch(hs, cnt, ctypes.byref(o), vs, st)
+    if rc < 0 or (check and rc not in (OK, ENEGCYCLE)):
+        raise _err(L, rc)
+    return rc, [s.as_dict() for s in st], V_outs

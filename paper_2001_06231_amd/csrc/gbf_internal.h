@@ -1,0 +1,75 @@
+// Internal interface between the host driver (gbf_api.hip) and the kernels
+// (gbf_kernels.hip).  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gbf {
+
+// One problem instance as the kernels see it.  Pair ids are global: pair p
+// of this instance has id pair_base + p, state x is instance-local.
+struct Inst {
+    const uint32_t* sptr;   // CSR row pointers [nK+1]
+    const int32_t* sidx;    // CSR successors [m]
+    const uint32_t* rptr;   // reverse CSR row pointers [n+1]
+    const uint32_t* rev;    // reverse CSR: local pair ids whose box/row holds the state
+    const uint64_t* box;    // BOX encoding [nK]
+    const int32_t* G;       // terminal cost bits [n]
+    const int32_t* g;       // running cost bits [nK] (pruned pairs = INF)
+    const uint8_t* avoid;   // [n]
+    void* V;                // value words [n] (int32 or fp32 key)
+    int32_t* stamp;         // last round in which the state was expanded [n]
+    const int32_t* win;     // BOX: per input 8 ints: min (lo-x) per axis, max (hi-x) per axis
+    int64_t n;
+    int64_t pair_base;      // first global pair id
+    int64_t max_rounds;     // round cap of this instance
+    int32_t K;
+    int32_t enc;            // 0 CSR, 1 BOX
+    int32_t dims[4];
+    int32_t strides[4];
+    int32_t index;          // position in the batch
+    int32_t dtype;          // 0 int32, 1 fp32
+};
+
+// Device-side solver state shared by all instances of one solve.
+struct Run {
+    uint32_t* bits[2];          // dirty-pair bitmaps (frontiers F1/F2)
+    uint32_t* list;             // compacted frontier (global pair ids)
+    uint32_t* counts;           // frontier size per round [max_rounds + 2]
+    unsigned long long* ctr;    // [8]: pair evals, edges, improvements, saturations
+    int32_t* inst_status;       // per instance: 1 = cap reached with work left
+    uint32_t* barrier;          // persistent mode: [0] arrive counter, [1] generation
+    int32_t* error;             // persistent mode: barrier timeout flag
+    int32_t* result;            // persistent mode: [0] rounds executed
+    int64_t nwords;             // words per bitmap
+    int64_t total_pairs;
+    int64_t max_rounds;         // global cap (max over instances)
+    int32_t ninst;
+    int32_t dtype;              // 0 int32, 1 fp32
+};
+
+constexpr int kMaxBatch = 1024;
+
+// Launch wrappers (all asynchronous on `s`).
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_validate(const Inst& I, const int64_t* sptr64, int64_t m, int dtype, int32_t* err,
+                           hipStream_t s);
+hipError_t launch_convert_ptr(const int64_t* in, uint32_t* out, int64_t n, hipStream_t s);
+hipError_t launch_prune(const Inst& I, int dtype, hipStream_t s);
+hipError_t launch_rev_count(const Inst& I, uint32_t* cnt, hipStream_t s);
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t s);
+hipError_t launch_rev_fill(const Inst& I, uint32_t* cursor, uint32_t* rev, hipStream_t s);
+hipError_t launch_box_window(const Inst& I, int32_t* win32, hipStream_t s);
+
+hipError_t launch_init(const Inst* dI, const Inst& I, int dtype, hipStream_t s);
+hipError_t launch_seed(const Inst* dI, int ninst, const Run& R, int64_t max_states, int dtype, hipStream_t s);
+hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s);
+hipError_t launch_relax(const Inst* dI, const Run& R, int round, int grid, int block, int dtype, int enc_mask,
+                        hipStream_t s);
+hipError_t launch_persistent(const Inst* dI, const Run& R, int grid, int block, int dtype, int enc_mask,
+                             hipStream_t s);
+int persistent_blocks_per_cu(int block, int dtype, int enc_mask);
+hipError_t launch_decode(const Inst& I, int dtype, void* out, hipStream_t s);
+hipError_t launch_policy(const Inst& I, int dtype, int32_t* pol, unsigned long long* bad, hipStream_t s);
+
+}  // namespace gbf
