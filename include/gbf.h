@@ -113,7 +113,8 @@ typedef struct gbf_opts {
     const uint16_t* bucket_key; /* BUCKETS: [n] device array, key of state x;
                                    only the processing order depends on it */
     int64_t max_rounds;     /* round cap; 0 = n (the paper's i < |X|) */
-    int32_t block;          /* threads per block (multiple of 64); 0 = default */
+    int32_t lanes;          /* lanes per frontier pair in the relax step:
+                               4, 8, 16 or 32; 0 = default (8) */
     int32_t grid;           /* blocks; 0 = default */
     int32_t v_memspace;     /* where V_out lives: GBF_HOST or GBF_DEVICE */
     int32_t profile;        /* 1 = time every relax launch with HIP events */
@@ -129,6 +130,8 @@ typedef struct gbf_stats {
     int64_t edge_relax;     /* sum of |F(x,u)| over those pairs */
     int64_t improvements;   /* successful strict decreases of V */
     int64_t saturations;    /* int32 sums clamped at -INT32_MAX */
+    int64_t expansions;     /* states whose predecessors were marked */
+    int64_t marks;          /* predecessor pairs (or box candidates) visited */
     double solve_ms;        /* HIP-event time of the solve on its stream */
     double relax_ms;        /* profile=1: summed time of the relax launches */
     int64_t relax_launches; /* profile=1: number of relax launches timed */
@@ -136,7 +139,8 @@ typedef struct gbf_stats {
     int32_t mode_used;      /* GBF_MODE_HOSTLOOP or GBF_MODE_PERSISTENT */
     int32_t grid_used;
     int32_t block_used;
-    int32_t reserved[3];
+    int32_t lanes_used;
+    int32_t reserved[2];
 } gbf_stats;
 
 typedef struct gbf_graph gbf_graph;

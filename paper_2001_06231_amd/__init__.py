@@ -50,7 +50,7 @@ class _Problem(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("mode", ctypes.c_int32), ("bucket_key", ctypes.c_void_p),
-                ("max_rounds", ctypes.c_int64), ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("max_rounds", ctypes.c_int64), ("lanes", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("v_memspace", ctypes.c_int32), ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
@@ -58,10 +58,11 @@ class _Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("fallback", ctypes.c_int32), ("rounds", ctypes.c_int64),
                 ("pair_evals", ctypes.c_int64), ("edge_relax", ctypes.c_int64),
                 ("improvements", ctypes.c_int64), ("saturations", ctypes.c_int64),
+                ("expansions", ctypes.c_int64), ("marks", ctypes.c_int64),
                 ("solve_ms", ctypes.c_double), ("relax_ms", ctypes.c_double),
                 ("relax_launches", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("mode_used", ctypes.c_int32), ("grid_used", ctypes.c_int32), ("block_used", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("lanes_used", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
     def as_dict(self):
         return {k: (getattr(self, k) if k != "reserved" else None) for k, _ in self._fields_ if k != "reserved"}
@@ -144,11 +145,14 @@ class Graph:
 
     def free(self):
         if getattr(self, "_h", None):
-            lib().gbf_free_graph(self._h)
+            L = _lib
+            if L is not None:
+                L.gbf_free_graph(self._h)
             self._h = None
 
-    def _opts(self, order, mode, max_rounds, grid, profile, bucket_key, v_space):
+    def _opts(self, order, mode, max_rounds, grid, profile, bucket_key, v_space, lanes=0):
         o = _Opts()
+        o.lanes = int(lanes)
         o.order = _ORDERS[order]
         o.mode = _MODES[mode]
         o.max_rounds = int(max_rounds)
@@ -162,7 +166,7 @@ class Graph:
         return o
 
     def solve(self, V_out=None, *, order="plain", mode="auto", max_rounds=0, grid=0, profile=False,
-              bucket_key=None, check=True):
+              bucket_key=None, lanes=0, check=True):
         """Runs the solver; returns (status, stats dict, V_out).  V_out may be
         a numpy array (host) or a torch tensor on the GPU; if None a numpy
         array is allocated."""
@@ -170,7 +174,7 @@ class Graph:
         if V_out is None:
             V_out = np.empty(self.n, dtype=np.int32 if self.dtype == I32 else np.float32)
         vp, vs = _ptr(V_out)
-        o = self._opts(order, mode, max_rounds, grid, profile, bucket_key, vs)
+        o = self._opts(order, mode, max_rounds, grid, profile, bucket_key, vs, lanes)
         st = _Stats()
         rc = L.gbf_solve(self._h, ctypes.byref(o), vp, ctypes.byref(st))
         if rc < 0 or (check and rc not in (OK, ENEGCYCLE)):
@@ -247,7 +251,7 @@ def load_problem(prob, encoding="csr", stream=None) -> Graph:
 
 
 def solve_batch(graphs: Sequence[Graph], V_outs=None, *, mode="auto", max_rounds=0, grid=0, profile=False,
-                check=True):
+                lanes=0, check=True):
     """gbf_solve_batch: one frontier over all instances.  Returns (worst
     status, list of per-instance stats, V_outs)."""
     L = lib()
@@ -262,6 +266,7 @@ def solve_batch(graphs: Sequence[Graph], V_outs=None, *, mode="auto", max_rounds
     o.mode = _MODES[mode]
     o.max_rounds = int(max_rounds)
     o.grid = int(grid)
+    o.lanes = int(lanes)
     o.profile = 1 if profile else 0
     o.v_memspace = spaces.pop()
     hs = (ctypes.c_void_p * cnt)(*[gr._h for gr in graphs])

@@ -17,6 +17,10 @@ using namespace gbf;
 
 static thread_local std::string t_err;
 
+// Blocks per CU of the persistent kernel: below the occupancy limit, so that
+// the cooperative grid is co-resident with margin.
+constexpr int kPersistentBlocksPerCU = 4;
+
 static int fail(int code, const std::string& msg) {
     t_err = msg;
     return code;
@@ -66,6 +70,7 @@ struct Scratch {
     uint32_t* list = nullptr;
     uint32_t* counts = nullptr;
     unsigned long long* ctr = nullptr;
+    unsigned long long* slots = nullptr;
     int32_t* inst_status = nullptr;
     uint32_t* barrier = nullptr;
     int32_t* error = nullptr;
@@ -92,6 +97,7 @@ struct gbf_graph {
     hipStream_t stream = nullptr;
     int device = 0;
     int cus = 0;
+    int clock_khz = 100000;
     DevMem mem;
     Inst inst{};
     bool solved = false;
@@ -117,6 +123,7 @@ static int ensure_scratch(Scratch& S, int64_t total_pairs, int64_t max_rounds, i
     if (!S.ctr) {
         int rc;
         if ((rc = S.mem.alloc((void**)&S.ctr, 8 * sizeof(unsigned long long)))) return rc;
+        if ((rc = S.mem.alloc((void**)&S.slots, (size_t)kMaxGrid * 8 * sizeof(unsigned long long)))) return rc;
         if ((rc = S.mem.alloc((void**)&S.barrier, 64))) return rc;
         if ((rc = S.mem.alloc((void**)&S.error, 64))) return rc;
         if ((rc = S.mem.alloc((void**)&S.result, 64))) return rc;
@@ -128,7 +135,7 @@ static int ensure_scratch(Scratch& S, int64_t total_pairs, int64_t max_rounds, i
         if ((rc = S.mem.alloc((void**)&S.inst_status, 4 * ninst))) return rc;
         S.ninst_cap = ninst;
     }
-    const size_t hb = 4096 + 8 * (size_t)ninst + 4 * 128;
+    const size_t hb = 4096 + 4 * (size_t)ninst + 1024;
     if (S.host_bytes < hb) {
         if (S.host) (void)hipHostFree(S.host);
         S.host = nullptr;
@@ -166,6 +173,9 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
     gr->stream = (hipStream_t)hip_stream;
     HIPC(hipGetDevice(&gr->device));
     HIPC(hipDeviceGetAttribute(&gr->cus, hipDeviceAttributeMultiprocessorCount, gr->device));
+    if (hipDeviceGetAttribute(&gr->clock_khz, hipDeviceAttributeWallClockRate, gr->device) != hipSuccess ||
+        gr->clock_khz <= 0)
+        gr->clock_khz = 100000;
     hipStream_t s = gr->stream;
     DevMem& M = gr->mem;
     Inst& I = gr->inst;
@@ -270,6 +280,7 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
         if ((rc = M.alloc((void**)&rev, (size_t)total * 4))) return rc;
         HIPC(hipMemcpyAsync(cnt, rptr, n * 4, hipMemcpyDeviceToDevice, s));
         HIPC(launch_rev_fill(I, cnt, rev, s));
+        HIPC(launch_sort_rows(rptr, rev, n, s));
         I.rptr = rptr;
         I.rev = rev;
         HIPC(hipStreamSynchronize(s));
@@ -307,10 +318,10 @@ extern "C" const char* gbf_last_error(void) { return t_err.c_str(); }
 // ------------------------------------------------------------------ solve core
 struct SolveOut {
     int64_t rounds = 0;
-    unsigned long long ctr[4] = {0, 0, 0, 0};
+    unsigned long long ctr[6] = {0, 0, 0, 0, 0, 0};
     double solve_ms = 0, relax_ms = 0;
     int64_t relax_launches = 0;
-    int mode = 0, grid = 0, block = 0;
+    int mode = 0, grid = 0, block = 0, lanes = 0;
     std::vector<int32_t> inst_status;
 };
 
@@ -319,7 +330,7 @@ struct SolveOut {
 // the per-round frontier sizes in growing batches.  Persistent mode: one
 // cooperative launch runs every round with grid barriers.
 static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, const gbf_opts& o, hipStream_t s,
-                      int cus, SolveOut& out) {
+                      int cus, int clock_khz, SolveOut& out) {
     const int ninst = (int)insts.size();
     int64_t total_pairs = 0, max_rounds = 0, max_states = 0;
     int enc_mask = 0;
@@ -338,6 +349,7 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
     R.list = S.list;
     R.counts = S.counts;
     R.ctr = S.ctr;
+    R.slots = S.slots;
     R.inst_status = S.inst_status;
     R.barrier = S.barrier;
     R.error = S.error;
@@ -347,6 +359,9 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
     R.max_rounds = max_rounds;
     R.ninst = ninst;
     R.dtype = dtype;
+    // a single barrier wait longer than 250 ms means the blocks are not
+    // co-resident (or the device is stuck): give up instead of hanging
+    R.timeout_ticks = (uint64_t)clock_khz * 250;
 
     HIPC(hipEventRecord(S.events[0], s));
     HIPC(hipMemcpyAsync(S.dinst, insts.data(), sizeof(Inst) * ninst, hipMemcpyHostToDevice, s));
@@ -354,17 +369,20 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
     HIPC(launch_fill_u32(R.bits[1], 0, R.nwords, s));
     HIPC(launch_fill_u32(R.counts, 0, max_rounds + 2, s));
     HIPC(launch_fill_u32((uint32_t*)R.ctr, 0, 16, s));
+    HIPC(launch_fill_u32((uint32_t*)R.slots, 0, (int64_t)kMaxGrid * 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.inst_status, 0, ninst, s));
     HIPC(launch_fill_u32(R.barrier, 0, 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.error, 0, 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.result, 0, 16, s));
     for (const Inst& I : insts) HIPC(launch_init(S.dinst, I, dtype, s));
-    HIPC(launch_seed(S.dinst, ninst, R, max_states, dtype, s));
+    HIPC(launch_seed(S.dinst, ninst, R, max_states, dtype, enc_mask, s));
 
     int mode = o.mode;
     int per_cu = 0;
+    const int lanes = o.lanes == 4 || o.lanes == 16 || o.lanes == 32 ? o.lanes : 8;
+    out.lanes = lanes;
     if (mode != GBF_MODE_HOSTLOOP) {
-        per_cu = persistent_blocks_per_cu(256, dtype, enc_mask);
+        per_cu = persistent_blocks_per_cu(R, lanes, dtype, enc_mask);
         if (per_cu <= 0) {
             if (mode == GBF_MODE_PERSISTENT) return fail(GBF_EHIP, "occupancy query failed");
             mode = GBF_MODE_HOSTLOOP;
@@ -374,16 +392,27 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
     }
     int32_t* host = (int32_t*)S.host;
     if (mode == GBF_MODE_PERSISTENT) {
-        int grid = o.grid > 0 ? std::min(o.grid, per_cu * cus) : per_cu * cus;
+        // co-residency is required; stay below the occupancy limit
+        const int cap = std::min(per_cu, kPersistentBlocksPerCU) * cus;
+        int grid = o.grid > 0 ? std::min(o.grid, cap) : cap;
         out.grid = grid;
         out.block = 256;
         if (o.profile) HIPC(hipEventRecord(S.events[2], s));
-        HIPC(launch_persistent(S.dinst, R, grid, 256, dtype, enc_mask, s));
+        HIPC(launch_persistent(S.dinst, R, grid, lanes, dtype, enc_mask, s));
         if (o.profile) HIPC(hipEventRecord(S.events[3], s));
         HIPC(hipMemcpyAsync(host, S.result, 4, hipMemcpyDeviceToHost, s));
         HIPC(hipMemcpyAsync(host + 1, S.error, 4, hipMemcpyDeviceToHost, s));
         HIPC(hipStreamSynchronize(s));
-        if (host[1] != 0) return fail(GBF_ETIMEOUT, "grid barrier timed out (blocks not co-resident?)");
+        if (host[1] != 0) {
+            if (o.mode == GBF_MODE_AUTO) {
+                // retry the whole solve with one launch sequence per round
+                gbf_opts o2 = o;
+                o2.mode = GBF_MODE_HOSTLOOP;
+                out = SolveOut();
+                return run_rounds(S, insts, dtype, o2, s, cus, clock_khz, out);
+            }
+            return fail(GBF_ETIMEOUT, "grid barrier timed out (blocks not co-resident?)");
+        }
         out.rounds = host[0];
         if (o.profile) {
             float ms = 0;
@@ -392,7 +421,7 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
             out.relax_launches = 1;
         }
     } else {
-        const int grid = o.grid > 0 ? o.grid : 4 * cus;
+        const int grid = o.grid > 0 ? std::min(o.grid, kMaxGrid) : 4 * cus;
         out.grid = grid;
         out.block = 256;
         int64_t r = 0;
@@ -407,7 +436,7 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
                 HIPC(launch_compact(R, (int)(r + k), 0, s));
                 const bool timed = o.profile && ev + 1 < (int)S.events.size();
                 if (timed) HIPC(hipEventRecord(S.events[ev], s));
-                HIPC(launch_relax(S.dinst, R, (int)(r + k), grid, 256, dtype, enc_mask, s));
+                HIPC(launch_relax(S.dinst, R, (int)(r + k), grid, lanes, dtype, enc_mask, s));
                 if (timed) {
                     HIPC(hipEventRecord(S.events[ev + 1], s));
                     ev += 2;
@@ -437,11 +466,12 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
     }
     out.mode = mode;
     out.inst_status.assign(ninst, 0);
-    HIPC(hipMemcpyAsync(host + 16, S.ctr, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(host + 32, S.inst_status, 4 * ninst, hipMemcpyDeviceToHost, s));
+    HIPC(launch_sum_slots(S.slots, kMaxGrid, S.ctr, s));
+    HIPC(hipMemcpyAsync(host + 16, S.ctr, 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(host + 64, S.inst_status, 4 * ninst, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    std::memcpy(out.ctr, host + 16, 4 * sizeof(unsigned long long));
-    for (int i = 0; i < ninst; ++i) out.inst_status[i] = host[32 + i];
+    std::memcpy(out.ctr, host + 16, 6 * sizeof(unsigned long long));
+    for (int i = 0; i < ninst; ++i) out.inst_status[i] = host[64 + i];
     return GBF_OK;
 }
 
@@ -460,6 +490,8 @@ static void fill_stats(gbf_stats* st, int status, const SolveOut& so, int64_t ro
     st->edge_relax = (int64_t)so.ctr[1];
     st->improvements = (int64_t)so.ctr[2];
     st->saturations = (int64_t)so.ctr[3];
+    st->expansions = (int64_t)so.ctr[4];
+    st->marks = (int64_t)so.ctr[5];
     st->solve_ms = so.solve_ms;
     st->relax_ms = so.relax_ms;
     st->relax_launches = so.relax_launches;
@@ -467,6 +499,7 @@ static void fill_stats(gbf_stats* st, int status, const SolveOut& so, int64_t ro
     st->mode_used = so.mode;
     st->grid_used = so.grid;
     st->block_used = so.block;
+    st->lanes_used = so.lanes;
 }
 
 static int write_values(gbf_graph* g, void* V_out, int memspace, hipStream_t s) {
@@ -494,7 +527,7 @@ extern "C" int gbf_solve(gbf_graph* g, const gbf_opts* opts, void* V_out, gbf_st
     I.max_rounds = o.max_rounds > 0 ? o.max_rounds : g->n;
     std::vector<Inst> insts{I};
     SolveOut so;
-    int rc = run_rounds(g->scratch, insts, g->dtype, o, s, g->cus, so);
+    int rc = run_rounds(g->scratch, insts, g->dtype, o, s, g->cus, g->clock_khz, so);
     if (rc) return rc;
     if ((rc = write_values(g, V_out, o.v_memspace, s))) return rc;
     HIPC(hipEventRecord(g->scratch.events[1], s));
@@ -522,7 +555,7 @@ extern "C" int gbf_extract_policy(gbf_graph* g, int32_t* policy_out, int32_t mem
     int32_t* dst = memspace == GBF_DEVICE ? policy_out : (int32_t*)S.list;
     HIPC(launch_policy(g->inst, g->dtype, dst, bad, s));
     if (memspace != GBF_DEVICE) HIPC(hipMemcpyAsync(policy_out, dst, g->n * 4, hipMemcpyDeviceToHost, s));
-    unsigned long long* hb = (unsigned long long*)((char*)S.host + 1024);
+    unsigned long long* hb = (unsigned long long*)((char*)S.host + 64);
     HIPC(hipMemcpyAsync(hb, bad, 8, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     if (residual) *residual = (int64_t)*hb;
@@ -569,7 +602,7 @@ extern "C" int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gb
     }
     if (base >= ((int64_t)1 << 32)) return fail(GBF_EINVAL, "batch has >= 2^32 pairs");
     SolveOut so;
-    int rc = run_rounds(ctx->scratch, insts, dtype, o, s, graphs[0]->cus, so);
+    int rc = run_rounds(ctx->scratch, insts, dtype, o, s, graphs[0]->cus, graphs[0]->clock_khz, so);
     if (rc) return rc;
     for (int i = 0; i < count; ++i) {
         if (!V_outs || !V_outs[i]) continue;

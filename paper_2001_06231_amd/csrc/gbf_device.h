@@ -19,6 +19,19 @@ namespace gbf {
 constexpr int kWave = 64;
 constexpr uint32_t kNoList = 0xffffffffu;
 
+// Global address space.  Pointers read from the instance table are generic
+// to the compiler, which would otherwise emit flat loads (these wait on both
+// the vector-memory and the LDS counters and serialise the memory pipeline).
+#define GBF_GLOBAL __attribute__((address_space(1)))
+template <class P>
+__device__ __forceinline__ GBF_GLOBAL P* gp(P* p) {
+    return (GBF_GLOBAL P*)p;
+}
+template <class P>
+__device__ __forceinline__ const GBF_GLOBAL P* gp(const P* p) {
+    return (const GBF_GLOBAL P*)p;
+}
+
 struct TI32 {
     using key_t = int32_t;
     static constexpr int32_t INF = 0x7fffffff;
@@ -37,8 +50,9 @@ struct TI32 {
         d = (int32_t)s;
         return true;
     }
-    __device__ static __forceinline__ int32_t amin(int32_t* p, int32_t v) { return atomicMin(p, v); }
-    __device__ static __forceinline__ void lds_max(int32_t* p, int32_t v) { atomicMax(p, v); }
+    __device__ static __forceinline__ int32_t amin(GBF_GLOBAL int32_t* p, int32_t v) {
+        return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __device__ static __forceinline__ int32_t out_word(int32_t k) { return k; }
 };
 
@@ -67,8 +81,9 @@ struct TF32 {
         d = key(s);
         return true;
     }
-    __device__ static __forceinline__ uint32_t amin(uint32_t* p, uint32_t v) { return atomicMin(p, v); }
-    __device__ static __forceinline__ void lds_max(uint32_t* p, uint32_t v) { atomicMax(p, v); }
+    __device__ static __forceinline__ uint32_t amin(GBF_GLOBAL uint32_t* p, uint32_t v) {
+        return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __device__ static __forceinline__ int32_t out_word(uint32_t k) { return __float_as_int(unkey(k)); }
 };
 
@@ -103,23 +118,6 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
     return v;
-}
-
-// Largest k in [0,64) with off[k] <= j (off is non-decreasing, off[0] = 0).
-__device__ __forceinline__ int seg_search(const int* off, int j) {
-    int lo = 0;
-#pragma unroll
-    for (int step = 32; step > 0; step >>= 1)
-        if (off[lo + step] <= j) lo += step;
-    return lo;
-}
-
-// Sets bit q of a dirty-pair bitmap; a plain read first skips the atomic
-// when the bit is already set (bits are only ever set within a round).
-__device__ __forceinline__ void set_bit(uint32_t* bits, uint32_t q) {
-    uint32_t* w = bits + (q >> 5);
-    const uint32_t b = 1u << (q & 31);
-    if (!(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & b)) atomicOr(w, b);
 }
 
 }  // namespace gbf

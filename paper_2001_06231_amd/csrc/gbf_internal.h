@@ -36,11 +36,13 @@ struct Run {
     uint32_t* bits[2];          // dirty-pair bitmaps (frontiers F1/F2)
     uint32_t* list;             // compacted frontier (global pair ids)
     uint32_t* counts;           // frontier size per round [max_rounds + 2]
-    unsigned long long* ctr;    // [8]: pair evals, edges, improvements, saturations
+    unsigned long long* ctr;    // [8]: pair evals, edges, improvements, saturations, expansions, marks
+    unsigned long long* slots;  // per-block statistics [kMaxGrid * 8]
     int32_t* inst_status;       // per instance: 1 = cap reached with work left
     uint32_t* barrier;          // persistent mode: [0] arrive counter, [1] generation
     int32_t* error;             // persistent mode: barrier timeout flag
     int32_t* result;            // persistent mode: [0] rounds executed
+    uint64_t timeout_ticks;     // persistent mode: bound of one barrier wait (device clock ticks)
     int64_t nwords;             // words per bitmap
     int64_t total_pairs;
     int64_t max_rounds;         // global cap (max over instances)
@@ -49,6 +51,7 @@ struct Run {
 };
 
 constexpr int kMaxBatch = 1024;
+constexpr int kMaxGrid = 8192;  // most blocks of any solver launch
 
 // Launch wrappers (all asynchronous on `s`).
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
@@ -62,13 +65,17 @@ hipError_t launch_rev_fill(const Inst& I, uint32_t* cursor, uint32_t* rev, hipSt
 hipError_t launch_box_window(const Inst& I, int32_t* win32, hipStream_t s);
 
 hipError_t launch_init(const Inst* dI, const Inst& I, int dtype, hipStream_t s);
-hipError_t launch_seed(const Inst* dI, int ninst, const Run& R, int64_t max_states, int dtype, hipStream_t s);
+hipError_t launch_seed(const Inst* dI, int ninst, const Run& R, int64_t max_states, int dtype, int enc_mask,
+                       hipStream_t s);
 hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s);
-hipError_t launch_relax(const Inst* dI, const Run& R, int round, int grid, int block, int dtype, int enc_mask,
+// `lanes`: lanes per listed pair in the relax step (4, 8, 16 or 32)
+hipError_t launch_relax(const Inst* dI, const Run& R, int round, int grid, int lanes, int dtype, int enc_mask,
                         hipStream_t s);
-hipError_t launch_persistent(const Inst* dI, const Run& R, int grid, int block, int dtype, int enc_mask,
+hipError_t launch_persistent(const Inst* dI, const Run& R, int grid, int lanes, int dtype, int enc_mask,
                              hipStream_t s);
-int persistent_blocks_per_cu(int block, int dtype, int enc_mask);
+int persistent_blocks_per_cu(const Run& R, int lanes, int dtype, int enc_mask);
+hipError_t launch_sum_slots(const unsigned long long* slots, int nslots, unsigned long long* ctr, hipStream_t s);
+hipError_t launch_sort_rows(const uint32_t* rptr, uint32_t* rev, int64_t n, hipStream_t s);
 hipError_t launch_decode(const Inst& I, int dtype, void* out, hipStream_t s);
 hipError_t launch_policy(const Inst& I, int dtype, int32_t* pol, unsigned long long* bad, hipStream_t s);
 

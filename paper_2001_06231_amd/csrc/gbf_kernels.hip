@@ -28,26 +28,51 @@ constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 
 struct Acc {
-    unsigned long long pairs = 0, edges = 0, impr = 0, sat = 0;
+    unsigned long long pairs = 0, edges = 0, impr = 0, sat = 0, expanded = 0, marks = 0;
 };
 
-struct WaveLds {
-    int off[kWave];
-    const int32_t* row[kWave];
-    void* vbase[kWave];
-    uint32_t mx[kWave];
-    int64_t qbase[kWave];
-};
+// Statistics: each block owns kCtrSlot counters in R.slots (block index
+// slot), reduced once at the end of a solve; no two blocks of one launch
+// touch the same slot, so no atomics (and no contention) are needed.
+constexpr int kCtrSlot = 8;
 
-__device__ __forceinline__ void flush_acc(const Acc& a, unsigned long long* ctr) {
-    unsigned long long p = wave_sum64(a.pairs), e = wave_sum64(a.edges), i = wave_sum64(a.impr),
-                       s = wave_sum64(a.sat);
-    if (lane_id() == 0) {
-        if (p) atomicAdd(ctr + 0, p);
-        if (e) atomicAdd(ctr + 1, e);
-        if (i) atomicAdd(ctr + 2, i);
-        if (s) atomicAdd(ctr + 3, s);
+__device__ __forceinline__ void flush_acc(const Acc& a, unsigned long long* slots) {
+    __shared__ unsigned long long s_acc[kWavesPerBlock][6];
+    const unsigned long long v[6] = {a.pairs, a.edges, a.impr, a.sat, a.expanded, a.marks};
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const unsigned long long t = wave_sum64(v[k]);
+        if (lane_id() == 0) s_acc[w][k] = t;
     }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        unsigned long long t = 0;
+#pragma unroll
+        for (int k = 0; k < kWavesPerBlock; ++k) t += s_acc[k][threadIdx.x];
+        if (t) slots[blockIdx.x * kCtrSlot + threadIdx.x] += t;
+    }
+}
+
+__global__ void k_sum_slots(const unsigned long long* slots, int nslots, unsigned long long* ctr) {
+    __shared__ unsigned long long s[kBlock];
+    for (int k = 0; k < 6; ++k) {
+        unsigned long long t = 0;
+        for (int b = threadIdx.x; b < nslots; b += blockDim.x) t += slots[b * kCtrSlot + k];
+        s[threadIdx.x] = t;
+        __syncthreads();
+        for (int h = kBlock / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) ctr[k] = s[0];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_sum_slots(const unsigned long long* slots, int nslots, unsigned long long* ctr, hipStream_t s) {
+    k_sum_slots<<<1, kBlock, 0, s>>>(slots, nslots, ctr);
+    return hipGetLastError();
 }
 
 template <bool MULTI>
@@ -238,6 +263,51 @@ hipError_t launch_rev_fill(const Inst& I, uint32_t* cursor, uint32_t* rev, hipSt
     return hipGetLastError();
 }
 
+// Sorts every reverse row ascending (bitonic network in LDS, one wave per
+// row) so that the pairs a state marks are visited in ascending order and
+// marks to the same bitmap word can be combined.  Rows longer than
+// kSortCap stay unsorted, which only costs combining, not correctness.
+constexpr int kSortCap = 1024;
+__global__ __launch_bounds__(kBlock) void k_sort_rows(const uint32_t* __restrict__ rptr, uint32_t* __restrict__ rev,
+                                                     int64_t n) {
+    __shared__ uint32_t buf[kWavesPerBlock][kSortCap];
+    uint32_t* B = buf[threadIdx.x / kWave];
+    const int lane = lane_id();
+    for (int64_t row = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave; row < n;
+         row += (int64_t)gridDim.x * kWavesPerBlock) {
+        const uint32_t s0 = rptr[row], len = rptr[row + 1] - s0;
+        if (len <= 1 || len > (uint32_t)kSortCap) continue;
+        uint32_t np2 = 2;
+        while (np2 < len) np2 <<= 1;
+        for (uint32_t i = lane; i < np2; i += kWave) B[i] = i < len ? rev[s0 + i] : 0xffffffffu;
+        wave_sync();
+        for (uint32_t k = 2; k <= np2; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t i = lane; i < np2; i += kWave) {
+                    const uint32_t ixj = i ^ j;
+                    if (ixj > i) {
+                        const uint32_t a = B[i], b = B[ixj];
+                        const bool asc = (i & k) == 0;
+                        if ((a > b) == asc) {
+                            B[i] = b;
+                            B[ixj] = a;
+                        }
+                    }
+                }
+                wave_sync();
+            }
+        }
+        for (uint32_t i = lane; i < len; i += kWave) rev[s0 + i] = B[i];
+        wave_sync();
+    }
+}
+
+hipError_t launch_sort_rows(const uint32_t* rptr, uint32_t* rev, int64_t n, hipStream_t s) {
+    k_sort_rows<<<grid_for((n + kWavesPerBlock - 1) / kWavesPerBlock, 1, 4096), kBlock, 0, s>>>(rptr, rev, n);
+    return hipGetLastError();
+}
+
+
 // Exclusive scan of n uint32 into out[0..n] (out[n] = total), three phases.
 constexpr int kScanBlock = 1024;
 __global__ void k_scan_local(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* blocksum) {
@@ -341,101 +411,133 @@ hipError_t launch_init(const Inst* dI, const Inst& I, int dtype, hipStream_t s) 
 }
 
 // ------------------------------------------------------------------ expand
-// Marks in `bits` every live pair (x',u') with y in F(x',u'), for the
-// states y of the lanes with `active` set.  CSR: the 64 reverse rows are
-// streamed by the whole wave.
-__device__ __forceinline__ void expand_wave_csr(const Inst& I, bool active, int64_t y, uint32_t* bits, WaveLds& S) {
+// Marks a set of dirty pairs in a bitmap.  Lanes hold pair ids q (ascending
+// within the wave when the reverse rows are sorted); lanes whose q fall in
+// the same 32-bit word are combined first (segmented OR over the run), so
+// one atomicOr per word and wave suffices.  A relaxed read skips words whose
+// bits are all set already (bits are only ever set within a round).
+__device__ __forceinline__ void mark_pairs(uint32_t* __restrict__ bits, uint32_t q, bool valid) {
     const int lane = lane_id();
-    uint32_t s0 = 0, len = 0;
-    if (active) {
-        s0 = I.rptr[y];
-        len = I.rptr[y + 1] - s0;
+    const uint32_t w = valid ? (q >> 5) : 0xffffffffu;
+    uint32_t m = valid ? (1u << (q & 31)) : 0u;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t om = __shfl_up(m, d, kWave);
+        const uint32_t ow = __shfl_up(w, d, kWave);
+        if (lane >= d && ow == w) m |= om;
     }
-    const int incl = wave_incl_scan((int)len);
-    const int total = __shfl(incl, kWave - 1, kWave);
-    if (total == 0) return;
-    wave_sync();
-    S.off[lane] = incl - (int)len;
-    S.row[lane] = reinterpret_cast<const int32_t*>(I.rev + s0);
-    S.qbase[lane] = I.pair_base;
-    wave_sync();
-    for (int j = lane; j < total; j += kWave) {
-        const int k = seg_search(S.off, j);
-        const uint32_t q = (uint32_t)S.row[k][j - S.off[k]];
-        set_bit(bits, (uint32_t)S.qbase[k] + q);
+    const uint32_t wn = __shfl_down(w, 1, kWave);
+    if (valid && (lane == kWave - 1 || wn != w)) {
+        GBF_GLOBAL uint32_t* word = gp(bits) + w;
+        // plain read: a stale word only has fewer bits set, never more
+        const uint32_t cur = *word;
+        if ((cur & m) != m) __hip_atomic_fetch_or(word, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    wave_sync();
 }
 
-// BOX: every input's predecessor window is scanned and filtered by
-// decoding the candidate's box (lane per state).
-__device__ __forceinline__ void expand_lane_box(const Inst& I, int64_t y, uint32_t* bits, int dtype) {
+// Whole-wave expansion of one state y (wave-uniform arguments): every live
+// pair (x',u') with y in F(x',u') is marked.  CSR: the (sorted) reverse row
+// of y is streamed by the wave.  BOX: for every input the predecessor
+// window is streamed and each candidate's box is decoded to filter it.
+template <int ENC>
+__device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint32_t* __restrict__ bits, Acc& acc) {
+    const int lane = lane_id();
+    const uint32_t base = (uint32_t)I.pair_base;
+    if (ENC == 1 || (ENC == 3 && I.enc == 0)) {
+        const GBF_GLOBAL uint32_t* rptr = gp(I.rptr);
+        const GBF_GLOBAL uint32_t* rev = gp(I.rev);
+        const uint32_t s0 = rptr[y], len = rptr[y + 1] - s0;
+        if (lane == 0) {
+            acc.expanded += 1;
+            acc.marks += len;
+        }
+        for (uint32_t t0 = 0; t0 < len; t0 += kWave) {
+            const uint32_t t = t0 + (uint32_t)lane;
+            const bool v = t < len;
+            const uint32_t q = v ? base + rev[s0 + t] : 0u;
+            mark_pairs(bits, q, v);
+        }
+        return;
+    }
     int yc[4];
     int64_t r = y;
+#pragma unroll
     for (int a = 0; a < 4; ++a) {
         yc[a] = (int)(r % I.dims[a]);
         r /= I.dims[a];
     }
-    const uint32_t base = (uint32_t)I.pair_base;
+    if (lane == 0) acc.expanded += 1;
+    const int dt = I.dtype;
     for (int u = 0; u < I.K; ++u) {
         const int32_t* w = I.win + u * 8;
-        int lo[4], hi[4];
+        int lo[4], sz[4];
         bool empty = false;
+#pragma unroll
         for (int a = 0; a < 4; ++a) {
             lo[a] = max(0, yc[a] - w[4 + a]);
-            hi[a] = min(I.dims[a] - 1, yc[a] - w[a]);
-            empty |= lo[a] > hi[a];
+            const int hi = min(I.dims[a] - 1, yc[a] - w[a]);
+            sz[a] = hi - lo[a] + 1;
+            empty |= sz[a] <= 0;
         }
         if (empty) continue;
-        for (int c3 = lo[3]; c3 <= hi[3]; ++c3)
-            for (int c2 = lo[2]; c2 <= hi[2]; ++c2)
-                for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
-                    for (int c0 = lo[0]; c0 <= hi[0]; ++c0) {
-                        const int64_t x = c0 + (int64_t)c1 * I.strides[1] + (int64_t)c2 * I.strides[2] +
-                                          (int64_t)c3 * I.strides[3];
-                        const int64_t q = x * I.K + u;
-                        if (!pair_live(I, q, dtype)) continue;
-                        BoxDec d = decode_box(I.box[q]);
-                        int64_t rr = d.lo;
-                        bool in = true;
-                        for (int a = 0; a < 4; ++a) {
-                            int lc = (int)(rr % I.dims[a]);
-                            rr /= I.dims[a];
-                            in &= (yc[a] >= lc) && (yc[a] <= lc + d.e[a]);
-                        }
-                        if (in) set_bit(bits, base + (uint32_t)q);
+        const uint32_t total = (uint32_t)(sz[0] * sz[1] * sz[2] * sz[3]);
+        if (lane == 0) acc.marks += total;
+        for (uint32_t t0 = 0; t0 < total; t0 += kWave) {
+            const uint32_t t = t0 + (uint32_t)lane;
+            bool hit = false;
+            uint32_t q = 0;
+            if (t < total) {
+                uint32_t rr = t;
+                const int c0 = (int)(rr % (uint32_t)sz[0]);
+                rr /= (uint32_t)sz[0];
+                const int c1 = (int)(rr % (uint32_t)sz[1]);
+                rr /= (uint32_t)sz[1];
+                const int c2 = (int)(rr % (uint32_t)sz[2]);
+                const int c3 = (int)(rr / (uint32_t)sz[2]);
+                const int64_t x = (lo[0] + c0) + (int64_t)(lo[1] + c1) * I.strides[1] +
+                                  (int64_t)(lo[2] + c2) * I.strides[2] + (int64_t)(lo[3] + c3) * I.strides[3];
+                const int64_t qq = x * I.K + u;
+                if (pair_live(I, qq, dt)) {
+                    const BoxDec d = decode_box(I.box[qq]);
+                    int64_t lr = d.lo;
+                    bool in = true;
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const int lc = (int)(lr % I.dims[a]);
+                        lr /= I.dims[a];
+                        in &= (yc[a] >= lc) && (yc[a] <= lc + d.e[a]);
                     }
+                    hit = in;
+                    q = base + (uint32_t)qq;
+                }
+            }
+            mark_pairs(bits, q, hit);
+        }
     }
 }
 
 // Seed: F1 <- union of pred(y) over states with G(y) < INF (Algorithm 1
-// initialisation), at pair level.
-template <class T>
+// initialisation), at pair level.  Each wave looks at 64 states and expands
+// the targets among them one after the other.
+template <class T, int ENC>
 __global__ __launch_bounds__(kBlock) void k_seed(const Inst* __restrict__ It, int ninst, Run R) {
-    __shared__ WaveLds lds[kWavesPerBlock];
-    WaveLds& S = lds[threadIdx.x / kWave];
+    Acc acc;
     for (int ii = 0; ii < ninst; ++ii) {
-        const Inst I = It[ii];
+        const Inst& I = It[ii];
         const int64_t nw = (I.n + kWave - 1) / kWave;
         for (int64_t w = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave; w < nw;
              w += (int64_t)gridDim.x * kWavesPerBlock) {
             const int64_t y = w * kWave + lane_id();
             bool act = false;
-            if (y < I.n) {
-                const auto Gk = T::from_raw(I.G[y]);
-                act = Gk != T::INF && !(I.avoid && I.avoid[y]);
+            if (y < I.n) act = T::from_raw(I.G[y]) != T::INF && !I.avoid[y];
+            unsigned long long bal = __ballot(act);
+            while (bal) {
+                const int l = __ffsll(bal) - 1;
+                bal &= bal - 1;
+                expand_state<ENC>(I, w * kWave + l, R.bits[0], acc);
             }
-            if (I.enc == 0) expand_wave_csr(I, act, y, R.bits[0], S);
-            else if (act) expand_lane_box(I, y, R.bits[0], R.dtype);
         }
     }
-}
-
-hipError_t launch_seed(const Inst* dI, int ninst, const Run& R, int64_t max_states, int dtype, hipStream_t s) {
-    const int grid = grid_for((max_states + kWave - 1) / kWave, kWavesPerBlock, 4096);
-    if (dtype == 1) k_seed<TF32><<<grid, kBlock, 0, s>>>(dI, ninst, R);
-    else k_seed<TI32><<<grid, kBlock, 0, s>>>(dI, ninst, R);
-    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ compact
@@ -446,7 +548,7 @@ __device__ __forceinline__ void compact_tile(uint32_t* __restrict__ bits, int64_
                                              uint32_t* __restrict__ list, uint32_t* cnt, int* s_w, uint32_t* s_base) {
     const int t = threadIdx.x;
     const int64_t wi = tile * kBlock + t;
-    uint32_t word = wi < nwords ? bits[wi] : 0u;
+    uint32_t word = wi < nwords ? gp(bits)[wi] : 0u;
     const int c = __popc(word);
     const int incl = wave_incl_scan(c);
     const int w = t / kWave;
@@ -464,11 +566,12 @@ __device__ __forceinline__ void compact_tile(uint32_t* __restrict__ bits, int64_
         __syncthreads();
         uint32_t pos = *s_base + (uint32_t)(wofs + incl - c);
         if (word) {
-            bits[wi] = 0u;
+            gp(bits)[wi] = 0u;
             const uint32_t bitbase = (uint32_t)(wi * 32);
+            GBF_GLOBAL uint32_t* out = gp(list);
             while (word) {
                 const int b = __ffs(word) - 1;
-                list[pos++] = bitbase + (uint32_t)b;
+                out[pos++] = bitbase + (uint32_t)b;
                 word &= word - 1u;
             }
         }
@@ -495,80 +598,83 @@ hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ relax
-// One wave handles list entries [base, base+64).  CSR: the successor rows of
-// the 64 pairs are concatenated and streamed by all lanes (coalesced), each
-// lane folding V[y] into its pair's LDS max; BOX: each lane decodes its own
-// box and walks it.
-template <class T, bool MULTI>
-__device__ __forceinline__ void relax_chunk(const Inst* __restrict__ It, const int64_t* bases, int ninst,
-                                            const Run& R, uint32_t count, uint32_t base, int round,
-                                            uint32_t* __restrict__ next, WaveLds& S, Acc& acc, int enc_mask) {
+// G lanes per listed pair: the group streams the pair's successor row (CSR,
+// coalesced) or walks its box (BOX), folds V[y] into a running max and
+// reduces it across the group with lane shuffles.  The group leader forms
+// d = g(x,u) + max and applies the strict improvement with atomicMin.  The
+// first improvement of a state in a round expands it with the whole wave.
+template <class T, int G>
+__device__ __forceinline__ typename T::key_t group_max(typename T::key_t v) {
+#pragma unroll
+    for (int d = G / 2; d > 0; d >>= 1) v = T::max2(v, __shfl_xor(v, d, kWave));
+    return v;
+}
+
+template <class T, bool MULTI, int ENC, int G>
+__device__ __forceinline__ void relax_wave(const Inst* __restrict__ It, const int64_t* bases, const Run& R,
+                                           uint32_t count, uint32_t first, int round, uint32_t* __restrict__ next,
+                                           Acc& acc) {
     using K = typename T::key_t;
     const int lane = lane_id();
-    const uint32_t i = base + (uint32_t)lane;
+    const int sub = lane & (G - 1);
+    const uint32_t i = first + (uint32_t)(lane / G);
     bool valid = i < count;
-    const uint32_t q = valid ? R.list[i] : 0u;
-    const int ii = find_inst<MULTI>(bases, ninst, (int64_t)q);
+    const uint32_t q = valid ? gp(R.list)[i] : 0u;
+    const int ii = find_inst<MULTI>(bases, R.ninst, (int64_t)q);
     const Inst& I = It[ii];
-    const int64_t p = (int64_t)q - (MULTI ? I.pair_base : 0);
+    const uint32_t p = q - (MULTI ? (uint32_t)I.pair_base : 0u);
     if (valid && round >= I.max_rounds) {
-        // this instance's round cap is reached with work left (Algorithm 1's
-        // second loop condition): its pairs are dropped and it is flagged
-        R.inst_status[ii] = 1;
+        // the instance's round cap (second condition of Algorithm 1's while
+        // loop) is reached with work left: drop the pair, flag the instance
+        if (sub == 0) R.inst_status[ii] = 1;
         valid = false;
     }
-    K* V = static_cast<K*>(I.V);
-    K m = T::INF;
-    if (enc_mask & 1) {  // some CSR instance present
-        const bool csr = valid && I.enc == 0;
-        uint32_t s0 = 0, len = 0;
-        if (csr) {
-            s0 = I.sptr[p];
-            len = I.sptr[p + 1] - s0;
-        }
-        const int incl = wave_incl_scan((int)len);
-        const int total = __shfl(incl, kWave - 1, kWave);
-        S.off[lane] = incl - (int)len;
-        S.row[lane] = I.sidx + s0;
-        S.vbase[lane] = I.V;
-        S.mx[lane] = (uint32_t)T::LOWEST;
-        wave_sync();
-        for (int j = lane; j < total; j += kWave) {
-            const int k = seg_search(S.off, j);
-            const int32_t y = S.row[k][j - S.off[k]];
-            const K v = MULTI ? static_cast<const K*>(S.vbase[k])[y] : V[y];
-            T::lds_max(reinterpret_cast<K*>(&S.mx[k]), v);
-        }
-        wave_sync();
-        if (csr) {
-            m = (K)S.mx[lane];
-            acc.edges += len;
-        }
-        wave_sync();
-    }
-    if ((enc_mask & 2) && valid && I.enc == 1) {
-        const BoxDec d = decode_box(I.box[p]);
-        K mx = (K)T::LOWEST;
-        for (int j3 = 0; j3 <= d.e[3]; ++j3)
-            for (int j2 = 0; j2 <= d.e[2]; ++j2)
-                for (int j1 = 0; j1 <= d.e[1]; ++j1) {
-                    const K* row = V + d.lo + (int64_t)j1 * I.strides[1] + (int64_t)j2 * I.strides[2] +
-                                   (int64_t)j3 * I.strides[3];
-                    for (int j0 = 0; j0 <= d.e[0]; ++j0) mx = T::max2(mx, row[j0]);
-                }
-        m = mx;
-        acc.edges += (unsigned long long)(d.e[0] + 1) * (d.e[1] + 1) * (d.e[2] + 1) * (d.e[3] + 1);
-    }
-    bool improved = false;
-    int64_t x = 0;
+    GBF_GLOBAL K* V = gp(static_cast<K*>(I.V));
+    K mx = (K)T::LOWEST;
+    uint32_t len = 0;
     if (valid) {
+        if (ENC == 1 || (ENC == 3 && I.enc == 0)) {
+            const GBF_GLOBAL uint32_t* sptr = gp(I.sptr);
+            const uint32_t s0 = sptr[p];
+            len = sptr[p + 1] - s0;
+            const GBF_GLOBAL int32_t* row = gp(I.sidx) + s0;
+            uint32_t t = (uint32_t)sub;
+            for (; t + G < len; t += 2 * G) {
+                const int32_t y0 = row[t], y1 = row[t + G];
+                const K v0 = V[y0], v1 = V[y1];
+                mx = T::max2(mx, T::max2(v0, v1));
+            }
+            if (t < len) mx = T::max2(mx, V[row[t]]);
+        } else {
+            const BoxDec d = decode_box(gp(I.box)[p]);
+            const uint32_t w0 = d.e[0] + 1, w1 = d.e[1] + 1, w2 = d.e[2] + 1;
+            const uint32_t lo = (uint32_t)d.lo, st1 = (uint32_t)I.strides[1], st2 = (uint32_t)I.strides[2],
+                           st3 = (uint32_t)I.strides[3];
+            len = w0 * w1 * w2 * (uint32_t)(d.e[3] + 1);
+            for (uint32_t t = (uint32_t)sub; t < len; t += G) {
+                const uint32_t rr = t / w0;
+                const uint32_t j0 = t - rr * w0;
+                const uint32_t r2 = rr / w1;
+                const uint32_t j1 = rr - r2 * w1;
+                const uint32_t j3 = r2 / w2;
+                const uint32_t j2 = r2 - j3 * w2;
+                mx = T::max2(mx, V[lo + j0 + j1 * st1 + j2 * st2 + j3 * st3]);
+            }
+        }
+    }
+    mx = group_max<T, G>(mx);
+    bool improved = false;
+    uint32_t x = 0;
+    if (valid && sub == 0) {
         acc.pairs += 1;
-        x = p / I.K;
+        acc.edges += len;
+        x = p / (uint32_t)I.K;
         K d;
         int sat = 0;
-        if (T::backup(I.g[p], m, d, sat)) {
+        if (T::backup(gp(I.g)[p], mx, d, sat)) {
             acc.sat += (unsigned)sat;
-            const K cur = __hip_atomic_load(V + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // plain read first: a stale V(x) is only ever too large
+            const K cur = V[x];
             if (T::less(d, cur)) {
                 const K old = T::amin(V + x, d);
                 if (T::less(d, old)) {
@@ -578,16 +684,37 @@ __device__ __forceinline__ void relax_chunk(const Inst* __restrict__ It, const i
             }
         }
     }
-    // first improvement of x in this round expands it (one expansion per
-    // state and round suffices: pairs marked now re-read V(x) next round)
-    const bool expand = improved && (atomicExch(I.stamp + x, round) != round);
-    if (enc_mask & 1) expand_wave_csr(I, expand && I.enc == 0, x, next, S);
-    if ((enc_mask & 2) && expand && I.enc == 1) expand_lane_box(I, x, next, R.dtype);
+    // one expansion per state and round suffices: the pairs it marks read
+    // V(x) again in the next round, after every update of this round
+    const bool expand =
+        improved && (__hip_atomic_exchange(gp(I.stamp) + x, round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != round);
+    unsigned long long bal = __ballot(expand);
+    while (bal) {
+        const int l = __ffsll(bal) - 1;
+        bal &= bal - 1;
+        const uint32_t xl = __shfl(x, l, kWave);
+        if (MULTI) {
+            const int il = __shfl(ii, l, kWave);
+            expand_state<ENC>(It[il], xl, next, acc);
+        } else {
+            expand_state<ENC>(It[0], xl, next, acc);
+        }
+    }
 }
 
-template <class T, bool MULTI>
-__global__ __launch_bounds__(kBlock) void k_relax(const Inst* __restrict__ It, Run R, int round, int enc_mask) {
-    __shared__ WaveLds lds[kWavesPerBlock];
+template <class T, bool MULTI, int ENC, int G>
+__device__ __forceinline__ void relax_round(const Inst* __restrict__ It, const int64_t* bases, const Run& R,
+                                            uint32_t count, int round, Acc& acc) {
+    constexpr uint32_t W = kWave / G;  // pairs per wave and step
+    uint32_t* next = R.bits[(round + 1) & 1];
+    const uint32_t wave = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    for (uint32_t first = wave * W; first < count; first += nwaves * W)
+        relax_wave<T, MULTI, ENC, G>(It, bases, R, count, first, round, next, acc);
+}
+
+template <class T, bool MULTI, int ENC, int G>
+__global__ __launch_bounds__(kBlock) void k_relax(const Inst* __restrict__ It, Run R, int round) {
     __shared__ int64_t s_bases[MULTI ? kMaxBatch : 1];
     const uint32_t count = R.counts[round];
     if (count == 0) return;
@@ -595,37 +722,17 @@ __global__ __launch_bounds__(kBlock) void k_relax(const Inst* __restrict__ It, R
         for (int k = threadIdx.x; k < R.ninst; k += blockDim.x) s_bases[k] = It[k].pair_base;
         __syncthreads();
     }
-    WaveLds& S = lds[threadIdx.x / kWave];
     Acc acc;
-    uint32_t* next = R.bits[(round + 1) & 1];
-    const uint32_t nchunks = (count + kWave - 1) / kWave;
-    for (uint32_t c = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; c < nchunks;
-         c += gridDim.x * kWavesPerBlock)
-        relax_chunk<T, MULTI>(It, s_bases, R.ninst, R, count, c * kWave, round, next, S, acc, enc_mask);
-    flush_acc(acc, R.ctr);
-}
-
-hipError_t launch_relax(const Inst* dI, const Run& R, int round, int grid, int block, int dtype, int enc_mask,
-                        hipStream_t s) {
-    (void)block;
-    const int g = grid > 0 ? grid : 1024;
-    const bool multi = R.ninst > 1;
-    if (dtype == 1) {
-        if (multi) k_relax<TF32, true><<<g, kBlock, 0, s>>>(dI, R, round, enc_mask);
-        else k_relax<TF32, false><<<g, kBlock, 0, s>>>(dI, R, round, enc_mask);
-    } else {
-        if (multi) k_relax<TI32, true><<<g, kBlock, 0, s>>>(dI, R, round, enc_mask);
-        else k_relax<TI32, false><<<g, kBlock, 0, s>>>(dI, R, round, enc_mask);
-    }
-    return hipGetLastError();
+    relax_round<T, MULTI, ENC, G>(It, s_bases, R, count, round, acc);
+    flush_acc(acc, R.slots);
 }
 
 // ------------------------------------------------------------------ persistent
-// All rounds in one launch.  Every wait is bounded: a barrier that does not
-// complete within ~2 s sets R.error and every block leaves the loop.
-constexpr uint64_t kSpinLimit = 1ull << 25;
-
-__device__ __forceinline__ bool grid_barrier(uint32_t* bar, int32_t* err, uint32_t nblocks) {
+// All rounds in one launch.  Every wait is bounded in wall-clock time: a
+// barrier that does not complete within R.timeout_ticks of the constant-rate
+// device clock sets R.error, and every block leaves the loop (blocks that
+// start after an error leave at once).
+__device__ __forceinline__ bool grid_barrier(uint32_t* bar, int32_t* err, uint32_t nblocks, uint64_t timeout_ticks) {
     __shared__ int s_ok;
     __threadfence();
     __syncthreads();
@@ -637,10 +744,11 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* bar, int32_t* err, uint32
             __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(bar + 1, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            uint64_t spins = 0;
+            const uint64_t t0 = wall_clock64();
             while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 __builtin_amdgcn_s_sleep(2);
-                if (++spins > kSpinLimit) {
+                if (wall_clock64() - t0 > timeout_ticks ||
+                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                     atomicOr(err, 1);
                     ok = 0;
                     break;
@@ -655,9 +763,8 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* bar, int32_t* err, uint32
     return s_ok != 0;
 }
 
-template <class T, bool MULTI>
-__global__ __launch_bounds__(kBlock) void k_persistent(const Inst* __restrict__ It, Run R, int enc_mask) {
-    __shared__ WaveLds lds[kWavesPerBlock];
+template <class T, bool MULTI, int ENC, int G>
+__global__ __launch_bounds__(kBlock) void k_persistent(const Inst* __restrict__ It, Run R) {
     __shared__ int64_t s_bases[MULTI ? kMaxBatch : 1];
     __shared__ int s_w[kWavesPerBlock];
     __shared__ uint32_t s_base;
@@ -665,54 +772,98 @@ __global__ __launch_bounds__(kBlock) void k_persistent(const Inst* __restrict__ 
         for (int k = threadIdx.x; k < R.ninst; k += blockDim.x) s_bases[k] = It[k].pair_base;
         __syncthreads();
     }
-    WaveLds& S = lds[threadIdx.x / kWave];
+    if (__hip_atomic_load(R.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
     Acc acc;
     const int64_t ntiles = (R.nwords + kBlock - 1) / kBlock;
     for (int round = 0;; ++round) {
         uint32_t* cur = R.bits[round & 1];
         for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
             compact_tile(cur, R.nwords, tile, R.list, R.counts + round, s_w, &s_base);
-        if (!grid_barrier(R.barrier, R.error, gridDim.x)) break;
+        if (!grid_barrier(R.barrier, R.error, gridDim.x, R.timeout_ticks)) break;
         const uint32_t count = __hip_atomic_load(R.counts + round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (count == 0) {
             if (blockIdx.x == 0 && threadIdx.x == 0) R.result[0] = round;
             break;
         }
-        uint32_t* next = R.bits[(round + 1) & 1];
-        const uint32_t nchunks = (count + kWave - 1) / kWave;
-        for (uint32_t c = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; c < nchunks;
-             c += gridDim.x * kWavesPerBlock)
-            relax_chunk<T, MULTI>(It, s_bases, R.ninst, R, count, c * kWave, round, next, S, acc, enc_mask);
-        if (!grid_barrier(R.barrier, R.error, gridDim.x)) break;
+        relax_round<T, MULTI, ENC, G>(It, s_bases, R, count, round, acc);
+        if (!grid_barrier(R.barrier, R.error, gridDim.x, R.timeout_ticks)) break;
     }
-    flush_acc(acc, R.ctr);
+    flush_acc(acc, R.slots);
 }
 
-template <class T, bool MULTI>
-static int occ_of() {
+// ------------------------------------------------------------------ dispatch
+// Kernel variants: value type (int32 / fp32 key), single or batched
+// instance table, encoding (1 CSR, 2 BOX, 3 mixed batch) and lanes per pair.
+using RelaxFn = void (*)(const Inst*, Run, int);
+using PersistFn = void (*)(const Inst*, Run);
+using SeedFn = void (*)(const Inst*, int, Run);
+
+template <class T, bool MULTI, int ENC>
+static void pick(int G, RelaxFn* rf, PersistFn* pf) {
+    switch (G) {
+        case 4: *rf = k_relax<T, MULTI, ENC, 4>; *pf = k_persistent<T, MULTI, ENC, 4>; break;
+        case 16: *rf = k_relax<T, MULTI, ENC, 16>; *pf = k_persistent<T, MULTI, ENC, 16>; break;
+        case 32: *rf = k_relax<T, MULTI, ENC, 32>; *pf = k_persistent<T, MULTI, ENC, 32>; break;
+        default: *rf = k_relax<T, MULTI, ENC, 8>; *pf = k_persistent<T, MULTI, ENC, 8>; break;
+    }
+}
+
+template <class T>
+static void pick_t(bool multi, int enc_mask, int G, RelaxFn* rf, PersistFn* pf) {
+    if (multi) {
+        if (enc_mask == 1) pick<T, true, 1>(G, rf, pf);
+        else if (enc_mask == 2) pick<T, true, 2>(G, rf, pf);
+        else pick<T, true, 3>(G, rf, pf);
+    } else {
+        if (enc_mask == 2) pick<T, false, 2>(G, rf, pf);
+        else pick<T, false, 1>(G, rf, pf);
+    }
+}
+
+static void pick_all(const Run& R, int dtype, int enc_mask, int G, RelaxFn* rf, PersistFn* pf) {
+    if (dtype == 1) pick_t<TF32>(R.ninst > 1, enc_mask, G, rf, pf);
+    else pick_t<TI32>(R.ninst > 1, enc_mask, G, rf, pf);
+}
+
+hipError_t launch_seed(const Inst* dI, int ninst, const Run& R, int64_t max_states, int dtype, int enc_mask,
+                       hipStream_t s) {
+    const int grid = grid_for((max_states + kWave - 1) / kWave, kWavesPerBlock, 4096);
+    SeedFn f;
+    if (dtype == 1) f = enc_mask == 1 ? k_seed<TF32, 1> : enc_mask == 2 ? k_seed<TF32, 2> : k_seed<TF32, 3>;
+    else f = enc_mask == 1 ? k_seed<TI32, 1> : enc_mask == 2 ? k_seed<TI32, 2> : k_seed<TI32, 3>;
+    f<<<grid, kBlock, 0, s>>>(dI, ninst, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_relax(const Inst* dI, const Run& R, int round, int grid, int lanes, int dtype, int enc_mask,
+                        hipStream_t s) {
+    RelaxFn rf;
+    PersistFn pf;
+    pick_all(R, dtype, enc_mask, lanes, &rf, &pf);
+    rf<<<grid > 0 ? std::min(grid, kMaxGrid) : 1024, kBlock, 0, s>>>(dI, R, round);
+    return hipGetLastError();
+}
+
+int persistent_blocks_per_cu(const Run& R, int lanes, int dtype, int enc_mask) {
+    RelaxFn rf;
+    PersistFn pf;
+    pick_all(R, dtype, enc_mask, lanes, &rf, &pf);
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<T, MULTI>, kBlock, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(pf), kBlock, 0) !=
+        hipSuccess)
+        return 0;
     return nb;
 }
 
-int persistent_blocks_per_cu(int block, int dtype, int enc_mask) {
-    (void)block;
-    (void)enc_mask;
-    return dtype == 1 ? std::min(occ_of<TF32, false>(), occ_of<TF32, true>())
-                      : std::min(occ_of<TI32, false>(), occ_of<TI32, true>());
-}
-
-hipError_t launch_persistent(const Inst* dI, const Run& R, int grid, int block, int dtype, int enc_mask,
+hipError_t launch_persistent(const Inst* dI, const Run& R, int grid, int lanes, int dtype, int enc_mask,
                              hipStream_t s) {
-    (void)block;
-    const bool multi = R.ninst > 1;
+    RelaxFn rf;
+    PersistFn pf;
+    pick_all(R, dtype, enc_mask, lanes, &rf, &pf);
     Run r = R;
-    int em = enc_mask;
-    void* args[] = {(void*)&dI, (void*)&r, (void*)&em};
-    const void* fn;
-    if (dtype == 1) fn = multi ? (const void*)k_persistent<TF32, true> : (const void*)k_persistent<TF32, false>;
-    else fn = multi ? (const void*)k_persistent<TI32, true> : (const void*)k_persistent<TI32, false>;
-    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBlock), args, 0, s);
+    const Inst* di = dI;
+    void* args[] = {(void*)&di, (void*)&r};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(pf), dim3(grid), dim3(kBlock), args, 0, s);
 }
 
 // ------------------------------------------------------------------ outputs
