@@ -114,11 +114,13 @@ typedef struct gbf_opts {
                                    only the processing order depends on it */
     int64_t max_rounds;     /* round cap; 0 = n (the paper's i < |X|) */
     int32_t lanes;          /* lanes per frontier pair in the relax step:
-                               4, 8, 16 or 32; 0 = default (8) */
+                               1, 2, 4, 8, 16 or 32; 0 = default (4) */
     int32_t grid;           /* blocks; 0 = default */
     int32_t v_memspace;     /* where V_out lives: GBF_HOST or GBF_DEVICE */
     int32_t profile;        /* 1 = time every relax launch with HIP events */
-    int32_t reserved[4];
+    int32_t batch_hint;     /* host-loop mode: rounds launched before the first
+                               frontier-size check; 0 = default (8) */
+    int32_t reserved[3];
 } gbf_opts;
 
 /* ---- statistics ------------------------------------------------------- */

@@ -51,7 +51,8 @@ class _Problem(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("mode", ctypes.c_int32), ("bucket_key", ctypes.c_void_p),
                 ("max_rounds", ctypes.c_int64), ("lanes", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("v_memspace", ctypes.c_int32), ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("v_memspace", ctypes.c_int32), ("profile", ctypes.c_int32), ("batch_hint", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class _Stats(ctypes.Structure):

@@ -19,7 +19,7 @@ static thread_local std::string t_err;
 
 // Blocks per CU of the persistent kernel: below the occupancy limit, so that
 // the cooperative grid is co-resident with margin.
-constexpr int kPersistentBlocksPerCU = 4;
+constexpr int kPersistentBlocksPerCU = 1;
 
 static int fail(int code, const std::string& msg) {
     t_err = msg;
@@ -66,7 +66,7 @@ struct DevMem {
 struct Scratch {
     int64_t total_pairs = 0;
     int64_t counts_cap = 0;
-    uint32_t* bits[2] = {nullptr, nullptr};
+    uint8_t* dirty[2] = {nullptr, nullptr};
     uint32_t* list = nullptr;
     uint32_t* counts = nullptr;
     unsigned long long* ctr = nullptr;
@@ -105,12 +105,12 @@ struct gbf_graph {
 };
 
 static int ensure_scratch(Scratch& S, int64_t total_pairs, int64_t max_rounds, int ninst, int nevents) {
-    const int64_t nwords = (total_pairs + 31) / 32;
+    const int64_t nchunks = (total_pairs + 15) / 16;
     if (S.total_pairs < total_pairs) {
-        if (S.bits[0]) S.mem.release(S.bits[0], 0), S.mem.release(S.bits[1], 0), S.mem.release(S.list, 0);
+        if (S.dirty[0]) S.mem.release(S.dirty[0], 0), S.mem.release(S.dirty[1], 0), S.mem.release(S.list, 0);
         int rc;
-        if ((rc = S.mem.alloc((void**)&S.bits[0], nwords * 4))) return rc;
-        if ((rc = S.mem.alloc((void**)&S.bits[1], nwords * 4))) return rc;
+        if ((rc = S.mem.alloc((void**)&S.dirty[0], nchunks * 16))) return rc;
+        if ((rc = S.mem.alloc((void**)&S.dirty[1], nchunks * 16))) return rc;
         if ((rc = S.mem.alloc((void**)&S.list, total_pairs * 4))) return rc;
         S.total_pairs = total_pairs;
     }
@@ -344,8 +344,8 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
     int rc = ensure_scratch(S, total_pairs, max_rounds, ninst, nevents);
     if (rc) return rc;
     Run R{};
-    R.bits[0] = S.bits[0];
-    R.bits[1] = S.bits[1];
+    R.dirty[0] = S.dirty[0];
+    R.dirty[1] = S.dirty[1];
     R.list = S.list;
     R.counts = S.counts;
     R.ctr = S.ctr;
@@ -354,7 +354,7 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
     R.barrier = S.barrier;
     R.error = S.error;
     R.result = S.result;
-    R.nwords = (total_pairs + 31) / 32;
+    R.nchunks = (total_pairs + 15) / 16;
     R.total_pairs = total_pairs;
     R.max_rounds = max_rounds;
     R.ninst = ninst;
@@ -365,8 +365,8 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
 
     HIPC(hipEventRecord(S.events[0], s));
     HIPC(hipMemcpyAsync(S.dinst, insts.data(), sizeof(Inst) * ninst, hipMemcpyHostToDevice, s));
-    HIPC(launch_fill_u32(R.bits[0], 0, R.nwords, s));
-    HIPC(launch_fill_u32(R.bits[1], 0, R.nwords, s));
+    HIPC(launch_fill_u32((uint32_t*)R.dirty[0], 0, R.nchunks * 4, s));
+    HIPC(launch_fill_u32((uint32_t*)R.dirty[1], 0, R.nchunks * 4, s));
     HIPC(launch_fill_u32(R.counts, 0, max_rounds + 2, s));
     HIPC(launch_fill_u32((uint32_t*)R.ctr, 0, 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.slots, 0, (int64_t)kMaxGrid * 16, s));
@@ -379,7 +379,10 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
 
     int mode = o.mode;
     int per_cu = 0;
-    const int lanes = o.lanes == 4 || o.lanes == 16 || o.lanes == 32 ? o.lanes : 8;
+    const int lanes = (o.lanes == 1 || o.lanes == 2 || o.lanes == 4 || o.lanes == 8 || o.lanes == 16 ||
+                       o.lanes == 32)
+                          ? o.lanes
+                          : 4;
     out.lanes = lanes;
     if (mode != GBF_MODE_HOSTLOOP) {
         per_cu = persistent_blocks_per_cu(R, lanes, dtype, enc_mask);
@@ -425,7 +428,7 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
         out.grid = grid;
         out.block = 256;
         int64_t r = 0;
-        int64_t batch = 4;
+        int64_t batch = o.batch_hint > 0 ? o.batch_hint : 8;
         int ev = 2;
         bool done = false;
         // the round after the last allowed one only flags capped instances,
@@ -452,7 +455,9 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
                     break;
                 }
             r += nb;
-            batch = std::min<int64_t>(batch * 2, 64);
+            // speculative rounds after the frontier drains cost a launch
+            // each, host reads cost a round trip: grow the batch moderately
+            batch = std::min<int64_t>(batch * 2, 16);
         }
         if (!done) return fail(GBF_EHIP, "internal: frontier did not drain after the round cap");
         if (o.profile) {

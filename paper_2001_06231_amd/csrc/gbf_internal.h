@@ -33,7 +33,7 @@ struct Inst {
 
 // Device-side solver state shared by all instances of one solve.
 struct Run {
-    uint32_t* bits[2];          // dirty-pair bitmaps (frontiers F1/F2)
+    uint8_t* dirty[2];          // dirty-pair byte maps (frontiers F1 / F2), 1 = pair is dirty
     uint32_t* list;             // compacted frontier (global pair ids)
     uint32_t* counts;           // frontier size per round [max_rounds + 2]
     unsigned long long* ctr;    // [8]: pair evals, edges, improvements, saturations, expansions, marks
@@ -43,7 +43,7 @@ struct Run {
     int32_t* error;             // persistent mode: barrier timeout flag
     int32_t* result;            // persistent mode: [0] rounds executed
     uint64_t timeout_ticks;     // persistent mode: bound of one barrier wait (device clock ticks)
-    int64_t nwords;             // words per bitmap
+    int64_t nchunks;            // 16-byte chunks per byte map
     int64_t total_pairs;
     int64_t max_rounds;         // global cap (max over instances)
     int32_t ninst;

@@ -36,8 +36,10 @@ struct Acc {
 // touch the same slot, so no atomics (and no contention) are needed.
 constexpr int kCtrSlot = 8;
 
+constexpr int kMaxWavesPerBlock = 16;
+
 __device__ __forceinline__ void flush_acc(const Acc& a, unsigned long long* slots) {
-    __shared__ unsigned long long s_acc[kWavesPerBlock][6];
+    __shared__ unsigned long long s_acc[kMaxWavesPerBlock][6];
     const unsigned long long v[6] = {a.pairs, a.edges, a.impr, a.sat, a.expanded, a.marks};
     const int w = threadIdx.x / kWave;
 #pragma unroll
@@ -48,8 +50,8 @@ __device__ __forceinline__ void flush_acc(const Acc& a, unsigned long long* slot
     __syncthreads();
     if (threadIdx.x < 6) {
         unsigned long long t = 0;
-#pragma unroll
-        for (int k = 0; k < kWavesPerBlock; ++k) t += s_acc[k][threadIdx.x];
+        const int nw = blockDim.x / kWave;
+        for (int k = 0; k < nw; ++k) t += s_acc[k][threadIdx.x];
         if (t) slots[blockIdx.x * kCtrSlot + threadIdx.x] += t;
     }
 }
@@ -411,27 +413,16 @@ hipError_t launch_init(const Inst* dI, const Inst& I, int dtype, hipStream_t s) 
 }
 
 // ------------------------------------------------------------------ expand
-// Marks a set of dirty pairs in a bitmap.  Lanes hold pair ids q (ascending
-// within the wave when the reverse rows are sorted); lanes whose q fall in
-// the same 32-bit word are combined first (segmented OR over the run), so
-// one atomicOr per word and wave suffices.  A relaxed read skips words whose
-// bits are all set already (bits are only ever set within a round).
-__device__ __forceinline__ void mark_pairs(uint32_t* __restrict__ bits, uint32_t q, bool valid) {
-    const int lane = lane_id();
-    const uint32_t w = valid ? (q >> 5) : 0xffffffffu;
-    uint32_t m = valid ? (1u << (q & 31)) : 0u;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t om = __shfl_up(m, d, kWave);
-        const uint32_t ow = __shfl_up(w, d, kWave);
-        if (lane >= d && ow == w) m |= om;
-    }
-    const uint32_t wn = __shfl_down(w, 1, kWave);
-    if (valid && (lane == kWave - 1 || wn != w)) {
-        GBF_GLOBAL uint32_t* word = gp(bits) + w;
-        // plain read: a stale word only has fewer bits set, never more
-        const uint32_t cur = *word;
-        if ((cur & m) != m) __hip_atomic_fetch_or(word, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Marks a pair dirty in the upcoming frontier: one byte per pair, set with a
+// plain store.  Marking is idempotent, so no read-modify-write is needed; on
+// this multi-XCD device every device-scope atomic executes at the memory
+// side (it bypasses L2), while a byte store is write-combined in L2 and
+// merged by byte mask on write-back.  A plain read skips pairs already
+// marked (a stale read only misses marks, never invents them).
+__device__ __forceinline__ void mark_pair(uint8_t* __restrict__ dirty, uint32_t q, bool valid) {
+    if (valid) {
+        GBF_GLOBAL uint8_t* b = gp(dirty) + q;
+        if (*b == 0) *b = 1;
     }
 }
 
@@ -440,7 +431,7 @@ __device__ __forceinline__ void mark_pairs(uint32_t* __restrict__ bits, uint32_t
 // of y is streamed by the wave.  BOX: for every input the predecessor
 // window is streamed and each candidate's box is decoded to filter it.
 template <int ENC>
-__device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint32_t* __restrict__ bits, Acc& acc) {
+__device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint8_t* __restrict__ dirty, Acc& acc) {
     const int lane = lane_id();
     const uint32_t base = (uint32_t)I.pair_base;
     if (ENC == 1 || (ENC == 3 && I.enc == 0)) {
@@ -455,7 +446,7 @@ __device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint32_t*
             const uint32_t t = t0 + (uint32_t)lane;
             const bool v = t < len;
             const uint32_t q = v ? base + rev[s0 + t] : 0u;
-            mark_pairs(bits, q, v);
+            mark_pair(dirty, q, v);
         }
         return;
     }
@@ -511,7 +502,7 @@ __device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint32_t*
                     q = base + (uint32_t)qq;
                 }
             }
-            mark_pairs(bits, q, hit);
+            mark_pair(dirty, q, hit);
         }
     }
 }
@@ -534,45 +525,59 @@ __global__ __launch_bounds__(kBlock) void k_seed(const Inst* __restrict__ It, in
             while (bal) {
                 const int l = __ffsll(bal) - 1;
                 bal &= bal - 1;
-                expand_state<ENC>(I, w * kWave + l, R.bits[0], acc);
+                expand_state<ENC>(I, w * kWave + l, R.dirty[0], acc);
             }
         }
     }
 }
 
 // ------------------------------------------------------------------ compact
-// One tile = kBlock bitmap words.  Each thread owns one word; a block scan
-// of the popcounts places the set bits (ascending within the tile) after a
-// single global atomicAdd per tile.  Words are cleared as they are read.
-__device__ __forceinline__ void compact_tile(uint32_t* __restrict__ bits, int64_t nwords, int64_t tile,
+// One tile = NB chunks of 16 bytes of the dirty byte map.  Each thread turns
+// its chunk into a 16-bit mask of dirty pairs; a block-wide scan of the mask
+// popcounts (wave prefix sums staged in LDS) places the pair ids, ascending
+// within the tile, after a single global atomicAdd per tile.  Chunks are
+// cleared as they are read.
+__device__ __forceinline__ uint32_t nonzero_bytes4(uint32_t w) {
+    const uint32_t hb = (((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w) & 0x80808080u;
+    return ((hb >> 7) & 1u) | ((hb >> 14) & 2u) | ((hb >> 21) & 4u) | ((hb >> 28) & 8u);
+}
+
+template <int NB>
+__device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_t nchunks, int64_t tile,
                                              uint32_t* __restrict__ list, uint32_t* cnt, int* s_w, uint32_t* s_base) {
     const int t = threadIdx.x;
-    const int64_t wi = tile * kBlock + t;
-    uint32_t word = wi < nwords ? gp(bits)[wi] : 0u;
-    const int c = __popc(word);
+    const int64_t ci = tile * NB + t;
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    GBF_GLOBAL u32x4* chunks = reinterpret_cast<GBF_GLOBAL u32x4*>(gp(dirty));
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (ci < nchunks) v = chunks[ci];
+    uint32_t mask = nonzero_bytes4(v.x) | (nonzero_bytes4(v.y) << 4) | (nonzero_bytes4(v.z) << 8) |
+                    (nonzero_bytes4(v.w) << 12);
+    const int c = __popc(mask);
     const int incl = wave_incl_scan(c);
     const int w = t / kWave;
     if (lane_id() == kWave - 1) s_w[w] = incl;
     __syncthreads();
     int wofs = 0, tot = 0;
 #pragma unroll
-    for (int k = 0; k < kWavesPerBlock; ++k) {
-        const int v = s_w[k];
-        wofs += k < w ? v : 0;
-        tot += v;
+    for (int k = 0; k < NB / kWave; ++k) {
+        const int vv = s_w[k];
+        wofs += k < w ? vv : 0;
+        tot += vv;
     }
     if (tot != 0) {
         if (t == 0) *s_base = atomicAdd(cnt, (uint32_t)tot);
         __syncthreads();
         uint32_t pos = *s_base + (uint32_t)(wofs + incl - c);
-        if (word) {
-            gp(bits)[wi] = 0u;
-            const uint32_t bitbase = (uint32_t)(wi * 32);
+        if (mask) {
+            const u32x4 zero = {0u, 0u, 0u, 0u};
+            chunks[ci] = zero;
+            const uint32_t base = (uint32_t)(ci * 16);
             GBF_GLOBAL uint32_t* out = gp(list);
-            while (word) {
-                const int b = __ffs(word) - 1;
-                out[pos++] = bitbase + (uint32_t)b;
-                word &= word - 1u;
+            while (mask) {
+                const int b = __ffs(mask) - 1;
+                out[pos++] = base + (uint32_t)b;
+                mask &= mask - 1u;
             }
         }
     }
@@ -583,14 +588,14 @@ __global__ __launch_bounds__(kBlock) void k_compact(Run R, int round) {
     __shared__ int s_w[kWavesPerBlock];
     __shared__ uint32_t s_base;
     if (round > 0 && R.counts[round - 1] == 0) return;  // frontier already empty
-    uint32_t* bits = R.bits[round & 1];
-    const int64_t ntiles = (R.nwords + kBlock - 1) / kBlock;
+    uint8_t* cur = R.dirty[round & 1];
+    const int64_t ntiles = (R.nchunks + kBlock - 1) / kBlock;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-        compact_tile(bits, R.nwords, tile, R.list, R.counts + round, s_w, &s_base);
+        compact_tile<kBlock>(cur, R.nchunks, tile, R.list, R.counts + round, s_w, &s_base);
 }
 
 hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s) {
-    const int64_t ntiles = (R.nwords + kBlock - 1) / kBlock;
+    const int64_t ntiles = (R.nchunks + kBlock - 1) / kBlock;
     int g = (int)std::min<int64_t>(ntiles, grid > 0 ? grid : 2048);
     if (g < 1) g = 1;
     k_compact<<<g, kBlock, 0, s>>>(R, round);
@@ -610,34 +615,64 @@ __device__ __forceinline__ typename T::key_t group_max(typename T::key_t v) {
     return v;
 }
 
-template <class T, bool MULTI, int ENC, int G>
-__device__ __forceinline__ void relax_wave(const Inst* __restrict__ It, const int64_t* bases, const Run& R,
-                                           uint32_t count, uint32_t first, int round, uint32_t* __restrict__ next,
-                                           Acc& acc) {
-    using K = typename T::key_t;
-    const int lane = lane_id();
-    const int sub = lane & (G - 1);
-    const uint32_t i = first + (uint32_t)(lane / G);
-    bool valid = i < count;
-    const uint32_t q = valid ? gp(R.list)[i] : 0u;
-    const int ii = find_inst<MULTI>(bases, R.ninst, (int64_t)q);
-    const Inst& I = It[ii];
-    const uint32_t p = q - (MULTI ? (uint32_t)I.pair_base : 0u);
-    if (valid && round >= I.max_rounds) {
+// Per-lane view of the listed pair that a lane group works on.
+struct PairCtx {
+    uint32_t s0, len;  // CSR row of the pair (BOX: unused)
+    uint32_t p;        // instance-local pair id
+    int ii;            // instance
+    bool valid;
+};
+
+template <bool MULTI, int ENC, int G>
+__device__ __forceinline__ PairCtx load_pair(const Inst* __restrict__ It, const int64_t* bases, const Run& R,
+                                             uint32_t count, uint32_t first, int round) {
+    PairCtx c;
+    const int sub = lane_id() & (G - 1);
+    const uint32_t i = first + (uint32_t)(lane_id() / G);
+    c.valid = i < count;
+    const uint32_t q = c.valid ? gp(R.list)[i] : 0u;
+    c.ii = find_inst<MULTI>(bases, R.ninst, (int64_t)q);
+    const Inst& I = It[c.ii];
+    c.p = q - (MULTI ? (uint32_t)I.pair_base : 0u);
+    if (c.valid && round >= I.max_rounds) {
         // the instance's round cap (second condition of Algorithm 1's while
         // loop) is reached with work left: drop the pair, flag the instance
-        if (sub == 0) R.inst_status[ii] = 1;
-        valid = false;
+        if (sub == 0) R.inst_status[c.ii] = 1;
+        c.valid = false;
     }
+    c.s0 = 0;
+    c.len = 0;
+    if (c.valid && (ENC == 1 || (ENC == 3 && I.enc == 0))) {
+        const GBF_GLOBAL uint32_t* sptr = gp(I.sptr);
+        c.s0 = sptr[c.p];
+        c.len = sptr[c.p + 1] - c.s0;
+    }
+    return c;
+}
+
+// Relaxes the pairs of one wave step (64/G pairs, G lanes each).
+template <class T, bool MULTI, int ENC, int G>
+__device__ __forceinline__ void relax_pairs(const Inst* __restrict__ It, const PairCtx& c, int round,
+                                            uint8_t* __restrict__ next, Acc& acc) {
+    using K = typename T::key_t;
+    constexpr int W = kWave / G;
+    const int lane = lane_id();
+    const int sub = lane & (G - 1);
+    const int grp = lane / G;
+    const Inst& I = It[c.ii];
     GBF_GLOBAL K* V = gp(static_cast<K*>(I.V));
+    const uint32_t x = c.p / (uint32_t)I.K;
+    K cur = (K)T::INF;
+    int32_t graw = 0;
+    if (c.valid) {
+        cur = V[x];
+        graw = gp(I.g)[c.p];
+    }
     K mx = (K)T::LOWEST;
-    uint32_t len = 0;
-    if (valid) {
+    uint32_t len = c.len;
+    if (c.valid) {
         if (ENC == 1 || (ENC == 3 && I.enc == 0)) {
-            const GBF_GLOBAL uint32_t* sptr = gp(I.sptr);
-            const uint32_t s0 = sptr[p];
-            len = sptr[p + 1] - s0;
-            const GBF_GLOBAL int32_t* row = gp(I.sidx) + s0;
+            const GBF_GLOBAL int32_t* row = gp(I.sidx) + c.s0;
             uint32_t t = (uint32_t)sub;
             for (; t + G < len; t += 2 * G) {
                 const int32_t y0 = row[t], y1 = row[t + G];
@@ -646,7 +681,7 @@ __device__ __forceinline__ void relax_wave(const Inst* __restrict__ It, const in
             }
             if (t < len) mx = T::max2(mx, V[row[t]]);
         } else {
-            const BoxDec d = decode_box(gp(I.box)[p]);
+            const BoxDec d = decode_box(gp(I.box)[c.p]);
             const uint32_t w0 = d.e[0] + 1, w1 = d.e[1] + 1, w2 = d.e[2] + 1;
             const uint32_t lo = (uint32_t)d.lo, st1 = (uint32_t)I.strides[1], st2 = (uint32_t)I.strides[2],
                            st3 = (uint32_t)I.strides[3];
@@ -663,38 +698,50 @@ __device__ __forceinline__ void relax_wave(const Inst* __restrict__ It, const in
         }
     }
     mx = group_max<T, G>(mx);
-    bool improved = false;
-    uint32_t x = 0;
-    if (valid && sub == 0) {
-        acc.pairs += 1;
-        acc.edges += len;
-        x = p / (uint32_t)I.K;
-        K d;
+    // candidate value of this pair (INF if it cannot improve V(x))
+    K d = (K)T::INF;
+    if (c.valid) {
         int sat = 0;
-        if (T::backup(gp(I.g)[p], mx, d, sat)) {
+        K dd;
+        if (T::backup(graw, mx, dd, sat) && T::less(dd, cur)) d = dd;
+        if (sub == 0) {
+            acc.pairs += 1;
+            acc.edges += len;
             acc.sat += (unsigned)sat;
-            // plain read first: a stale V(x) is only ever too large
-            const K cur = V[x];
-            if (T::less(d, cur)) {
-                const K old = T::amin(V + x, d);
-                if (T::less(d, old)) {
-                    improved = true;
-                    acc.impr += 1;
-                }
-            }
         }
     }
-    // one expansion per state and round suffices: the pairs it marks read
-    // V(x) again in the next round, after every update of this round
-    const bool expand =
-        improved && (__hip_atomic_exchange(gp(I.stamp) + x, round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != round);
+    // The pairs of one state are adjacent in the (ascending) list: take the
+    // min over the run of groups with the same state so that one atomic and
+    // one expansion per state and wave step suffice.
+    const uint32_t key = c.valid ? x : 0xffffffffu;
+    const int ikey = c.valid ? c.ii : -1;
+#pragma unroll
+    for (int st = 1; st < W; st <<= 1) {
+        const K od = __shfl_down(d, st * G, kWave);
+        const uint32_t ok = __shfl_down(key, st * G, kWave);
+        const int oi = MULTI ? __shfl_down(ikey, st * G, kWave) : ikey;
+        if (grp + st < W && ok == key && oi == ikey) d = T::less(od, d) ? od : d;
+    }
+    const uint32_t pkey = __shfl_up(key, G, kWave);
+    const int pi = MULTI ? __shfl_up(ikey, G, kWave) : ikey;
+    const bool head = c.valid && sub == 0 && (grp == 0 || pkey != key || pi != ikey);
+    // strict improvement (Algorithm 1: d < W(x)): a non-returning atomicMin;
+    // the plain read above decided that it lowers V(x) (if a concurrent
+    // update lowered it further, the expansion below is redundant, never
+    // wrong: marks are idempotent)
+    bool expand = false;
+    if (head && T::less(d, cur)) {
+        __hip_atomic_fetch_min(V + x, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        acc.impr += 1;
+        expand = true;
+    }
     unsigned long long bal = __ballot(expand);
     while (bal) {
         const int l = __ffsll(bal) - 1;
         bal &= bal - 1;
         const uint32_t xl = __shfl(x, l, kWave);
         if (MULTI) {
-            const int il = __shfl(ii, l, kWave);
+            const int il = __shfl(c.ii, l, kWave);
             expand_state<ENC>(It[il], xl, next, acc);
         } else {
             expand_state<ENC>(It[0], xl, next, acc);
@@ -706,11 +753,25 @@ template <class T, bool MULTI, int ENC, int G>
 __device__ __forceinline__ void relax_round(const Inst* __restrict__ It, const int64_t* bases, const Run& R,
                                             uint32_t count, int round, Acc& acc) {
     constexpr uint32_t W = kWave / G;  // pairs per wave and step
-    uint32_t* next = R.bits[(round + 1) & 1];
-    const uint32_t wave = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-    for (uint32_t first = wave * W; first < count; first += nwaves * W)
-        relax_wave<T, MULTI, ENC, G>(It, bases, R, count, first, round, next, acc);
+    uint8_t* next = R.dirty[(round + 1) & 1];
+    const uint32_t wpb = blockDim.x / kWave;
+    const uint32_t wave = blockIdx.x * wpb + threadIdx.x / kWave;
+    const uint32_t stride = gridDim.x * wpb * W;
+    uint32_t first = wave * W;
+    if (first >= count) return;
+    PairCtx c = load_pair<MULTI, ENC, G>(It, bases, R, count, first, round);
+    while (true) {
+        const uint32_t nf = first + stride;
+        // software pipelining: the next step's list entry and row bounds
+        // are loaded before this step's successor rows
+        PairCtx n;
+        const bool more = nf < count;
+        if (more) n = load_pair<MULTI, ENC, G>(It, bases, R, count, nf, round);
+        relax_pairs<T, MULTI, ENC, G>(It, c, round, next, acc);
+        if (!more) break;
+        c = n;
+        first = nf;
+    }
 }
 
 template <class T, bool MULTI, int ENC, int G>
@@ -734,9 +795,11 @@ __global__ __launch_bounds__(kBlock) void k_relax(const Inst* __restrict__ It, R
 // start after an error leave at once).
 __device__ __forceinline__ bool grid_barrier(uint32_t* bar, int32_t* err, uint32_t nblocks, uint64_t timeout_ticks) {
     __shared__ int s_ok;
-    __threadfence();
+    // the block barrier completes every wave's stores; one agent-scope
+    // fence per block (not per wave) then publishes them device-wide
     __syncthreads();
     if (threadIdx.x == 0) {
+        __threadfence();
         int ok = 1;
         const uint32_t gen = __hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -757,16 +820,18 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* bar, int32_t* err, uint32
         }
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
         s_ok = ok;
+        __threadfence();
     }
     __syncthreads();
-    __threadfence();
     return s_ok != 0;
 }
 
+constexpr int kPBlock = 1024;  // persistent kernel: one 16-wave block per CU
+
 template <class T, bool MULTI, int ENC, int G>
-__global__ __launch_bounds__(kBlock) void k_persistent(const Inst* __restrict__ It, Run R) {
+__global__ __launch_bounds__(kPBlock) void k_persistent(const Inst* __restrict__ It, Run R) {
     __shared__ int64_t s_bases[MULTI ? kMaxBatch : 1];
-    __shared__ int s_w[kWavesPerBlock];
+    __shared__ int s_w[kPBlock / kWave];
     __shared__ uint32_t s_base;
     if (MULTI) {
         for (int k = threadIdx.x; k < R.ninst; k += blockDim.x) s_bases[k] = It[k].pair_base;
@@ -774,11 +839,11 @@ __global__ __launch_bounds__(kBlock) void k_persistent(const Inst* __restrict__ 
     }
     if (__hip_atomic_load(R.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
     Acc acc;
-    const int64_t ntiles = (R.nwords + kBlock - 1) / kBlock;
+    const int64_t ntiles = (R.nchunks + kPBlock - 1) / kPBlock;
     for (int round = 0;; ++round) {
-        uint32_t* cur = R.bits[round & 1];
+        uint8_t* cur = R.dirty[round & 1];
         for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            compact_tile(cur, R.nwords, tile, R.list, R.counts + round, s_w, &s_base);
+            compact_tile<kPBlock>(cur, R.nchunks, tile, R.list, R.counts + round, s_w, &s_base);
         if (!grid_barrier(R.barrier, R.error, gridDim.x, R.timeout_ticks)) break;
         const uint32_t count = __hip_atomic_load(R.counts + round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (count == 0) {
@@ -801,6 +866,8 @@ using SeedFn = void (*)(const Inst*, int, Run);
 template <class T, bool MULTI, int ENC>
 static void pick(int G, RelaxFn* rf, PersistFn* pf) {
     switch (G) {
+        case 1: *rf = k_relax<T, MULTI, ENC, 1>; *pf = k_persistent<T, MULTI, ENC, 1>; break;
+        case 2: *rf = k_relax<T, MULTI, ENC, 2>; *pf = k_persistent<T, MULTI, ENC, 2>; break;
         case 4: *rf = k_relax<T, MULTI, ENC, 4>; *pf = k_persistent<T, MULTI, ENC, 4>; break;
         case 16: *rf = k_relax<T, MULTI, ENC, 16>; *pf = k_persistent<T, MULTI, ENC, 16>; break;
         case 32: *rf = k_relax<T, MULTI, ENC, 32>; *pf = k_persistent<T, MULTI, ENC, 32>; break;
@@ -849,7 +916,7 @@ int persistent_blocks_per_cu(const Run& R, int lanes, int dtype, int enc_mask) {
     PersistFn pf;
     pick_all(R, dtype, enc_mask, lanes, &rf, &pf);
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(pf), kBlock, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(pf), kPBlock, 0) !=
         hipSuccess)
         return 0;
     return nb;
@@ -863,7 +930,7 @@ hipError_t launch_persistent(const Inst* dI, const Run& R, int grid, int lanes, 
     Run r = R;
     const Inst* di = dI;
     void* args[] = {(void*)&di, (void*)&r};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(pf), dim3(grid), dim3(kBlock), args, 0, s);
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(pf), dim3(grid), dim3(kPBlock), args, 0, s);
 }
 
 // ------------------------------------------------------------------ outputs

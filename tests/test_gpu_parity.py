@@ -121,14 +121,15 @@ def test_grid2d_64x64(grid2d, encoding, mode):
     _assert_exact(prob, ref, _gpu_solve(prob, encoding, mode), f"grid2d-{encoding}-{mode}")
 
 
-@pytest.mark.parametrize("grid", [1, 3, 64, 2048])
-def test_grid2d_launch_shapes(grid2d, grid):
-    """Results do not depend on the number of blocks (a race would show as a
-    launch-shape dependence)."""
+@pytest.mark.parametrize("grid,lanes", [(1, 1), (3, 2), (64, 4), (2048, 8), (4096, 16), (512, 32)])
+def test_grid2d_launch_shapes(grid2d, grid, lanes):
+    """Results do not depend on the number of blocks or lanes per pair (a
+    race would show as a launch-shape dependence)."""
     prob, ref = grid2d
-    _case(f"grid2d grid={grid}")
-    _assert_exact(prob, ref, _gpu_solve(prob, "csr", "hostloop", grid=grid), f"grid{grid}")
-    _assert_exact(prob, ref, _gpu_solve(prob, "csr", "persistent", grid=grid), f"pgrid{grid}")
+    _case(f"grid2d grid={grid} lanes={lanes}")
+    for enc in ("csr", "box"):
+        _assert_exact(prob, ref, _gpu_solve(prob, enc, "hostloop", grid=grid, lanes=lanes), f"grid{grid}")
+        _assert_exact(prob, ref, _gpu_solve(prob, enc, "persistent", grid=grid, lanes=lanes), f"pgrid{grid}")
 
 
 @pytest.mark.parametrize("encoding", ["csr", "box"])
@@ -151,6 +152,13 @@ def test_grid4d_40x40x24x10_int32(grid4d_full, encoding, mode):
     prob, ref = grid4d_full
     _case(f"grid4d 40x40x24x10 int32 {encoding} {mode}")
     _assert_exact(prob, ref, _gpu_solve(prob, encoding, mode), f"grid4d-{encoding}-{mode}")
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 8, 32])
+def test_grid4d_40x40x24x10_lanes(grid4d_full, lanes):
+    prob, ref = grid4d_full
+    _case(f"grid4d 40x40x24x10 int32 csr lanes={lanes}")
+    _assert_exact(prob, ref, _gpu_solve(prob, "csr", "hostloop", lanes=lanes, grid=4096), f"lanes{lanes}")
 
 
 @pytest.fixture(scope="module")
