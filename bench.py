@@ -1,18 +1,24 @@
 """Benchmark of the generalized Bellman-Ford solver on one MI355X.
 
 One step = one full pass of the hot path on device-resident inputs: solve
-(initialise W <- G, seed the frontier, all frontier rounds until it drains)
-plus extraction of the canonical controller with its fixed-point residual.
-Workload: the 4-D UAV-style grid 40x40x24x10 (384,000 cells), 12 inputs,
-int32 potential-form costs, explicit successor lists (CSR).
+(initialise W <- G, seed the frontier, every frontier round until it drains:
+compact, relax, expand) plus extraction of the canonical controller with its
+fixed-point residual.  Workload: the 4-D UAV-style grid 40x40x24x10
+(384,000 cells), 12 inputs, int32 potential-form costs, explicit successor
+lists (CSR).
 
 Prints ONE JSON line.  `value` = edge relaxations (sum of |F(x,u)| over the
 pairs the GPU evaluated) per second of step time.  `roofline` is for the
-dominant kernel (the persistent round kernel), with its algorithmic bytes
-divided by its HIP-event duration measured inside the timed steps.
-`cpu_baseline` is the single-threaded CPU oracle on the same instance.
+dominant kernel (the relax kernel in host-loop mode, the round kernel in
+persistent mode): its algorithmic bytes per launch divided by its average
+launch duration, both measured inside the timed steps with HIP events on the
+solver's stream.  `traffic` is the measured HBM bytes per launch of that
+kernel from the committed rocprofv3 counter summary, if the kernel source is
+unchanged since it was taken.  `cpu_baseline` is the single-threaded CPU
+oracle on the same instance.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,18 +30,45 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "edge relaxations/sec + solve time, 4D 384k-cell graph; learned/batched vs plain"
+KERNEL_SRC = os.path.join(ROOT, "paper_2001_06231_amd", "csrc", "gbf_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "relax_traffic_grid4d_384k.txt")
 
 
-def algorithmic_bytes(st, npairs, mode):
-    """Bytes the method must move (not cache behaviour), per solve:
-    relax (CSR) 20 B per evaluated pair + 8 B per edge (index + value);
-    expand 8 B per expanded state + 8 B per predecessor pair marked;
-    compact (persistent kernel only) npairs/4 B per round (bitmap read and
-    clear) + 4 B per listed pair."""
-    b = 20 * st["pair_evals"] + 8 * st["edge_relax"] + 8 * st["expansions"] + 8 * st["marks"]
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes(st, npairs, mode, rounds):
+    """Bytes the method must move per solve (not cache behaviour):
+    relax (CSR): 20 B per evaluated pair (list id 4, row bounds 8, cost 4,
+    W(x) 4) + 8 B per edge (successor index 4, W(y) 4);
+    expand: 8 B per expanded state (reverse-row bounds) + 5 B per marked
+    predecessor pair (reverse entry 4, dirty byte 1);
+    compact (part of the persistent round kernel only): the dirty byte map
+    is read once per round (npairs B) + 4 B per listed pair."""
+    b = 20 * st["pair_evals"] + 8 * st["edge_relax"] + 8 * st["expansions"] + 5 * st["marks"]
     if mode == "persistent":
-        b += (st["rounds"] + 1) * npairs / 4 + 4 * st["pair_evals"]
+        b += (rounds + 1) * npairs + 4 * st["pair_evals"]
     return b
+
+
+def read_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if it is missing or was taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash() or kv.get("kernel") != kernel:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def run(args):
@@ -52,6 +85,13 @@ def run(args):
     gen_s = time.time() - t0
     print(f"[bench] generated {prob.name}: n={prob.n} pairs={prob.npairs} m={prob.m} in {gen_s:.1f}s",
           file=sys.stderr, flush=True)
+    if args.calib_copy:
+        # a plain 256 MiB device copy: reference for the HBM byte counters
+        x = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     t0 = time.time()
     graph = gbf.load_problem(prob, encoding="csr", stream=stream)
     torch.cuda.synchronize()
@@ -60,7 +100,7 @@ def run(args):
     pol = torch.empty(prob.n, dtype=torch.int32, device="cuda")
 
     def step():
-        status, st, _ = graph.solve(V, mode=args.mode, profile=True)
+        status, st, _ = graph.solve(V, mode=args.mode, lanes=args.lanes, grid=args.grid, profile=True)
         _, res = graph.policy(pol)
         if status != gbf.OK or res != 0:
             raise RuntimeError(f"solve failed: status={status} residual={res}")
@@ -79,13 +119,14 @@ def run(args):
 
     ms_per_step = 1e3 * elapsed / args.steps
     edges = float(np.mean([s["edge_relax"] for s in stats]))
-    solve_ms = float(np.median([s["solve_ms"] for s in stats]))
     mode_used = "persistent" if stats[0]["mode_used"] == gbf.MODE_PERSISTENT else "hostloop"
-    kern_ms = sum(s["relax_ms"] for s in stats) / max(1, sum(s["relax_launches"] for s in stats))
-    bytes_per_launch = float(np.mean([algorithmic_bytes(s, prob.npairs, mode_used) for s in stats]))
-    if mode_used == "hostloop":
-        bytes_per_launch /= max(1.0, np.mean([s["relax_launches"] for s in stats]))
+    kernel = "k_persistent" if mode_used == "persistent" else "k_relax"
+    launches = sum(s["relax_launches"] for s in stats)
+    kern_ms = sum(s["relax_ms"] for s in stats) / max(1, launches)
+    total_bytes = sum(algorithmic_bytes(s, prob.npairs, mode_used, s["rounds"]) for s in stats)
+    bytes_per_launch = total_bytes / max(1, launches)
     achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
+    traffic = read_traffic(kernel)
     out = {
         "metric": METRIC,
         "value": edges / (ms_per_step * 1e-3),
@@ -105,25 +146,28 @@ def run(args):
             "n_states": prob.n, "pairs": prob.npairs, "edges_m": prob.m,
             "parallelism": "single GPU",
         },
-        "solve_ms": solve_ms,
-        "rounds": int(stats[0]["rounds"]),
+        "solve_ms": float(np.median([s["solve_ms"] for s in stats])),
+        "rounds": int(np.median([s["rounds"] for s in stats])),
         "edge_relax_per_solve": edges,
         "pair_evals_per_solve": float(np.mean([s["pair_evals"] for s in stats])),
         "mode": mode_used,
+        "lanes": int(stats[0]["lanes_used"]),
         "grid": int(stats[0]["grid_used"]),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_persistent" if mode_used == "persistent" else "k_relax",
+            "kernel": kernel,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel_ms": kern_ms,
+            "traffic": traffic,
+            "kernel_avg_ms": kern_ms,
+            "launches_per_step": launches / args.steps,
             "algorithmic_bytes_per_launch": bytes_per_launch,
         },
         "load_s": load_s,
         "device_bytes": int(stats[0]["device_bytes"]),
+        "kernel_source_sha256_16": kernel_source_hash(),
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_reps)
@@ -143,8 +187,8 @@ def cpu_baseline(prob, reps):
         edges.append(r["counters"]["edge_relax"])
     t = float(np.median(times))
     return {"value": float(np.median(edges)) / t, "unit": "edge_relaxations/s", "cores": 1, "kind": "oracle",
-            "sample": f"the full 4-D 384k-cell instance, {reps} single-threaded solves (median); "
-                      "oracle counts its own relaxations (state frontier x all inputs)",
+            "sample": f"the full 4-D 384k-cell instance, {reps} single-threaded solves (median); the oracle "
+                      "counts its own relaxations (state frontier x all inputs)",
             "solve_s": t}
 
 
@@ -153,9 +197,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="persistent", choices=["persistent", "hostloop", "auto"])
+    ap.add_argument("--mode", default="auto", choices=["persistent", "hostloop", "auto"])
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--calib-copy", action="store_true", help="run a 256 MiB device copy first (counter reference)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver has no multi-GPU "

@@ -390,7 +390,10 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
             if (mode == GBF_MODE_PERSISTENT) return fail(GBF_EHIP, "occupancy query failed");
             mode = GBF_MODE_HOSTLOOP;
         } else if (mode == GBF_MODE_AUTO) {
-            mode = GBF_MODE_PERSISTENT;
+            // measured on MI355X: one launch pair per round beats the
+            // cooperative kernel for single instances (its grid barriers
+            // write back and invalidate L2); batches use the persistent form
+            mode = ninst > 1 ? GBF_MODE_PERSISTENT : GBF_MODE_HOSTLOOP;
         }
     }
     int32_t* host = (int32_t*)S.host;
@@ -424,7 +427,7 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
             out.relax_launches = 1;
         }
     } else {
-        const int grid = o.grid > 0 ? std::min(o.grid, kMaxGrid) : 4 * cus;
+        const int grid = o.grid > 0 ? std::min(o.grid, kMaxGrid) : 8 * cus;
         out.grid = grid;
         out.block = 256;
         int64_t r = 0;
