@@ -104,6 +104,12 @@ typedef struct gbf_problem {
      * derives from the boxes (a superset of pred, allowed by Sect. V-B). */
     int32_t dims[4];
     const uint64_t* box; /* [n*K] */
+    /* GBF_BOX only: 1 = expand the boxes into explicit successor lists on the
+     * device at load time and solve with those (faster, ~8 bytes per
+     * successor more memory); 0 = keep the implicit encoding (Sect. IV-B:
+     * keeping images of F and pred in memory vs recomputing them). */
+    int32_t expand_box;
+    int32_t reserved[3];
 } gbf_problem;
 
 /* ---- solve options --------------------------------------------------- */
@@ -142,7 +148,8 @@ typedef struct gbf_stats {
     int32_t grid_used;
     int32_t block_used;
     int32_t lanes_used;
-    int32_t reserved[2];
+    int32_t graph_used;     /* 1 = batched solve replayed from a HIP graph */
+    int32_t reserved[1];
 } gbf_stats;
 
 typedef struct gbf_graph gbf_graph;

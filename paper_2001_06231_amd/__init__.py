@@ -45,7 +45,8 @@ class _Problem(ctypes.Structure):
     _fields_ = [("n_states", ctypes.c_int64), ("n_inputs", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("encoding", ctypes.c_int32), ("memspace", ctypes.c_int32), ("G", ctypes.c_void_p),
                 ("g", ctypes.c_void_p), ("avoid", ctypes.c_void_p), ("succ_ptr", ctypes.c_void_p),
-                ("succ_idx", ctypes.c_void_p), ("dims", ctypes.c_int32 * 4), ("box", ctypes.c_void_p)]
+                ("succ_idx", ctypes.c_void_p), ("dims", ctypes.c_int32 * 4), ("box", ctypes.c_void_p),
+                ("expand_box", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class _Opts(ctypes.Structure):
@@ -63,7 +64,7 @@ class _Stats(ctypes.Structure):
                 ("solve_ms", ctypes.c_double), ("relax_ms", ctypes.c_double),
                 ("relax_launches", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("mode_used", ctypes.c_int32), ("grid_used", ctypes.c_int32), ("block_used", ctypes.c_int32),
-                ("lanes_used", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("lanes_used", ctypes.c_int32), ("graph_used", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
     def as_dict(self):
         return {k: (getattr(self, k) if k != "reserved" else None) for k, _ in self._fields_ if k != "reserved"}
@@ -197,7 +198,7 @@ class Graph:
 
 
 def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=None, succ_idx=None,
-               dims=None, box=None, stream=None) -> Graph:
+               dims=None, box=None, expand_box=False, stream=None) -> Graph:
     """gbf_load_graph.  Arrays are numpy (host) or torch tensors on the GPU
     (all of one kind).  G/g are int32 or float32 bit patterns."""
     L = lib()
@@ -231,6 +232,7 @@ def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=
         d = list(dims) + [1] * (4 - len(dims))
         for a in range(4):
             p.dims[a] = int(d[a])
+        p.expand_box = 1 if expand_box else 0
     if len(spaces) > 1:
         raise ValueError("problem arrays must all be host arrays or all device tensors")
     p.memspace = spaces.pop() if spaces else HOST
@@ -243,7 +245,12 @@ def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=
 
 def load_problem(prob, encoding="csr", stream=None) -> Graph:
     """Loads an object with the fields of an optimal control problem
-    (n, K, dtype, G, g, avoid, succ_ptr/succ_idx or dims/box_packed())."""
+    (n, K, dtype, G, g, avoid, succ_ptr/succ_idx or dims/box_packed()).
+    encoding: "csr" (explicit lists; expanded from the boxes on the device
+    when the object carries no lists), "box" (implicit) or "box->csr"."""
+    if encoding == "box->csr" or (encoding == "csr" and getattr(prob, "succ_ptr", None) is None):
+        return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="box", avoid=prob.avoid,
+                          dims=prob.dims, box=prob.box_packed(), expand_box=True, stream=stream)
     if encoding == "csr":
         return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="csr", avoid=prob.avoid,
                           succ_ptr=prob.succ_ptr, succ_idx=prob.succ_idx, stream=stream)

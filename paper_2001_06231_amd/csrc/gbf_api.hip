@@ -263,8 +263,41 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
         return fail(GBF_EINVAL, msg);
     }
 
-    if (p->encoding == GBF_CSR) {
-        HIPC(launch_convert_ptr(sptr64, const_cast<uint32_t*>(I.sptr), np + 1, s));
+    if (p->encoding == GBF_BOX && p->expand_box) {
+        // materialise F as successor lists on the device (then as CSR below)
+        uint32_t *sizes, *sptr, *tmp;
+        unsigned long long* tot64;
+        const int64_t nb = (np + 1023) / 1024 + 1;
+        if ((rc = M.alloc((void**)&sizes, (np + 1) * 4)) || (rc = M.alloc((void**)&sptr, (np + 1) * 4)) ||
+            (rc = M.alloc((void**)&tmp, nb * 4)) || (rc = M.alloc((void**)&tot64, 8)))
+            return rc;
+        HIPC(hipMemsetAsync(tot64, 0, 8, s));
+        HIPC(launch_box_sizes(I, sizes, tot64, s));
+        unsigned long long total64 = 0;
+        HIPC(hipMemcpyAsync(&total64, tot64, 8, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        // exact 64-bit total first: the 32-bit scan below must not wrap
+        if (total64 >= (1ull << 31))
+            return fail(GBF_EINVAL, "expanded successor lists must hold < 2^31 entries");
+        HIPC(launch_scan(sizes, sptr, np, tmp, s));
+        const uint32_t mtot = (uint32_t)total64;
+        int32_t* sidx;
+        if ((rc = M.alloc((void**)&sidx, (size_t)mtot * 4))) return rc;
+        HIPC(launch_box_fill(I, sptr, sidx, s));
+        M.release(sizes, (np + 1) * 4);
+        M.release(tmp, nb * 4);
+        M.release(tot64, 8);
+        M.release((void*)I.box, np * 8);
+        I.box = nullptr;
+        I.sptr = sptr;
+        I.sidx = sidx;
+        I.enc = GBF_CSR;
+        gr->enc = GBF_CSR;
+        gr->m = mtot;
+        m = mtot;
+    }
+    if (I.enc == GBF_CSR) {
+        if (sptr64) HIPC(launch_convert_ptr(sptr64, const_cast<uint32_t*>(I.sptr), np + 1, s));
         HIPC(launch_prune(I, p->dtype, s));
         uint32_t *cnt, *rptr, *tmp, *rev;
         const int64_t nb = (n + 1023) / 1024 + 1;
@@ -284,7 +317,7 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
         I.rptr = rptr;
         I.rev = rev;
         HIPC(hipStreamSynchronize(s));
-        M.release(sptr64, (np + 1) * 8);
+        if (sptr64) M.release(sptr64, (np + 1) * 8);
         M.release(cnt, (n + 1) * 4);
         M.release(tmp, nb * 4);
     } else {
@@ -321,29 +354,33 @@ struct SolveOut {
     unsigned long long ctr[6] = {0, 0, 0, 0, 0, 0};
     double solve_ms = 0, relax_ms = 0;
     int64_t relax_launches = 0;
-    int mode = 0, grid = 0, block = 0, lanes = 0;
+    int mode = 0, grid = 0, block = 0, lanes = 0, graph = 0;
     std::vector<int32_t> inst_status;
 };
 
-// Runs the frontier iteration over `insts` (already initialised device
-// table `S.dinst`).  Host-loop mode: compact + relax per round, the host reads
-// the per-round frontier sizes in growing batches.  Persistent mode: one
-// cooperative launch runs every round with grid barriers.
-static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, const gbf_opts& o, hipStream_t s,
-                      int cus, int clock_khz, SolveOut& out) {
-    const int ninst = (int)insts.size();
-    int64_t total_pairs = 0, max_rounds = 0, max_states = 0;
-    int enc_mask = 0;
+// Everything needed to enqueue one solve over a table of instances.
+struct Plan {
+    Run R{};
+    int ninst = 0;
+    int64_t max_rounds = 0, max_states = 0;
+    int enc_mask = 0, lanes = 4, mode = GBF_MODE_HOSTLOOP, grid = 0, dtype = 0;
+};
+
+static int plan_solve(Scratch& S, const std::vector<Inst>& insts, int dtype, const gbf_opts& o, int cus,
+                      int clock_khz, Plan& P) {
+    P.ninst = (int)insts.size();
+    P.dtype = dtype;
+    int64_t total_pairs = 0;
     for (const Inst& I : insts) {
         total_pairs = std::max<int64_t>(total_pairs, I.pair_base + I.n * I.K);
-        max_rounds = std::max<int64_t>(max_rounds, I.max_rounds);
-        max_states = std::max<int64_t>(max_states, I.n);
-        enc_mask |= I.enc == 0 ? 1 : 2;
+        P.max_rounds = std::max<int64_t>(P.max_rounds, I.max_rounds);
+        P.max_states = std::max<int64_t>(P.max_states, I.n);
+        P.enc_mask |= I.enc == 0 ? 1 : 2;
     }
-    const int nevents = o.profile ? 2 * (int)std::min<int64_t>(max_rounds + 2, 4096) + 2 : 2;
-    int rc = ensure_scratch(S, total_pairs, max_rounds, ninst, nevents);
+    const int nevents = o.profile ? 2 * (int)std::min<int64_t>(P.max_rounds + 2, 4096) + 2 : 4;
+    int rc = ensure_scratch(S, total_pairs, P.max_rounds, P.ninst, nevents);
     if (rc) return rc;
-    Run R{};
+    Run& R = P.R;
     R.dirty[0] = S.dirty[0];
     R.dirty[1] = S.dirty[1];
     R.list = S.list;
@@ -356,60 +393,146 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
     R.result = S.result;
     R.nchunks = (total_pairs + 15) / 16;
     R.total_pairs = total_pairs;
-    R.max_rounds = max_rounds;
-    R.ninst = ninst;
+    R.max_rounds = P.max_rounds;
+    R.ninst = P.ninst;
     R.dtype = dtype;
     // a single barrier wait longer than 250 ms means the blocks are not
     // co-resident (or the device is stuck): give up instead of hanging
     R.timeout_ticks = (uint64_t)clock_khz * 250;
+    P.lanes = (o.lanes == 1 || o.lanes == 2 || o.lanes == 4 || o.lanes == 8 || o.lanes == 16 || o.lanes == 32)
+                  ? o.lanes
+                  : 4;
+    P.mode = o.mode;
+    if (P.mode != GBF_MODE_HOSTLOOP) {
+        const int per_cu = persistent_blocks_per_cu(R, P.lanes, dtype, P.enc_mask);
+        if (per_cu <= 0) {
+            if (P.mode == GBF_MODE_PERSISTENT) return fail(GBF_EHIP, "occupancy query failed");
+            P.mode = GBF_MODE_HOSTLOOP;
+        } else {
+            if (P.mode == GBF_MODE_AUTO) {
+                // measured on MI355X: one launch pair per round beats the
+                // cooperative kernel for single instances (its grid barriers
+                // write back and invalidate L2); batches use the persistent
+                // form, which can be captured in a HIP graph
+                P.mode = P.ninst > 1 ? GBF_MODE_PERSISTENT : GBF_MODE_HOSTLOOP;
+            }
+            // co-residency is required; stay below the occupancy limit
+            const int cap = std::min(per_cu, kPersistentBlocksPerCU) * cus;
+            P.grid = o.grid > 0 ? std::min(o.grid, cap) : cap;
+        }
+    }
+    if (P.mode == GBF_MODE_HOSTLOOP) P.grid = o.grid > 0 ? std::min(o.grid, kMaxGrid) : 8 * cus;
+    return GBF_OK;
+}
 
-    HIPC(hipEventRecord(S.events[0], s));
-    HIPC(hipMemcpyAsync(S.dinst, insts.data(), sizeof(Inst) * ninst, hipMemcpyHostToDevice, s));
+// Fills, W <- G, seed.  Kernels only (no memset), so it can be captured.
+static int enqueue_init(Scratch& S, const Plan& P, const std::vector<Inst>& insts, hipStream_t s) {
+    const Run& R = P.R;
     HIPC(launch_fill_u32((uint32_t*)R.dirty[0], 0, R.nchunks * 4, s));
     HIPC(launch_fill_u32((uint32_t*)R.dirty[1], 0, R.nchunks * 4, s));
-    HIPC(launch_fill_u32(R.counts, 0, max_rounds + 2, s));
+    HIPC(launch_fill_u32(R.counts, 0, P.max_rounds + 2, s));
     HIPC(launch_fill_u32((uint32_t*)R.ctr, 0, 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.slots, 0, (int64_t)kMaxGrid * 16, s));
-    HIPC(launch_fill_u32((uint32_t*)R.inst_status, 0, ninst, s));
+    HIPC(launch_fill_u32((uint32_t*)R.inst_status, 0, P.ninst, s));
     HIPC(launch_fill_u32(R.barrier, 0, 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.error, 0, 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.result, 0, 16, s));
-    for (const Inst& I : insts) HIPC(launch_init(S.dinst, I, dtype, s));
-    HIPC(launch_seed(S.dinst, ninst, R, max_states, dtype, enc_mask, s));
+    for (const Inst& I : insts) HIPC(launch_init(S.dinst, I, P.dtype, s));
+    HIPC(launch_seed(S.dinst, P.ninst, R, P.max_states, P.dtype, P.enc_mask, s));
+    return GBF_OK;
+}
 
-    int mode = o.mode;
-    int per_cu = 0;
-    const int lanes = (o.lanes == 1 || o.lanes == 2 || o.lanes == 4 || o.lanes == 8 || o.lanes == 16 ||
-                       o.lanes == 32)
-                          ? o.lanes
-                          : 4;
-    out.lanes = lanes;
-    if (mode != GBF_MODE_HOSTLOOP) {
-        per_cu = persistent_blocks_per_cu(R, lanes, dtype, enc_mask);
-        if (per_cu <= 0) {
-            if (mode == GBF_MODE_PERSISTENT) return fail(GBF_EHIP, "occupancy query failed");
-            mode = GBF_MODE_HOSTLOOP;
-        } else if (mode == GBF_MODE_AUTO) {
-            // measured on MI355X: one launch pair per round beats the
-            // cooperative kernel for single instances (its grid barriers
-            // write back and invalidate L2); batches use the persistent form
-            mode = ninst > 1 ? GBF_MODE_PERSISTENT : GBF_MODE_HOSTLOOP;
+// Statistics reduction and read-back of the status words into pinned host
+// memory (all capturable).  Layout of S.host: [0] rounds, [1] barrier error,
+// [16..27] counters (6 x u64), [64..] per-instance status.
+static int enqueue_readback(Scratch& S, const Plan& P, hipStream_t s) {
+    int32_t* host = (int32_t*)S.host;
+    HIPC(launch_sum_slots(S.slots, kMaxGrid, S.ctr, s));
+    HIPC(hipMemcpyAsync(host, S.result, 4, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(host + 1, S.error, 4, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(host + 16, S.ctr, 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(host + 64, S.inst_status, 4 * P.ninst, hipMemcpyDeviceToHost, s));
+    return GBF_OK;
+}
+
+static void read_host(const Scratch& S, const Plan& P, SolveOut& out, bool rounds_from_host) {
+    const int32_t* host = (const int32_t*)S.host;
+    if (rounds_from_host) out.rounds = host[0];
+    std::memcpy(out.ctr, host + 16, 6 * sizeof(unsigned long long));
+    out.inst_status.assign(P.ninst, 0);
+    for (int i = 0; i < P.ninst; ++i) out.inst_status[i] = host[64 + i];
+    out.mode = P.mode;
+    out.grid = P.grid;
+    out.block = P.mode == GBF_MODE_PERSISTENT ? 1024 : 256;
+    out.lanes = P.lanes;
+}
+
+// Host-loop rounds: compact + relax per round; the host reads the per-round
+// frontier sizes after each batch of rounds (rounds launched after the
+// frontier drained exit at once).
+static int enqueue_hostloop(Scratch& S, const Plan& P, const gbf_opts& o, hipStream_t s, SolveOut& out) {
+    const Run& R = P.R;
+    int32_t* host = (int32_t*)S.host;
+    int64_t r = 0;
+    int64_t batch = o.batch_hint > 0 ? o.batch_hint : 8;
+    int ev = 2;
+    bool done = false;
+    // the round after the last allowed one only flags capped instances, so a
+    // zero count appears at round max_rounds + 1 at the latest
+    while (!done && r <= P.max_rounds + 1) {
+        const int64_t nb = std::min<int64_t>(batch, P.max_rounds + 2 - r);
+        for (int64_t k = 0; k < nb; ++k) {
+            HIPC(launch_compact(R, (int)(r + k), 0, s));
+            const bool timed = o.profile && ev + 1 < (int)S.events.size();
+            if (timed) HIPC(hipEventRecord(S.events[ev], s));
+            HIPC(launch_relax(S.dinst, R, (int)(r + k), P.grid, P.lanes, P.dtype, P.enc_mask, s));
+            if (timed) {
+                HIPC(hipEventRecord(S.events[ev + 1], s));
+                ev += 2;
+            }
+        }
+        const int64_t nread = std::min<int64_t>(nb, 1000);
+        HIPC(hipMemcpyAsync(host + 256, R.counts + r, nread * 4, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        for (int64_t k = 0; k < nread; ++k)
+            if (host[256 + k] == 0) {
+                out.rounds = r + k;
+                done = true;
+                break;
+            }
+        r += nb;
+        // speculative rounds after the frontier drains cost a launch each,
+        // host reads a round trip: grow the batch moderately
+        batch = std::min<int64_t>(batch * 2, 16);
+    }
+    if (!done) return fail(GBF_EHIP, "internal: frontier did not drain after the round cap");
+    if (o.profile) {
+        for (int e = 2; e < ev; e += 2) {
+            float ms = 0;
+            HIPC(hipEventElapsedTime(&ms, S.events[e], S.events[e + 1]));
+            out.relax_ms += ms;
+            out.relax_launches++;
         }
     }
-    int32_t* host = (int32_t*)S.host;
-    if (mode == GBF_MODE_PERSISTENT) {
-        // co-residency is required; stay below the occupancy limit
-        const int cap = std::min(per_cu, kPersistentBlocksPerCU) * cus;
-        int grid = o.grid > 0 ? std::min(o.grid, cap) : cap;
-        out.grid = grid;
-        out.block = 256;
+    return GBF_OK;
+}
+
+// Runs one solve over `insts`, not captured.
+static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, const gbf_opts& o, hipStream_t s,
+                      int cus, int clock_khz, SolveOut& out) {
+    Plan P;
+    int rc = plan_solve(S, insts, dtype, o, cus, clock_khz, P);
+    if (rc) return rc;
+    HIPC(hipEventRecord(S.events[0], s));
+    HIPC(hipMemcpyAsync(S.dinst, insts.data(), sizeof(Inst) * P.ninst, hipMemcpyHostToDevice, s));
+    if ((rc = enqueue_init(S, P, insts, s))) return rc;
+    if (P.mode == GBF_MODE_PERSISTENT) {
         if (o.profile) HIPC(hipEventRecord(S.events[2], s));
-        HIPC(launch_persistent(S.dinst, R, grid, lanes, dtype, enc_mask, s));
+        HIPC(launch_persistent(S.dinst, P.R, P.grid, P.lanes, dtype, P.enc_mask, false, s));
         if (o.profile) HIPC(hipEventRecord(S.events[3], s));
-        HIPC(hipMemcpyAsync(host, S.result, 4, hipMemcpyDeviceToHost, s));
-        HIPC(hipMemcpyAsync(host + 1, S.error, 4, hipMemcpyDeviceToHost, s));
+        if ((rc = enqueue_readback(S, P, s))) return rc;
         HIPC(hipStreamSynchronize(s));
-        if (host[1] != 0) {
+        if (((int32_t*)S.host)[1] != 0) {
             if (o.mode == GBF_MODE_AUTO) {
                 // retry the whole solve with one launch sequence per round
                 gbf_opts o2 = o;
@@ -419,67 +542,19 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
             }
             return fail(GBF_ETIMEOUT, "grid barrier timed out (blocks not co-resident?)");
         }
-        out.rounds = host[0];
+        read_host(S, P, out, true);
         if (o.profile) {
             float ms = 0;
             HIPC(hipEventElapsedTime(&ms, S.events[2], S.events[3]));
             out.relax_ms = ms;
             out.relax_launches = 1;
         }
-    } else {
-        const int grid = o.grid > 0 ? std::min(o.grid, kMaxGrid) : 8 * cus;
-        out.grid = grid;
-        out.block = 256;
-        int64_t r = 0;
-        int64_t batch = o.batch_hint > 0 ? o.batch_hint : 8;
-        int ev = 2;
-        bool done = false;
-        // the round after the last allowed one only flags capped instances,
-        // so a zero count appears at round max_rounds + 1 at the latest
-        while (!done && r <= max_rounds + 1) {
-            const int64_t nb = std::min<int64_t>(batch, max_rounds + 2 - r);
-            for (int64_t k = 0; k < nb; ++k) {
-                HIPC(launch_compact(R, (int)(r + k), 0, s));
-                const bool timed = o.profile && ev + 1 < (int)S.events.size();
-                if (timed) HIPC(hipEventRecord(S.events[ev], s));
-                HIPC(launch_relax(S.dinst, R, (int)(r + k), grid, lanes, dtype, enc_mask, s));
-                if (timed) {
-                    HIPC(hipEventRecord(S.events[ev + 1], s));
-                    ev += 2;
-                }
-            }
-            const int64_t nread = std::min<int64_t>(nb, 1000);
-            HIPC(hipMemcpyAsync(host, R.counts + r, nread * 4, hipMemcpyDeviceToHost, s));
-            HIPC(hipStreamSynchronize(s));
-            for (int64_t k = 0; k < nread; ++k)
-                if (host[k] == 0) {
-                    out.rounds = r + k;
-                    done = true;
-                    break;
-                }
-            r += nb;
-            // speculative rounds after the frontier drains cost a launch
-            // each, host reads cost a round trip: grow the batch moderately
-            batch = std::min<int64_t>(batch * 2, 16);
-        }
-        if (!done) return fail(GBF_EHIP, "internal: frontier did not drain after the round cap");
-        if (o.profile) {
-            for (int e = 2; e < ev; e += 2) {
-                float ms = 0;
-                HIPC(hipEventElapsedTime(&ms, S.events[e], S.events[e + 1]));
-                out.relax_ms += ms;
-                out.relax_launches++;
-            }
-        }
+        return GBF_OK;
     }
-    out.mode = mode;
-    out.inst_status.assign(ninst, 0);
-    HIPC(launch_sum_slots(S.slots, kMaxGrid, S.ctr, s));
-    HIPC(hipMemcpyAsync(host + 16, S.ctr, 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(host + 64, S.inst_status, 4 * ninst, hipMemcpyDeviceToHost, s));
+    if ((rc = enqueue_hostloop(S, P, o, s, out))) return rc;
+    if ((rc = enqueue_readback(S, P, s))) return rc;
     HIPC(hipStreamSynchronize(s));
-    std::memcpy(out.ctr, host + 16, 6 * sizeof(unsigned long long));
-    for (int i = 0; i < ninst; ++i) out.inst_status[i] = host[64 + i];
+    read_host(S, P, out, false);
     return GBF_OK;
 }
 
@@ -508,6 +583,7 @@ static void fill_stats(gbf_stats* st, int status, const SolveOut& so, int64_t ro
     st->grid_used = so.grid;
     st->block_used = so.block;
     st->lanes_used = so.lanes;
+    st->graph_used = so.graph;
 }
 
 static int write_values(gbf_graph* g, void* V_out, int memspace, hipStream_t s) {
@@ -515,7 +591,7 @@ static int write_values(gbf_graph* g, void* V_out, int memspace, hipStream_t s) 
     if (memspace == GBF_DEVICE) {
         HIPC(launch_decode(g->inst, g->dtype, V_out, s));
     } else {
-        // decode in place into the scratch list buffer, then copy out
+        // decode into the scratch list buffer, then copy out
         HIPC(launch_decode(g->inst, g->dtype, g->scratch.list, s));
         HIPC(hipMemcpyAsync(V_out, g->scratch.list, g->n * 4, hipMemcpyDeviceToHost, s));
     }
@@ -558,7 +634,7 @@ extern "C" int gbf_extract_policy(gbf_graph* g, int32_t* policy_out, int32_t mem
     Scratch& S = g->scratch;
     int rc = ensure_scratch(S, g->n * g->K, 1, 1, 2);
     if (rc) return rc;
-    unsigned long long* bad = S.ctr + 4;
+    unsigned long long* bad = S.ctr + 6;
     HIPC(launch_fill_u32((uint32_t*)bad, 0, 2, s));
     int32_t* dst = memspace == GBF_DEVICE ? policy_out : (int32_t*)S.list;
     HIPC(launch_policy(g->inst, g->dtype, dst, bad, s));
@@ -571,11 +647,59 @@ extern "C" int gbf_extract_policy(gbf_graph* g, int32_t* policy_out, int32_t mem
 }
 
 // ------------------------------------------------------------------ batch
+// A batch context is kept per set of handles: its scratch, its instance
+// table and, for the persistent form with device outputs, a HIP graph of the
+// whole solve (fills, W <- G, seed, the cooperative round kernel, statistics,
+// decode into the outputs, status read-back) that later calls replay.
 struct BatchCtx {
     std::vector<gbf_graph*> graphs;
     Scratch scratch;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t priv = nullptr;  // capture and replay stream (default priority)
+    std::vector<void*> vouts;
+    gbf_opts key_opts{};
+    bool graph_failed = false;
+    ~BatchCtx() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (priv) (void)hipStreamDestroy(priv);
+    }
 };
 static std::map<std::vector<gbf_graph*>, std::unique_ptr<BatchCtx>> g_batches;
+
+static bool same_opts(const gbf_opts& a, const gbf_opts& b) {
+    return a.mode == b.mode && a.max_rounds == b.max_rounds && a.lanes == b.lanes && a.grid == b.grid &&
+           a.v_memspace == b.v_memspace;
+}
+
+static int capture_batch(BatchCtx& ctx, const Plan& P, const std::vector<Inst>& insts, void* const* V_outs,
+                         hipStream_t s) {
+    Scratch& S = ctx.scratch;
+    hipGraph_t graph = nullptr;
+    HIPC(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_init(S, P, insts, s);
+    hipError_t e = hipSuccess;
+    if (!rc) e = launch_persistent(S.dinst, P.R, P.grid, P.lanes, P.dtype, P.enc_mask, true, s);
+    if (!rc && e == hipSuccess) rc = enqueue_readback(S, P, s);
+    if (!rc && e == hipSuccess)
+        for (size_t i = 0; i < insts.size(); ++i)
+            if (V_outs && V_outs[i]) {
+                e = launch_decode(insts[i], P.dtype, V_outs[i], s);
+                if (e != hipSuccess) break;
+            }
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (rc || e != hipSuccess || e2 != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return fail(GBF_EHIP, std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(GBF_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(e));
+    if (ctx.exec) (void)hipGraphExecDestroy(ctx.exec);
+    ctx.exec = exec;
+    return GBF_OK;
+}
 
 extern "C" int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gbf_opts* opts, void* const* V_outs,
                                gbf_stats* st) {
@@ -583,10 +707,12 @@ extern "C" int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gb
     if (count > kMaxBatch) return fail(GBF_EINVAL, "batch larger than " + std::to_string(kMaxBatch));
     gbf_opts o = opts ? *opts : default_opts();
     if (o.order != GBF_ORDER_PLAIN) return fail(GBF_EINVAL, "batched solves use the plain order");
+    if (o.v_memspace != GBF_HOST && o.v_memspace != GBF_DEVICE) return fail(GBF_EINVAL, "bad v_memspace");
+    for (int i = 0; i < count; ++i)
+        if (!graphs[i]) return fail(GBF_EINVAL, "NULL graph in batch");
     const int dtype = graphs[0]->dtype;
     hipStream_t s = graphs[0]->stream;
     for (int i = 0; i < count; ++i) {
-        if (!graphs[i]) return fail(GBF_EINVAL, "NULL graph in batch");
         if (graphs[i]->dtype != dtype) return fail(GBF_EINVAL, "batch mixes value types");
         if (graphs[i]->stream != s || graphs[i]->device != graphs[0]->device)
             return fail(GBF_EINVAL, "batch spans streams or devices");
@@ -609,32 +735,78 @@ extern "C" int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gb
         graphs[i]->solved = false;
     }
     if (base >= ((int64_t)1 << 32)) return fail(GBF_EINVAL, "batch has >= 2^32 pairs");
+    Scratch& S = ctx->scratch;
     SolveOut so;
-    int rc = run_rounds(ctx->scratch, insts, dtype, o, s, graphs[0]->cus, graphs[0]->clock_khz, so);
+    Plan P;
+    int rc = plan_solve(S, insts, dtype, o, graphs[0]->cus, graphs[0]->clock_khz, P);
     if (rc) return rc;
-    for (int i = 0; i < count; ++i) {
-        if (!V_outs || !V_outs[i]) continue;
-        if (o.v_memspace == GBF_DEVICE) {
-            HIPC(launch_decode(insts[i], dtype, V_outs[i], s));
-        } else {
-            HIPC(launch_decode(insts[i], dtype, ctx->scratch.list, s));
-            HIPC(hipMemcpyAsync(V_outs[i], ctx->scratch.list, insts[i].n * 4, hipMemcpyDeviceToHost, s));
+    const bool graphable = P.mode == GBF_MODE_PERSISTENT && o.v_memspace == GBF_DEVICE && !o.profile;
+    bool replayed = false;
+    if (graphable && !ctx->graph_failed && !ctx->priv) {
+        // the caller's stream may be the legacy default stream, which cannot
+        // be captured: capture and replay on a stream of our own
+        if (hipStreamCreateWithFlags(&ctx->priv, hipStreamNonBlocking) != hipSuccess) {
+            ctx->priv = nullptr;
+            ctx->graph_failed = true;
         }
     }
-    HIPC(hipEventRecord(ctx->scratch.events[1], s));
-    HIPC(hipEventSynchronize(ctx->scratch.events[1]));
+    if (graphable && !ctx->graph_failed) {
+        hipStream_t gs = ctx->priv;
+        // inputs and outputs are ordered on the caller's stream
+        HIPC(hipStreamSynchronize(s));
+        std::vector<void*> vo(V_outs ? V_outs : nullptr, V_outs ? V_outs + count : nullptr);
+        const bool fresh = !ctx->exec || vo != ctx->vouts || !same_opts(o, ctx->key_opts);
+        if (fresh) {
+            HIPC(hipMemcpyAsync(S.dinst, insts.data(), sizeof(Inst) * count, hipMemcpyHostToDevice, gs));
+            HIPC(hipStreamSynchronize(gs));
+            if (capture_batch(*ctx, P, insts, V_outs, gs) != GBF_OK) {
+                ctx->graph_failed = true;  // fall back to direct launches
+                (void)hipGetLastError();
+            } else {
+                ctx->vouts = vo;
+                ctx->key_opts = o;
+            }
+        }
+        if (!ctx->graph_failed) {
+            HIPC(hipEventRecord(S.events[0], gs));
+            HIPC(hipGraphLaunch(ctx->exec, gs));
+            HIPC(hipEventRecord(S.events[1], gs));
+            HIPC(hipStreamSynchronize(gs));
+            if (((int32_t*)S.host)[1] != 0) {
+                if (o.mode != GBF_MODE_AUTO) return fail(GBF_ETIMEOUT, "grid barrier timed out");
+            } else {
+                read_host(S, P, so, true);
+                so.graph = 1;
+                replayed = true;
+            }
+        }
+    }
+    if (!replayed) {
+        gbf_opts o2 = o;
+        if (graphable && o.mode == GBF_MODE_AUTO && ((int32_t*)S.host)[1] != 0) o2.mode = GBF_MODE_HOSTLOOP;
+        rc = run_rounds(S, insts, dtype, o2, s, graphs[0]->cus, graphs[0]->clock_khz, so);
+        if (rc) return rc;
+        for (int i = 0; i < count; ++i) {
+            if (!V_outs || !V_outs[i]) continue;
+            if (o.v_memspace == GBF_DEVICE) {
+                HIPC(launch_decode(insts[i], dtype, V_outs[i], s));
+            } else {
+                HIPC(launch_decode(insts[i], dtype, S.list, s));
+                HIPC(hipMemcpyAsync(V_outs[i], S.list, insts[i].n * 4, hipMemcpyDeviceToHost, s));
+            }
+        }
+        HIPC(hipEventRecord(S.events[1], s));
+        HIPC(hipEventSynchronize(S.events[1]));
+    }
     float ms = 0;
-    HIPC(hipEventElapsedTime(&ms, ctx->scratch.events[0], ctx->scratch.events[1]));
+    HIPC(hipEventElapsedTime(&ms, S.events[0], S.events[1]));
     so.solve_ms = ms;
     int worst = GBF_OK;
     for (int i = 0; i < count; ++i) {
         const int status = so.inst_status[i] ? GBF_ENEGCYCLE : GBF_OK;
         if (status != GBF_OK) worst = status;
         graphs[i]->solved = true;
-        if (st) {
-            SolveOut si = so;
-            fill_stats(st + i, status, si, insts[i].max_rounds, graphs[i]->mem.bytes);
-        }
+        if (st) fill_stats(st + i, status, so, insts[i].max_rounds, graphs[i]->mem.bytes);
     }
     if (worst != GBF_OK) fail(worst, "round cap reached in some instance");
     return worst;

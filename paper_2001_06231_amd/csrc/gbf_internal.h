@@ -63,6 +63,8 @@ hipError_t launch_rev_count(const Inst& I, uint32_t* cnt, hipStream_t s);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t s);
 hipError_t launch_rev_fill(const Inst& I, uint32_t* cursor, uint32_t* rev, hipStream_t s);
 hipError_t launch_box_window(const Inst& I, int32_t* win32, hipStream_t s);
+hipError_t launch_box_sizes(const Inst& I, uint32_t* sizes, unsigned long long* total, hipStream_t s);
+hipError_t launch_box_fill(const Inst& I, const uint32_t* sptr, int32_t* sidx, hipStream_t s);
 
 hipError_t launch_init(const Inst* dI, const Inst& I, int dtype, hipStream_t s);
 hipError_t launch_seed(const Inst* dI, int ninst, const Run& R, int64_t max_states, int dtype, int enc_mask,
@@ -71,8 +73,10 @@ hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s);
 // `lanes`: lanes per listed pair in the relax step (4, 8, 16 or 32)
 hipError_t launch_relax(const Inst* dI, const Run& R, int round, int grid, int lanes, int dtype, int enc_mask,
                         hipStream_t s);
+// `attr_launch`: launch through hipLaunchKernelExC with the cooperative
+// attribute (the form that stream capture records as a graph node)
 hipError_t launch_persistent(const Inst* dI, const Run& R, int grid, int lanes, int dtype, int enc_mask,
-                             hipStream_t s);
+                             bool attr_launch, hipStream_t s);
 int persistent_blocks_per_cu(const Run& R, int lanes, int dtype, int enc_mask);
 hipError_t launch_sum_slots(const unsigned long long* slots, int nslots, unsigned long long* ctr, hipStream_t s);
 hipError_t launch_sort_rows(const uint32_t* rptr, uint32_t* rev, int64_t n, hipStream_t s);

@@ -19,10 +19,29 @@
 // maximal fixed point (Sect. IV-A: the processing order is irrelevant; the
 // operator is monotone and every pair is re-evaluated after its last
 // successor change).
+#include <cstring>
+
 #include "gbf_device.h"
 #include "gbf_internal.h"
 
+// Compile-time tuning knobs (measured defaults).
+#ifndef GBF_NT_ROWS
+#define GBF_NT_ROWS 0  // streaming (non-temporal) loads for successor rows
+#endif
+#ifndef GBF_NT_MISC
+#define GBF_NT_MISC 0  // ... for list entries, row bounds, costs, reverse rows
+#endif
+#ifndef GBF_COMPACT_C
+#define GBF_COMPACT_C 1
+#endif
+
 namespace gbf {
+
+template <bool NT, class P>
+__device__ __forceinline__ P ldx(const GBF_GLOBAL P* p) {
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
@@ -393,6 +412,46 @@ hipError_t launch_box_window(const Inst& I, int32_t* win32, hipStream_t s) {
     return hipGetLastError();
 }
 
+// BOX -> CSR on the device: sizes, then (after a scan) each pair writes its
+// box's cells in ascending linear order.
+__global__ void k_box_sizes(Inst I, uint32_t* sizes, unsigned long long* total) {
+    const int64_t npairs = I.n * I.K;
+    unsigned long long acc = 0;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npairs; p += (int64_t)gridDim.x * blockDim.x) {
+        const BoxDec d = decode_box(I.box[p]);
+        const unsigned long long k = (unsigned long long)(d.e[0] + 1) * (d.e[1] + 1) * (d.e[2] + 1) * (d.e[3] + 1);
+        sizes[p] = (uint32_t)(k > 0xffffffffull ? 0xffffffffull : k);
+        acc += k;
+    }
+    acc = wave_sum64(acc);
+    if (lane_id() == 0 && acc) atomicAdd(total, acc);
+}
+
+hipError_t launch_box_sizes(const Inst& I, uint32_t* sizes, unsigned long long* total, hipStream_t s) {
+    k_box_sizes<<<grid_for(I.n * I.K, 256, 1024), 256, 0, s>>>(I, sizes, total);
+    return hipGetLastError();
+}
+
+__global__ void k_box_fill(Inst I, const uint32_t* sptr, int32_t* sidx) {
+    const int64_t npairs = I.n * I.K;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npairs; p += (int64_t)gridDim.x * blockDim.x) {
+        const BoxDec d = decode_box(I.box[p]);
+        uint32_t pos = sptr[p];
+        for (int j3 = 0; j3 <= d.e[3]; ++j3)
+            for (int j2 = 0; j2 <= d.e[2]; ++j2)
+                for (int j1 = 0; j1 <= d.e[1]; ++j1) {
+                    const int64_t r0 = d.lo + (int64_t)j1 * I.strides[1] + (int64_t)j2 * I.strides[2] +
+                                       (int64_t)j3 * I.strides[3];
+                    for (int j0 = 0; j0 <= d.e[0]; ++j0) sidx[pos++] = (int32_t)(r0 + j0);
+                }
+    }
+}
+
+hipError_t launch_box_fill(const Inst& I, const uint32_t* sptr, int32_t* sidx, hipStream_t s) {
+    k_box_fill<<<grid_for(I.n * I.K, 256), 256, 0, s>>>(I, sptr, sidx);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ init
 // W <- G (Algorithm 1 initialisation), avoid cells pinned to INF; stamps
 // cleared.
@@ -445,7 +504,7 @@ __device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint8_t* 
         for (uint32_t t0 = 0; t0 < len; t0 += kWave) {
             const uint32_t t = t0 + (uint32_t)lane;
             const bool v = t < len;
-            const uint32_t q = v ? base + rev[s0 + t] : 0u;
+            const uint32_t q = v ? base + ldx<GBF_NT_MISC>(rev + s0 + t) : 0u;
             mark_pair(dirty, q, v);
         }
         return;
@@ -542,60 +601,87 @@ __device__ __forceinline__ uint32_t nonzero_bytes4(uint32_t w) {
     return ((hb >> 7) & 1u) | ((hb >> 14) & 2u) | ((hb >> 21) & 4u) | ((hb >> 28) & 8u);
 }
 
-template <int NB>
-__device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_t nchunks, int64_t tile,
+// A super-tile is C consecutive tiles of NB chunks: the counts of all C
+// tiles are scanned first, then one global atomicAdd reserves the whole
+// super-tile's slots (device-scope atomics execute at the memory side and
+// serialise on the single counter, so fewer is better), then the ids are
+// written in ascending order.
+template <int NB, int C>
+__device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_t nchunks, int64_t stile,
                                              uint32_t* __restrict__ list, uint32_t* cnt, int* s_w, uint32_t* s_base) {
-    const int t = threadIdx.x;
-    const int64_t ci = tile * NB + t;
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-    GBF_GLOBAL u32x4* chunks = reinterpret_cast<GBF_GLOBAL u32x4*>(gp(dirty));
-    u32x4 v = {0u, 0u, 0u, 0u};
-    if (ci < nchunks) v = chunks[ci];
-    uint32_t mask = nonzero_bytes4(v.x) | (nonzero_bytes4(v.y) << 4) | (nonzero_bytes4(v.z) << 8) |
-                    (nonzero_bytes4(v.w) << 12);
-    const int c = __popc(mask);
-    const int incl = wave_incl_scan(c);
+    constexpr int NW = NB / kWave;
+    const int t = threadIdx.x;
     const int w = t / kWave;
-    if (lane_id() == kWave - 1) s_w[w] = incl;
-    __syncthreads();
-    int wofs = 0, tot = 0;
+    GBF_GLOBAL u32x4* chunks = reinterpret_cast<GBF_GLOBAL u32x4*>(gp(dirty));
+    uint32_t mask[C];
+    int loc[C];
 #pragma unroll
-    for (int k = 0; k < NB / kWave; ++k) {
-        const int vv = s_w[k];
-        wofs += k < w ? vv : 0;
-        tot += vv;
+    for (int i = 0; i < C; ++i) {
+        const int64_t ci = (stile * C + i) * NB + t;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (ci < nchunks) v = chunks[ci];
+        mask[i] = nonzero_bytes4(v.x) | (nonzero_bytes4(v.y) << 4) | (nonzero_bytes4(v.z) << 8) |
+                  (nonzero_bytes4(v.w) << 12);
+        const int c = __popc(mask[i]);
+        const int incl = wave_incl_scan(c);
+        loc[i] = incl - c;
+        if (lane_id() == kWave - 1) s_w[i * NW + w] = incl;
     }
-    if (tot != 0) {
-        if (t == 0) *s_base = atomicAdd(cnt, (uint32_t)tot);
+    __syncthreads();
+    int run = 0;
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        int wofs = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int vv = s_w[i * NW + k];
+            wofs += k < w ? vv : 0;
+            tot += vv;
+        }
+        loc[i] += run + wofs;
+        run += tot;
+    }
+    if (run != 0) {
+        if (t == 0) *s_base = atomicAdd(cnt, (uint32_t)run);
         __syncthreads();
-        uint32_t pos = *s_base + (uint32_t)(wofs + incl - c);
-        if (mask) {
-            const u32x4 zero = {0u, 0u, 0u, 0u};
-            chunks[ci] = zero;
-            const uint32_t base = (uint32_t)(ci * 16);
-            GBF_GLOBAL uint32_t* out = gp(list);
-            while (mask) {
-                const int b = __ffs(mask) - 1;
-                out[pos++] = base + (uint32_t)b;
-                mask &= mask - 1u;
+        const uint32_t base = *s_base;
+        GBF_GLOBAL uint32_t* out = gp(list);
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            uint32_t m = mask[i];
+            if (m) {
+                const int64_t ci = (stile * C + i) * NB + t;
+                const u32x4 zero = {0u, 0u, 0u, 0u};
+                chunks[ci] = zero;
+                uint32_t pos = base + (uint32_t)loc[i];
+                const uint32_t pbase = (uint32_t)(ci * 16);
+                while (m) {
+                    const int b = __ffs(m) - 1;
+                    out[pos++] = pbase + (uint32_t)b;
+                    m &= m - 1u;
+                }
             }
         }
     }
     __syncthreads();
 }
 
+constexpr int kCompactC = GBF_COMPACT_C;  // tiles per super-tile, 256-thread blocks
+constexpr int kPCompactC = 2;  // tiles per super-tile, 1024-thread blocks
+
 __global__ __launch_bounds__(kBlock) void k_compact(Run R, int round) {
-    __shared__ int s_w[kWavesPerBlock];
+    __shared__ int s_w[kCompactC * kWavesPerBlock];
     __shared__ uint32_t s_base;
     if (round > 0 && R.counts[round - 1] == 0) return;  // frontier already empty
     uint8_t* cur = R.dirty[round & 1];
-    const int64_t ntiles = (R.nchunks + kBlock - 1) / kBlock;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-        compact_tile<kBlock>(cur, R.nchunks, tile, R.list, R.counts + round, s_w, &s_base);
+    const int64_t nst = (R.nchunks + kBlock * kCompactC - 1) / (kBlock * kCompactC);
+    for (int64_t st = blockIdx.x; st < nst; st += gridDim.x)
+        compact_tile<kBlock, kCompactC>(cur, R.nchunks, st, R.list, R.counts + round, s_w, &s_base);
 }
 
 hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s) {
-    const int64_t ntiles = (R.nchunks + kBlock - 1) / kBlock;
+    const int64_t ntiles = (R.nchunks + kBlock * kCompactC - 1) / (kBlock * kCompactC);
     int g = (int)std::min<int64_t>(ntiles, grid > 0 ? grid : 2048);
     if (g < 1) g = 1;
     k_compact<<<g, kBlock, 0, s>>>(R, round);
@@ -630,7 +716,7 @@ __device__ __forceinline__ PairCtx load_pair(const Inst* __restrict__ It, const 
     const int sub = lane_id() & (G - 1);
     const uint32_t i = first + (uint32_t)(lane_id() / G);
     c.valid = i < count;
-    const uint32_t q = c.valid ? gp(R.list)[i] : 0u;
+    const uint32_t q = c.valid ? ldx<GBF_NT_MISC>(gp(R.list) + i) : 0u;
     c.ii = find_inst<MULTI>(bases, R.ninst, (int64_t)q);
     const Inst& I = It[c.ii];
     c.p = q - (MULTI ? (uint32_t)I.pair_base : 0u);
@@ -644,8 +730,8 @@ __device__ __forceinline__ PairCtx load_pair(const Inst* __restrict__ It, const 
     c.len = 0;
     if (c.valid && (ENC == 1 || (ENC == 3 && I.enc == 0))) {
         const GBF_GLOBAL uint32_t* sptr = gp(I.sptr);
-        c.s0 = sptr[c.p];
-        c.len = sptr[c.p + 1] - c.s0;
+        c.s0 = ldx<GBF_NT_MISC>(sptr + c.p);
+        c.len = ldx<GBF_NT_MISC>(sptr + c.p + 1) - c.s0;
     }
     return c;
 }
@@ -666,7 +752,7 @@ __device__ __forceinline__ void relax_pairs(const Inst* __restrict__ It, const P
     int32_t graw = 0;
     if (c.valid) {
         cur = V[x];
-        graw = gp(I.g)[c.p];
+        graw = ldx<GBF_NT_MISC>(gp(I.g) + c.p);
     }
     K mx = (K)T::LOWEST;
     uint32_t len = c.len;
@@ -675,13 +761,13 @@ __device__ __forceinline__ void relax_pairs(const Inst* __restrict__ It, const P
             const GBF_GLOBAL int32_t* row = gp(I.sidx) + c.s0;
             uint32_t t = (uint32_t)sub;
             for (; t + G < len; t += 2 * G) {
-                const int32_t y0 = row[t], y1 = row[t + G];
+                const int32_t y0 = ldx<GBF_NT_ROWS>(row + t), y1 = ldx<GBF_NT_ROWS>(row + t + G);
                 const K v0 = V[y0], v1 = V[y1];
                 mx = T::max2(mx, T::max2(v0, v1));
             }
-            if (t < len) mx = T::max2(mx, V[row[t]]);
+            if (t < len) mx = T::max2(mx, V[ldx<GBF_NT_ROWS>(row + t)]);
         } else {
-            const BoxDec d = decode_box(gp(I.box)[c.p]);
+            const BoxDec d = decode_box(ldx<GBF_NT_MISC>(gp(I.box) + c.p));
             const uint32_t w0 = d.e[0] + 1, w1 = d.e[1] + 1, w2 = d.e[2] + 1;
             const uint32_t lo = (uint32_t)d.lo, st1 = (uint32_t)I.strides[1], st2 = (uint32_t)I.strides[2],
                            st3 = (uint32_t)I.strides[3];
@@ -831,7 +917,7 @@ constexpr int kPBlock = 1024;  // persistent kernel: one 16-wave block per CU
 template <class T, bool MULTI, int ENC, int G>
 __global__ __launch_bounds__(kPBlock) void k_persistent(const Inst* __restrict__ It, Run R) {
     __shared__ int64_t s_bases[MULTI ? kMaxBatch : 1];
-    __shared__ int s_w[kPBlock / kWave];
+    __shared__ int s_w[kPCompactC * (kPBlock / kWave)];
     __shared__ uint32_t s_base;
     if (MULTI) {
         for (int k = threadIdx.x; k < R.ninst; k += blockDim.x) s_bases[k] = It[k].pair_base;
@@ -839,11 +925,11 @@ __global__ __launch_bounds__(kPBlock) void k_persistent(const Inst* __restrict__
     }
     if (__hip_atomic_load(R.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
     Acc acc;
-    const int64_t ntiles = (R.nchunks + kPBlock - 1) / kPBlock;
+    const int64_t ntiles = (R.nchunks + kPBlock * kPCompactC - 1) / (kPBlock * kPCompactC);
     for (int round = 0;; ++round) {
         uint8_t* cur = R.dirty[round & 1];
         for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            compact_tile<kPBlock>(cur, R.nchunks, tile, R.list, R.counts + round, s_w, &s_base);
+            compact_tile<kPBlock, kPCompactC>(cur, R.nchunks, tile, R.list, R.counts + round, s_w, &s_base);
         if (!grid_barrier(R.barrier, R.error, gridDim.x, R.timeout_ticks)) break;
         const uint32_t count = __hip_atomic_load(R.counts + round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (count == 0) {
@@ -923,13 +1009,28 @@ int persistent_blocks_per_cu(const Run& R, int lanes, int dtype, int enc_mask) {
 }
 
 hipError_t launch_persistent(const Inst* dI, const Run& R, int grid, int lanes, int dtype, int enc_mask,
-                             hipStream_t s) {
+                             bool attr_launch, hipStream_t s) {
     RelaxFn rf;
     PersistFn pf;
     pick_all(R, dtype, enc_mask, lanes, &rf, &pf);
     Run r = R;
     const Inst* di = dI;
     void* args[] = {(void*)&di, (void*)&r};
+    if (attr_launch) {
+        hipLaunchAttribute attr;
+        std::memset(&attr, 0, sizeof(attr));
+        attr.id = hipLaunchAttributeCooperative;
+        attr.val.cooperative = 1;
+        hipLaunchConfig_t cfg;
+        std::memset(&cfg, 0, sizeof(cfg));
+        cfg.gridDim = dim3(grid);
+        cfg.blockDim = dim3(kPBlock);
+        cfg.dynamicSmemBytes = 0;
+        cfg.stream = s;
+        cfg.attrs = &attr;
+        cfg.numAttrs = 1;
+        return hipLaunchKernelExC(&cfg, reinterpret_cast<const void*>(pf), args);
+    }
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(pf), dim3(grid), dim3(kPBlock), args, 0, s);
 }
 
@@ -947,17 +1048,93 @@ hipError_t launch_decode(const Inst& I, int dtype, void* out, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Canonical controller and fixed-point residual: per state, one application
-// of P to the final V, scanning inputs in ascending order and keeping the
-// first strict improvement over G (hand over on ties with G).
+// Canonical controller and fixed-point residual: one application of P to
+// the final V.  One lane per pair; a wave holds 64/K whole states, so the
+// scan over a state's inputs (ascending u, first strict improvement over
+// G, hand over on ties with G) reads the K backups from LDS.
+template <class T, int ENC>
+__global__ __launch_bounds__(kBlock) void k_policy(Inst I, int32_t* pol, unsigned long long* bad) {
+    using K = typename T::key_t;
+    __shared__ K s_d[kBlock];
+    const GBF_GLOBAL K* V = gp(static_cast<const K*>(I.V));
+    const int lane = lane_id();
+    const int K_ = I.K;
+    const int spw = kWave / K_;  // whole states per wave
+    const int64_t nsteps = (I.n + spw - 1) / spw;
+    unsigned long long nb = 0;
+    K* sd = s_d + (threadIdx.x / kWave) * kWave;
+    for (int64_t st = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave; st < nsteps;
+         st += (int64_t)gridDim.x * kWavesPerBlock) {
+        const int si = lane / K_, u = lane - si * K_;
+        const int64_t x = st * spw + si;
+        const bool valid = si < spw && x < I.n;
+        K d = (K)T::INF;
+        if (valid) {
+            const int64_t p = x * K_ + u;
+            K m = (K)T::LOWEST;
+            if (ENC == 1) {
+                const GBF_GLOBAL uint32_t* sptr = gp(I.sptr);
+                const GBF_GLOBAL int32_t* sidx = gp(I.sidx);
+                const uint32_t e1 = ldx<GBF_NT_MISC>(sptr + p + 1);
+                uint32_t j = ldx<GBF_NT_MISC>(sptr + p);
+                // four independent gathers in flight per lane
+                for (; j + 4 <= e1; j += 4) {
+                    const int32_t y0 = ldx<GBF_NT_ROWS>(sidx + j), y1 = ldx<GBF_NT_ROWS>(sidx + j + 1),
+                                  y2 = ldx<GBF_NT_ROWS>(sidx + j + 2), y3 = ldx<GBF_NT_ROWS>(sidx + j + 3);
+                    m = T::max2(T::max2(m, T::max2(V[y0], V[y1])), T::max2(V[y2], V[y3]));
+                }
+                for (; j < e1; ++j) m = T::max2(m, V[ldx<GBF_NT_ROWS>(sidx + j)]);
+            } else {
+                const BoxDec bd = decode_box(ldx<GBF_NT_MISC>(gp(I.box) + p));
+                for (int j3 = 0; j3 <= bd.e[3]; ++j3)
+                    for (int j2 = 0; j2 <= bd.e[2]; ++j2)
+                        for (int j1 = 0; j1 <= bd.e[1]; ++j1) {
+                            const int64_t r0 = bd.lo + (int64_t)j1 * I.strides[1] + (int64_t)j2 * I.strides[2] +
+                                               (int64_t)j3 * I.strides[3];
+                            for (int j0 = 0; j0 <= bd.e[0]; ++j0) m = T::max2(m, V[r0 + j0]);
+                        }
+            }
+            K dd;
+            int sat = 0;
+            if (T::backup(gp(I.g)[p], m, dd, sat)) d = dd;
+        }
+        sd[lane] = d;
+        wave_sync();
+        if (valid && u == 0) {
+            const K vx = V[x];
+            if (I.avoid[x]) {
+                pol[x] = -2;
+                nb += vx != T::INF;
+            } else {
+                K best = T::from_raw(gp(I.G)[x]);
+                int pu = -1;
+                for (int k = 0; k < K_; ++k) {
+                    const K dk = sd[si * K_ + k];
+                    if (T::less(dk, best)) {
+                        best = dk;
+                        pu = k;
+                    }
+                }
+                if (best == T::INF) pu = -2;
+                pol[x] = pu;
+                nb += best != vx;
+            }
+        }
+        wave_sync();
+    }
+    nb = wave_sum64(nb);
+    if (lane_id() == 0 && nb) atomicAdd(bad, nb);
+}
+
+// States with more than 64 inputs: one thread per state.
 template <class T>
-__global__ void k_policy(Inst I, int32_t* pol, unsigned long long* bad) {
+__global__ void k_policy_wide(Inst I, int32_t* pol, unsigned long long* bad) {
     using K = typename T::key_t;
     const K* V = static_cast<const K*>(I.V);
     unsigned long long nb = 0;
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < I.n; x += (int64_t)gridDim.x * blockDim.x) {
         const K vx = V[x];
-        if (I.avoid && I.avoid[x]) {
+        if (I.avoid[x]) {
             pol[x] = -2;
             nb += vx != T::INF;
             continue;
@@ -994,8 +1171,20 @@ __global__ void k_policy(Inst I, int32_t* pol, unsigned long long* bad) {
 }
 
 hipError_t launch_policy(const Inst& I, int dtype, int32_t* pol, unsigned long long* bad, hipStream_t s) {
-    if (dtype == 1) k_policy<TF32><<<grid_for(I.n, 256), 256, 0, s>>>(I, pol, bad);
-    else k_policy<TI32><<<grid_for(I.n, 256), 256, 0, s>>>(I, pol, bad);
+    if (I.K > kWave) {
+        if (dtype == 1) k_policy_wide<TF32><<<grid_for(I.n, 256), 256, 0, s>>>(I, pol, bad);
+        else k_policy_wide<TI32><<<grid_for(I.n, 256), 256, 0, s>>>(I, pol, bad);
+        return hipGetLastError();
+    }
+    const int64_t steps = (I.n + (kWave / I.K) - 1) / (kWave / I.K);
+    const int grid = grid_for(steps, kWavesPerBlock, 8192);
+    if (dtype == 1) {
+        if (I.enc == 0) k_policy<TF32, 1><<<grid, kBlock, 0, s>>>(I, pol, bad);
+        else k_policy<TF32, 2><<<grid, kBlock, 0, s>>>(I, pol, bad);
+    } else {
+        if (I.enc == 0) k_policy<TI32, 1><<<grid, kBlock, 0, s>>>(I, pol, bad);
+        else k_policy<TI32, 2><<<grid, kBlock, 0, s>>>(I, pol, bad);
+    }
     return hipGetLastError();
 }
 

@@ -170,36 +170,90 @@ def cell_coords(dims) -> np.ndarray:
     return out
 
 
+def _box_shapes(ext: np.ndarray):
+    """Shape id of every box and the list of distinct shapes (w0,w1,w2,w3)."""
+    e = ext.astype(np.int64)
+    emax = e.max(axis=0) + 1 if e.shape[0] else np.ones(4, dtype=np.int64)
+    sid = e[:, 0] + emax[0] * (e[:, 1] + emax[1] * (e[:, 2] + emax[2] * e[:, 3]))
+    return sid, emax
+
+
 def boxes_to_csr(dims, lo: np.ndarray, ext: np.ndarray):
     """Expand boxes into ascending CSR rows (generator-side expansion).
 
     Within a box the cells are listed in ascending linear order, i.e.
-    lexicographically in (j3, j2, j1, j0) with offsets j_a in [0, ext_a]."""
+    lexicographically in (j3, j2, j1, j0) with offsets j_a in [0, ext_a].
+    Pairs are grouped by box shape so that each group is one broadcast."""
     st = strides(dims)
     e = ext.astype(np.int64)
-    w0, w1, w2 = e[:, 0] + 1, e[:, 1] + 1, e[:, 2] + 1
-    sizes = w0 * w1 * w2 * (e[:, 3] + 1)
+    sizes = (e[:, 0] + 1) * (e[:, 1] + 1) * (e[:, 2] + 1) * (e[:, 3] + 1)
     ptr = np.zeros(lo.shape[0] + 1, dtype=np.int64)
     np.cumsum(sizes, out=ptr[1:])
     idx = np.empty(int(ptr[-1]), dtype=np.int32)
-    emax = e.max(axis=0) if e.shape[0] else np.zeros(4, dtype=np.int64)
+    sid, emax = _box_shapes(ext)
+    order = np.argsort(sid, kind="stable")
+    bounds = np.searchsorted(sid[order], np.arange(int(np.prod(emax)) + 1))
     base = lo.astype(np.int64)
-    for j3 in range(emax[3] + 1):
-        for j2 in range(emax[2] + 1):
-            for j1 in range(emax[1] + 1):
-                for j0 in range(emax[0] + 1):
-                    sel = np.nonzero((ext[:, 0] >= j0) & (ext[:, 1] >= j1) &
-                                     (ext[:, 2] >= j2) & (ext[:, 3] >= j3))[0]
-                    rank = j0 + w0[sel] * (j1 + w1[sel] * (j2 + w2[sel] * j3))
-                    off = j0 * st[0] + j1 * st[1] + j2 * st[2] + j3 * st[3]
-                    idx[ptr[sel] + rank] = (base[sel] + off).astype(np.int32)
+    for shape in range(int(np.prod(emax))):
+        sel = order[bounds[shape]:bounds[shape + 1]]
+        if sel.size == 0:
+            continue
+        w0 = shape % emax[0]
+        r = shape // emax[0]
+        w1 = r % emax[1]
+        r //= emax[1]
+        w2 = r % emax[2]
+        w3 = r // emax[2]
+        j3, j2, j1, j0 = np.meshgrid(np.arange(w3 + 1), np.arange(w2 + 1), np.arange(w1 + 1),
+                                     np.arange(w0 + 1), indexing="ij")
+        offs = (j0 * st[0] + j1 * st[1] + j2 * st[2] + j3 * st[3]).reshape(-1)
+        k = offs.size
+        pos = ptr[sel][:, None] + np.arange(k)[None, :]
+        idx[pos.reshape(-1)] = (base[sel][:, None] + offs[None, :]).reshape(-1).astype(np.int32)
     return ptr, idx
 
 
 def box_min(dims, lo: np.ndarray, ext: np.ndarray, field: np.ndarray, csr=None) -> np.ndarray:
-    """min of `field` over each box (input construction only)."""
-    ptr, idx = csr if csr is not None else boxes_to_csr(dims, lo, ext)
-    return np.minimum.reduceat(field[idx], ptr[:-1].astype(np.intp))
+    """min of `field` over each box (input construction only), by separable
+    window minima: for every extent combination the field of minima over
+    [x, x+e] per axis is built once, then each box reads its corner."""
+    if csr is not None:
+        ptr, idx = csr
+        return np.minimum.reduceat(field[idx], ptr[:-1].astype(np.intp))
+    st = strides(dims)
+    f = field.astype(np.float64)
+    n = f.size
+    e = ext.astype(np.int64)
+    emax = e.max(axis=0)
+
+    def window(g, a, w):
+        # min over cells x, x+st_a, ..., x+w*st_a (only read where in range)
+        out = g.copy()
+        for j in range(1, w + 1):
+            sh = np.full(n, np.inf)
+            sh[:n - j * st[a]] = g[j * st[a]:]
+            np.minimum(out, sh, out=out)
+        return out
+
+    out = np.empty(lo.shape[0])
+    lo64 = lo.astype(np.int64)
+    sid, smax = _box_shapes(ext)
+    order = np.argsort(sid, kind="stable")
+    bounds = np.searchsorted(sid[order], np.arange(int(np.prod(smax)) + 1))
+    for e0 in range(emax[0] + 1):
+        f0 = window(f, 0, e0)
+        for e1 in range(emax[1] + 1):
+            f1 = window(f0, 1, e1)
+            for e2 in range(emax[2] + 1):
+                f2 = window(f1, 2, e2)
+                for e3 in range(emax[3] + 1):
+                    shape = e0 + smax[0] * (e1 + smax[1] * (e2 + smax[2] * e3))
+                    sel = order[bounds[shape]:bounds[shape + 1]]
+                    if sel.size == 0:
+                        continue
+                    f3 = window(f2, 3, e3)
+                    out[sel] = f3[lo64[sel]]
+    return out
 
 
 def _gauss_kernel(sigma: float) -> np.ndarray:
@@ -378,8 +432,7 @@ def grid_problem(dims, K: int, ext_probs, *, seed: int, dtype: str = "i32",
         f = (1.0 - tilt_mix) * sm + tilt_mix * ramp
         f = (f - f.min()) / (f.max() - f.min()) * phi_top
         phi = np.rint(f).astype(np.int64) if dtype == "i32" else f
-    csr = boxes_to_csr(dims, lo, ext)
-    mphi = box_min(dims, lo, ext, phi, csr=csr)
+    mphi = box_min(dims, lo, ext, phi)
     phix = np.repeat(phi.astype(np.float64), K)
     if dtype == "i32":
         c = r_c.integers(c_range[0], c_range[1], n * K)
@@ -396,7 +449,7 @@ def grid_problem(dims, K: int, ext_probs, *, seed: int, dtype: str = "i32",
                    box_lo=lo, box_ext=ext, target=tmask, phi=phi, cost_c=c, c_min=c_min,
                    name=name)
     if with_csr:
-        prob.succ_ptr, prob.succ_idx = csr
+        prob.ensure_csr()
     return prob
 
 

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     # sizes of the ABI structs as laid out by the C compiler
-    assert ctypes.sizeof(gbf._Problem) == 8 + 4 * 4 + 8 * 5 + 16 + 8
+    assert ctypes.sizeof(gbf._Problem) == 8 + 4 * 4 + 8 * 5 + 16 + 8 + 16
     assert ctypes.sizeof(gbf._Opts) == 4 * 2 + 8 + 8 + 4 * 4 + 16
     assert ctypes.sizeof(gbf._Stats) % 8 == 0
 
