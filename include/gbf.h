@@ -69,7 +69,7 @@ extern "C" {
 #define GBF_ORDER_PLAIN 0   /* frontier rounds as in Algorithm 1 */
 #define GBF_ORDER_BUCKETS 1 /* frontier drained in ascending bucket key */
 
-#define GBF_MODE_AUTO 0
+#define GBF_MODE_AUTO 0       /* currently the host loop (faster on MI355X) */
 #define GBF_MODE_HOSTLOOP 1   /* one launch sequence per round from the host */
 #define GBF_MODE_PERSISTENT 2 /* all rounds in one cooperative launch */
 
@@ -143,6 +143,7 @@ typedef struct gbf_stats {
     double solve_ms;        /* HIP-event time of the solve on its stream */
     double relax_ms;        /* profile=1: summed time of the relax launches */
     int64_t relax_launches; /* profile=1: number of relax launches timed */
+    double barrier_ms;      /* persistent mode: time block 0 spent in grid barriers */
     int64_t device_bytes;   /* device memory held by the graph handle */
     int32_t mode_used;      /* GBF_MODE_HOSTLOOP or GBF_MODE_PERSISTENT */
     int32_t grid_used;

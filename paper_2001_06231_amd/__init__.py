@@ -62,7 +62,7 @@ class _Stats(ctypes.Structure):
                 ("improvements", ctypes.c_int64), ("saturations", ctypes.c_int64),
                 ("expansions", ctypes.c_int64), ("marks", ctypes.c_int64),
                 ("solve_ms", ctypes.c_double), ("relax_ms", ctypes.c_double),
-                ("relax_launches", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("relax_launches", ctypes.c_int64), ("barrier_ms", ctypes.c_double), ("device_bytes", ctypes.c_int64),
                 ("mode_used", ctypes.c_int32), ("grid_used", ctypes.c_int32), ("block_used", ctypes.c_int32),
                 ("lanes_used", ctypes.c_int32), ("graph_used", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 

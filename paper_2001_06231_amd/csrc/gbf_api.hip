@@ -19,7 +19,10 @@ static thread_local std::string t_err;
 
 // Blocks per CU of the persistent kernel: below the occupancy limit, so that
 // the cooperative grid is co-resident with margin.
-constexpr int kPersistentBlocksPerCU = 1;
+#ifndef GBF_PBLOCKS
+#define GBF_PBLOCKS 2
+#endif
+constexpr int kPersistentBlocksPerCU = GBF_PBLOCKS;
 
 static int fail(int code, const std::string& msg) {
     t_err = msg;
@@ -124,7 +127,7 @@ static int ensure_scratch(Scratch& S, int64_t total_pairs, int64_t max_rounds, i
         int rc;
         if ((rc = S.mem.alloc((void**)&S.ctr, 8 * sizeof(unsigned long long)))) return rc;
         if ((rc = S.mem.alloc((void**)&S.slots, (size_t)kMaxGrid * 8 * sizeof(unsigned long long)))) return rc;
-        if ((rc = S.mem.alloc((void**)&S.barrier, 64))) return rc;
+        if ((rc = S.mem.alloc((void**)&S.barrier, 4096))) return rc;
         if ((rc = S.mem.alloc((void**)&S.error, 64))) return rc;
         if ((rc = S.mem.alloc((void**)&S.result, 64))) return rc;
     }
@@ -352,7 +355,7 @@ extern "C" const char* gbf_last_error(void) { return t_err.c_str(); }
 struct SolveOut {
     int64_t rounds = 0;
     unsigned long long ctr[6] = {0, 0, 0, 0, 0, 0};
-    double solve_ms = 0, relax_ms = 0;
+    double solve_ms = 0, relax_ms = 0, barrier_ms = 0;
     int64_t relax_launches = 0;
     int mode = 0, grid = 0, block = 0, lanes = 0, graph = 0;
     std::vector<int32_t> inst_status;
@@ -411,10 +414,11 @@ static int plan_solve(Scratch& S, const std::vector<Inst>& insts, int dtype, con
         } else {
             if (P.mode == GBF_MODE_AUTO) {
                 // measured on MI355X: one launch pair per round beats the
-                // cooperative kernel for single instances (its grid barriers
-                // write back and invalidate L2); batches use the persistent
-                // form, which can be captured in a HIP graph
-                P.mode = P.ninst > 1 ? GBF_MODE_PERSISTENT : GBF_MODE_HOSTLOOP;
+                // cooperative kernel for single instances and for batches
+                // (every grid barrier writes back and invalidates the L2 of
+                // each XCD, once per block); the persistent form is kept for
+                // callers that want one graph-capturable launch
+                P.mode = GBF_MODE_HOSTLOOP;
             }
             // co-residency is required; stay below the occupancy limit
             const int cap = std::min(per_cu, kPersistentBlocksPerCU) * cus;
@@ -434,7 +438,7 @@ static int enqueue_init(Scratch& S, const Plan& P, const std::vector<Inst>& inst
     HIPC(launch_fill_u32((uint32_t*)R.ctr, 0, 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.slots, 0, (int64_t)kMaxGrid * 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.inst_status, 0, P.ninst, s));
-    HIPC(launch_fill_u32(R.barrier, 0, 16, s));
+    HIPC(launch_fill_u32(R.barrier, 0, 1024, s));
     HIPC(launch_fill_u32((uint32_t*)R.error, 0, 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.result, 0, 16, s));
     for (const Inst& I : insts) HIPC(launch_init(S.dinst, I, P.dtype, s));
@@ -450,14 +454,20 @@ static int enqueue_readback(Scratch& S, const Plan& P, hipStream_t s) {
     HIPC(launch_sum_slots(S.slots, kMaxGrid, S.ctr, s));
     HIPC(hipMemcpyAsync(host, S.result, 4, hipMemcpyDeviceToHost, s));
     HIPC(hipMemcpyAsync(host + 1, S.error, 4, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(host + 4, S.result + 2, 8, hipMemcpyDeviceToHost, s));
     HIPC(hipMemcpyAsync(host + 16, S.ctr, 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIPC(hipMemcpyAsync(host + 64, S.inst_status, 4 * P.ninst, hipMemcpyDeviceToHost, s));
     return GBF_OK;
 }
 
-static void read_host(const Scratch& S, const Plan& P, SolveOut& out, bool rounds_from_host) {
+static void read_host(const Scratch& S, const Plan& P, SolveOut& out, bool rounds_from_host, int clock_khz) {
     const int32_t* host = (const int32_t*)S.host;
-    if (rounds_from_host) out.rounds = host[0];
+    if (rounds_from_host) {
+        out.rounds = host[0];
+        uint64_t ticks;
+        std::memcpy(&ticks, host + 4, 8);
+        out.barrier_ms = (double)ticks / (double)clock_khz;
+    }
     std::memcpy(out.ctr, host + 16, 6 * sizeof(unsigned long long));
     out.inst_status.assign(P.ninst, 0);
     for (int i = 0; i < P.ninst; ++i) out.inst_status[i] = host[64 + i];
@@ -542,7 +552,7 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
             }
             return fail(GBF_ETIMEOUT, "grid barrier timed out (blocks not co-resident?)");
         }
-        read_host(S, P, out, true);
+        read_host(S, P, out, true, clock_khz);
         if (o.profile) {
             float ms = 0;
             HIPC(hipEventElapsedTime(&ms, S.events[2], S.events[3]));
@@ -554,7 +564,7 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
     if ((rc = enqueue_hostloop(S, P, o, s, out))) return rc;
     if ((rc = enqueue_readback(S, P, s))) return rc;
     HIPC(hipStreamSynchronize(s));
-    read_host(S, P, out, false);
+    read_host(S, P, out, false, clock_khz);
     return GBF_OK;
 }
 
@@ -578,6 +588,7 @@ static void fill_stats(gbf_stats* st, int status, const SolveOut& so, int64_t ro
     st->solve_ms = so.solve_ms;
     st->relax_ms = so.relax_ms;
     st->relax_launches = so.relax_launches;
+    st->barrier_ms = so.barrier_ms;
     st->device_bytes = (int64_t)bytes;
     st->mode_used = so.mode;
     st->grid_used = so.grid;
@@ -775,7 +786,7 @@ extern "C" int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gb
             if (((int32_t*)S.host)[1] != 0) {
                 if (o.mode != GBF_MODE_AUTO) return fail(GBF_ETIMEOUT, "grid barrier timed out");
             } else {
-                read_host(S, P, so, true);
+                read_host(S, P, so, true, graphs[0]->clock_khz);
                 so.graph = 1;
                 replayed = true;
             }

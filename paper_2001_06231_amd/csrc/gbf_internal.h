@@ -39,7 +39,7 @@ struct Run {
     unsigned long long* ctr;    // [8]: pair evals, edges, improvements, saturations, expansions, marks
     unsigned long long* slots;  // per-block statistics [kMaxGrid * 8]
     int32_t* inst_status;       // per instance: 1 = cap reached with work left
-    uint32_t* barrier;          // persistent mode: [0] arrive counter, [1] generation
+    uint32_t* barrier;          // persistent mode: barrier words (see grid_barrier), 2304 bytes
     int32_t* error;             // persistent mode: barrier timeout flag
     int32_t* result;            // persistent mode: [0] rounds executed
     uint64_t timeout_ticks;     // persistent mode: bound of one barrier wait (device clock ticks)

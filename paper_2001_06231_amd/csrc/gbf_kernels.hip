@@ -34,6 +34,9 @@
 #ifndef GBF_COMPACT_C
 #define GBF_COMPACT_C 1
 #endif
+#ifndef GBF_PBLOCKS
+#define GBF_PBLOCKS 2  // persistent kernel: 1024-thread blocks per CU
+#endif
 
 namespace gbf {
 
@@ -46,8 +49,10 @@ __device__ __forceinline__ P ldx(const GBF_GLOBAL P* p) {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 
+// Per-lane statistics (32-bit; folded into the wave's 64-bit LDS slot after
+// every round, so they cannot overflow).
 struct Acc {
-    unsigned long long pairs = 0, edges = 0, impr = 0, sat = 0, expanded = 0, marks = 0;
+    uint32_t pairs = 0, edges = 0, impr = 0, sat = 0, expanded = 0, marks = 0;
 };
 
 // Statistics: each block owns kCtrSlot counters in R.slots (block index
@@ -57,20 +62,34 @@ constexpr int kCtrSlot = 8;
 
 constexpr int kMaxWavesPerBlock = 16;
 
-__device__ __forceinline__ void flush_acc(const Acc& a, unsigned long long* slots) {
-    __shared__ unsigned long long s_acc[kMaxWavesPerBlock][6];
-    const unsigned long long v[6] = {a.pairs, a.edges, a.impr, a.sat, a.expanded, a.marks};
+struct AccLds {
+    unsigned long long v[kMaxWavesPerBlock][6];
+};
+
+__device__ __forceinline__ void acc_init(AccLds& L) {
+    if (lane_id() < 6) L.v[threadIdx.x / kWave][lane_id()] = 0;
+}
+
+// Adds this wave's lane counters to its LDS slot and clears them.
+__device__ __forceinline__ void fold_acc(Acc& a, AccLds& L) {
+    const uint32_t v[6] = {a.pairs, a.edges, a.impr, a.sat, a.expanded, a.marks};
     const int w = threadIdx.x / kWave;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        const unsigned long long t = wave_sum64(v[k]);
-        if (lane_id() == 0) s_acc[w][k] = t;
+        const unsigned long long t = wave_sum64((unsigned long long)v[k]);
+        if (lane_id() == 0) L.v[w][k] += t;
     }
+    a = Acc();
+}
+
+// Block total into the block's slot (the only writer of that slot).
+__device__ __forceinline__ void flush_acc(Acc& a, AccLds& L, unsigned long long* slots) {
+    fold_acc(a, L);
     __syncthreads();
     if (threadIdx.x < 6) {
         unsigned long long t = 0;
         const int nw = blockDim.x / kWave;
-        for (int k = 0; k < nw; ++k) t += s_acc[k][threadIdx.x];
+        for (int k = 0; k < nw; ++k) t += L.v[k][threadIdx.x];
         if (t) slots[blockIdx.x * kCtrSlot + threadIdx.x] += t;
     }
 }
@@ -668,7 +687,7 @@ __device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_
 }
 
 constexpr int kCompactC = GBF_COMPACT_C;  // tiles per super-tile, 256-thread blocks
-constexpr int kPCompactC = 2;  // tiles per super-tile, 1024-thread blocks
+constexpr int kPCompactC = 1;  // tiles per super-tile, 1024-thread blocks
 
 __global__ __launch_bounds__(kBlock) void k_compact(Run R, int round) {
     __shared__ int s_w[kCompactC * kWavesPerBlock];
@@ -843,20 +862,9 @@ __device__ __forceinline__ void relax_round(const Inst* __restrict__ It, const i
     const uint32_t wpb = blockDim.x / kWave;
     const uint32_t wave = blockIdx.x * wpb + threadIdx.x / kWave;
     const uint32_t stride = gridDim.x * wpb * W;
-    uint32_t first = wave * W;
-    if (first >= count) return;
-    PairCtx c = load_pair<MULTI, ENC, G>(It, bases, R, count, first, round);
-    while (true) {
-        const uint32_t nf = first + stride;
-        // software pipelining: the next step's list entry and row bounds
-        // are loaded before this step's successor rows
-        PairCtx n;
-        const bool more = nf < count;
-        if (more) n = load_pair<MULTI, ENC, G>(It, bases, R, count, nf, round);
+    for (uint32_t first = wave * W; first < count; first += stride) {
+        const PairCtx c = load_pair<MULTI, ENC, G>(It, bases, R, count, first, round);
         relax_pairs<T, MULTI, ENC, G>(It, c, round, next, acc);
-        if (!more) break;
-        c = n;
-        first = nf;
     }
 }
 
@@ -869,9 +877,11 @@ __global__ __launch_bounds__(kBlock) void k_relax(const Inst* __restrict__ It, R
         for (int k = threadIdx.x; k < R.ninst; k += blockDim.x) s_bases[k] = It[k].pair_base;
         __syncthreads();
     }
+    __shared__ AccLds s_acc;
+    acc_init(s_acc);
     Acc acc;
     relax_round<T, MULTI, ENC, G>(It, s_bases, R, count, round, acc);
-    flush_acc(acc, R.slots);
+    flush_acc(acc, s_acc, R.slots);
 }
 
 // ------------------------------------------------------------------ persistent
@@ -879,6 +889,15 @@ __global__ __launch_bounds__(kBlock) void k_relax(const Inst* __restrict__ It, R
 // barrier that does not complete within R.timeout_ticks of the constant-rate
 // device clock sets R.error, and every block leaves the loop (blocks that
 // start after an error leave at once).
+// Barrier words, each on its own 128-byte line (uint32 index * 32):
+//   line 0: top-level arrival counter, line 1: generation,
+//   line 2 + g: arrival counter of group g (blocks b with b % kBarGroups == g).
+// Arrivals are device-scope atomics, which execute at the memory side and
+// serialise per address; spreading them over groups keeps each chain short.
+constexpr int kBarGroups = 16;
+constexpr int kBarLine = 32;
+static_assert((2 + kBarGroups) * kBarLine * 4 <= 4096, "barrier words exceed their 4 KiB allocation");
+
 __device__ __forceinline__ bool grid_barrier(uint32_t* bar, int32_t* err, uint32_t nblocks, uint64_t timeout_ticks) {
     __shared__ int s_ok;
     // the block barrier completes every wave's stores; one agent-scope
@@ -887,15 +906,28 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* bar, int32_t* err, uint32
     if (threadIdx.x == 0) {
         __threadfence();
         int ok = 1;
-        const uint32_t gen = __hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(bar + 1, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        uint32_t* top = bar;
+        uint32_t* gen_w = bar + kBarLine;
+        const uint32_t ng = nblocks < (uint32_t)kBarGroups ? nblocks : (uint32_t)kBarGroups;
+        const uint32_t grp = blockIdx.x % ng;
+        uint32_t* gctr = bar + (2 + grp) * kBarLine;
+        const uint32_t gsize = nblocks / ng + (grp < nblocks % ng ? 1u : 0u);
+        const uint32_t gen = __hip_atomic_load(gen_w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t a = __hip_atomic_fetch_add(gctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        bool released = false;
+        if (a == gsize - 1) {
+            __hip_atomic_store(gctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t t = __hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == ng - 1) {
+                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(gen_w, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                released = true;
+            }
+        }
+        if (!released) {
             const uint64_t t0 = wall_clock64();
-            while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
+            while (__hip_atomic_load(gen_w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(4);
                 if (wall_clock64() - t0 > timeout_ticks ||
                     __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                     atomicOr(err, 1);
@@ -914,8 +946,11 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* bar, int32_t* err, uint32
 
 constexpr int kPBlock = 1024;  // persistent kernel: one 16-wave block per CU
 
+// CSR variants fit 64 VGPRs (two 16-wave blocks per CU); the box
+// variants need more registers and run one block per CU.
 template <class T, bool MULTI, int ENC, int G>
-__global__ __launch_bounds__(kPBlock) void k_persistent(const Inst* __restrict__ It, Run R) {
+__global__ __launch_bounds__(kPBlock) __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 4 * GBF_PBLOCKS : 4)))
+void k_persistent(const Inst* __restrict__ It, Run R) {
     __shared__ int64_t s_bases[MULTI ? kMaxBatch : 1];
     __shared__ int s_w[kPCompactC * (kPBlock / kWave)];
     __shared__ uint32_t s_base;
@@ -924,22 +959,33 @@ __global__ __launch_bounds__(kPBlock) void k_persistent(const Inst* __restrict__
         __syncthreads();
     }
     if (__hip_atomic_load(R.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+    __shared__ AccLds s_acc;
+    acc_init(s_acc);
     Acc acc;
+    uint64_t t_bar = 0;  // block 0: device-clock ticks spent in barriers
     const int64_t ntiles = (R.nchunks + kPBlock * kPCompactC - 1) / (kPBlock * kPCompactC);
     for (int round = 0;; ++round) {
         uint8_t* cur = R.dirty[round & 1];
         for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
             compact_tile<kPBlock, kPCompactC>(cur, R.nchunks, tile, R.list, R.counts + round, s_w, &s_base);
-        if (!grid_barrier(R.barrier, R.error, gridDim.x, R.timeout_ticks)) break;
+        uint64_t t0 = wall_clock64();
+        const bool ok1 = grid_barrier(R.barrier, R.error, gridDim.x, R.timeout_ticks);
+        t_bar += wall_clock64() - t0;
+        if (!ok1) break;
         const uint32_t count = __hip_atomic_load(R.counts + round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (count == 0) {
             if (blockIdx.x == 0 && threadIdx.x == 0) R.result[0] = round;
             break;
         }
         relax_round<T, MULTI, ENC, G>(It, s_bases, R, count, round, acc);
-        if (!grid_barrier(R.barrier, R.error, gridDim.x, R.timeout_ticks)) break;
+        fold_acc(acc, s_acc);
+        t0 = wall_clock64();
+        const bool ok2 = grid_barrier(R.barrier, R.error, gridDim.x, R.timeout_ticks);
+        t_bar += wall_clock64() - t0;
+        if (!ok2) break;
     }
-    flush_acc(acc, R.slots);
+    if (blockIdx.x == 0 && threadIdx.x == 0) reinterpret_cast<uint64_t*>(R.result)[1] = t_bar;
+    flush_acc(acc, s_acc, R.slots);
 }
 
 // ------------------------------------------------------------------ dispatch
