@@ -162,6 +162,8 @@ class Graph:
         o.profile = 1 if profile else 0
         o.v_memspace = v_space
         if bucket_key is not None:
+            if bucket_key.element_size() != 2 or bucket_key.numel() < self.n:
+                raise ValueError("bucket_key must hold n 16-bit keys")
             o.bucket_key, sp = _ptr(bucket_key)
             if sp != DEVICE:
                 raise ValueError("bucket_key must be a device tensor")

@@ -78,6 +78,8 @@ struct Scratch {
     uint32_t* barrier = nullptr;
     int32_t* error = nullptr;
     int32_t* result = nullptr;
+    uint8_t* occ = nullptr;   // bucket order: occupancy per bucket [65536]
+    uint32_t* thr = nullptr;  // bucket order: selected bucket
     Inst* dinst = nullptr;
     int ninst_cap = 0;
     void* host = nullptr;  // pinned readback area
@@ -130,6 +132,8 @@ static int ensure_scratch(Scratch& S, int64_t total_pairs, int64_t max_rounds, i
         if ((rc = S.mem.alloc((void**)&S.barrier, 4096))) return rc;
         if ((rc = S.mem.alloc((void**)&S.error, 64))) return rc;
         if ((rc = S.mem.alloc((void**)&S.result, 64))) return rc;
+        if ((rc = S.mem.alloc((void**)&S.occ, 65536))) return rc;
+        if ((rc = S.mem.alloc((void**)&S.thr, 64))) return rc;
     }
     if (S.ninst_cap < ninst) {
         if (S.dinst) S.mem.release(S.dinst, 0), S.mem.release(S.inst_status, 0);
@@ -367,6 +371,7 @@ struct Plan {
     int ninst = 0;
     int64_t max_rounds = 0, max_states = 0;
     int enc_mask = 0, lanes = 4, mode = GBF_MODE_HOSTLOOP, grid = 0, dtype = 0;
+    bool bucket = false;
 };
 
 static int plan_solve(Scratch& S, const std::vector<Inst>& insts, int dtype, const gbf_opts& o, int cus,
@@ -394,6 +399,20 @@ static int plan_solve(Scratch& S, const std::vector<Inst>& insts, int dtype, con
     R.barrier = S.barrier;
     R.error = S.error;
     R.result = S.result;
+    R.occ = S.occ;
+    R.thr = S.thr;
+    R.key = nullptr;
+    R.keyK = 1;
+    if (o.order == GBF_ORDER_BUCKETS) {
+        // one byte map: the selection leaves unlisted pairs in place and the
+        // relax step marks into the same map
+        if (P.ninst != 1) return fail(GBF_EINVAL, "bucket order is for single solves");
+        if (o.mode == GBF_MODE_PERSISTENT) return fail(GBF_EINVAL, "bucket order runs in host-loop mode");
+        R.dirty[1] = R.dirty[0];
+        R.key = insts[0].key;
+        R.keyK = insts[0].K;
+        P.bucket = true;
+    }
     R.nchunks = (total_pairs + 15) / 16;
     R.total_pairs = total_pairs;
     R.max_rounds = P.max_rounds;
@@ -405,7 +424,7 @@ static int plan_solve(Scratch& S, const std::vector<Inst>& insts, int dtype, con
     P.lanes = (o.lanes == 1 || o.lanes == 2 || o.lanes == 4 || o.lanes == 8 || o.lanes == 16 || o.lanes == 32)
                   ? o.lanes
                   : 4;
-    P.mode = o.mode;
+    P.mode = P.bucket ? GBF_MODE_HOSTLOOP : o.mode;
     if (P.mode != GBF_MODE_HOSTLOOP) {
         const int per_cu = persistent_blocks_per_cu(R, P.lanes, dtype, P.enc_mask);
         if (per_cu <= 0) {
@@ -441,6 +460,7 @@ static int enqueue_init(Scratch& S, const Plan& P, const std::vector<Inst>& inst
     HIPC(launch_fill_u32(R.barrier, 0, 1024, s));
     HIPC(launch_fill_u32((uint32_t*)R.error, 0, 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.result, 0, 16, s));
+    if (P.bucket) HIPC(launch_fill_u32((uint32_t*)R.occ, 0, 65536 / 4, s));
     for (const Inst& I : insts) HIPC(launch_init(S.dinst, I, P.dtype, s));
     HIPC(launch_seed(S.dinst, P.ninst, R, P.max_states, P.dtype, P.enc_mask, s));
     return GBF_OK;
@@ -492,7 +512,8 @@ static int enqueue_hostloop(Scratch& S, const Plan& P, const gbf_opts& o, hipStr
     while (!done && r <= P.max_rounds + 1) {
         const int64_t nb = std::min<int64_t>(batch, P.max_rounds + 2 - r);
         for (int64_t k = 0; k < nb; ++k) {
-            HIPC(launch_compact(R, (int)(r + k), 0, s));
+            if (P.bucket) HIPC(launch_bucket_compact(R, (int)(r + k), 0, s));
+            else HIPC(launch_compact(R, (int)(r + k), 0, s));
             const bool timed = o.profile && ev + 1 < (int)S.events.size();
             if (timed) HIPC(hipEventRecord(S.events[ev], s));
             HIPC(launch_relax(S.dinst, R, (int)(r + k), P.grid, P.lanes, P.dtype, P.enc_mask, s));
@@ -620,10 +641,34 @@ extern "C" int gbf_solve(gbf_graph* g, const gbf_opts* opts, void* V_out, gbf_st
     Inst I = g->inst;
     I.pair_base = 0;
     I.max_rounds = o.max_rounds > 0 ? o.max_rounds : g->n;
+    const bool bucket = o.order == GBF_ORDER_BUCKETS;
+    if (bucket) {
+        // the bucket schedule may split a plain round into several: its cap
+        // is the plain cap plus one round per possible bucket; hitting it
+        // reruns the plain order (which decides the status)
+        int rc = ensure_scratch(g->scratch, g->n * g->K, 1, 1, 4);
+        if (rc) return rc;
+        I.key = o.bucket_key;
+        I.occ = g->scratch.occ;
+        I.max_rounds += 65536;
+    }
     std::vector<Inst> insts{I};
     SolveOut so;
     int rc = run_rounds(g->scratch, insts, g->dtype, o, s, g->cus, g->clock_khz, so);
     if (rc) return rc;
+    int fallback = 0;
+    if (bucket && so.inst_status[0]) {
+        gbf_opts o2 = o;
+        o2.order = GBF_ORDER_PLAIN;
+        o2.bucket_key = nullptr;
+        gbf_stats st2;
+        rc = gbf_solve(g, &o2, V_out, &st2);
+        if (st) {
+            *st = st2;
+            st->fallback = 1;
+        }
+        return rc;
+    }
     if ((rc = write_values(g, V_out, o.v_memspace, s))) return rc;
     HIPC(hipEventRecord(g->scratch.events[1], s));
     HIPC(hipEventSynchronize(g->scratch.events[1]));
@@ -632,6 +677,7 @@ extern "C" int gbf_solve(gbf_graph* g, const gbf_opts* opts, void* V_out, gbf_st
     so.solve_ms = ms;
     const int status = so.inst_status[0] ? GBF_ENEGCYCLE : GBF_OK;
     fill_stats(st, status, so, I.max_rounds, g->mem.bytes + g->scratch.mem.bytes);
+    if (st) st->fallback = fallback;
     g->solved = true;
     if (status != GBF_OK) fail(status, "round cap reached with a non-empty frontier");
     return status;

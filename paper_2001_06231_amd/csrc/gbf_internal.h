@@ -20,6 +20,8 @@ struct Inst {
     void* V;                // value words [n] (int32 or fp32 key)
     int32_t* stamp;         // last round in which the state was expanded [n]
     const int32_t* win;     // BOX: per input 8 ints: min (lo-x) per axis, max (hi-x) per axis
+    const uint16_t* key;    // bucket order: bucket key of each state [n], else NULL
+    uint8_t* occ;           // bucket order: occupancy flag per bucket [65536]
     int64_t n;
     int64_t pair_base;      // first global pair id
     int64_t max_rounds;     // round cap of this instance
@@ -43,11 +45,15 @@ struct Run {
     int32_t* error;             // persistent mode: barrier timeout flag
     int32_t* result;            // persistent mode: [0] rounds executed
     uint64_t timeout_ticks;     // persistent mode: bound of one barrier wait (device clock ticks)
+    const uint16_t* key;        // bucket order (single instance): state keys [n]
+    uint8_t* occ;               // bucket order: occupancy flag per bucket [65536]
+    uint32_t* thr;              // bucket order: bucket selected for the current round
     int64_t nchunks;            // 16-byte chunks per byte map
     int64_t total_pairs;
     int64_t max_rounds;         // global cap (max over instances)
     int32_t ninst;
     int32_t dtype;              // 0 int32, 1 fp32
+    int32_t keyK;               // bucket order: inputs per state
 };
 
 constexpr int kMaxBatch = 1024;
@@ -70,6 +76,9 @@ hipError_t launch_init(const Inst* dI, const Inst& I, int dtype, hipStream_t s);
 hipError_t launch_seed(const Inst* dI, int ninst, const Run& R, int64_t max_states, int dtype, int enc_mask,
                        hipStream_t s);
 hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s);
+// bucket order: bucket selection + compaction of the selected pairs (one
+// byte map, R.dirty[0] == R.dirty[1])
+hipError_t launch_bucket_compact(const Run& R, int round, int grid, hipStream_t s);
 // `lanes`: lanes per listed pair in the relax step (4, 8, 16 or 32)
 hipError_t launch_relax(const Inst* dI, const Run& R, int round, int grid, int lanes, int dtype, int enc_mask,
                         hipStream_t s);

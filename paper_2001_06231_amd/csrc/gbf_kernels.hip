@@ -497,10 +497,16 @@ hipError_t launch_init(const Inst* dI, const Inst& I, int dtype, hipStream_t s) 
 // side (it bypasses L2), while a byte store is write-combined in L2 and
 // merged by byte mask on write-back.  A plain read skips pairs already
 // marked (a stale read only misses marks, never invents them).
-__device__ __forceinline__ void mark_pair(uint8_t* __restrict__ dirty, uint32_t q, bool valid) {
+// Bucket order: the first mark of a pair also flags its state's bucket as
+// occupied (another idempotent byte store).
+__device__ __forceinline__ void mark_pair(const Inst& I, uint8_t* __restrict__ dirty, uint32_t base, uint32_t q,
+                                          bool valid) {
     if (valid) {
-        GBF_GLOBAL uint8_t* b = gp(dirty) + q;
-        if (*b == 0) *b = 1;
+        GBF_GLOBAL uint8_t* b = gp(dirty) + base + q;
+        if (*b == 0) {
+            *b = 1;
+            if (I.key) gp(I.occ)[gp(I.key)[q / (uint32_t)I.K]] = 1;
+        }
     }
 }
 
@@ -523,8 +529,8 @@ __device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint8_t* 
         for (uint32_t t0 = 0; t0 < len; t0 += kWave) {
             const uint32_t t = t0 + (uint32_t)lane;
             const bool v = t < len;
-            const uint32_t q = v ? base + ldx<GBF_NT_MISC>(rev + s0 + t) : 0u;
-            mark_pair(dirty, q, v);
+            const uint32_t q = v ? ldx<GBF_NT_MISC>(rev + s0 + t) : 0u;
+            mark_pair(I, dirty, base, q, v);
         }
         return;
     }
@@ -577,10 +583,10 @@ __device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint8_t* 
                         in &= (yc[a] >= lc) && (yc[a] <= lc + d.e[a]);
                     }
                     hit = in;
-                    q = base + (uint32_t)qq;
+                    q = (uint32_t)qq;
                 }
             }
-            mark_pair(dirty, q, hit);
+            mark_pair(I, dirty, base, q, hit);
         }
     }
 }
@@ -615,6 +621,11 @@ __global__ __launch_bounds__(kBlock) void k_seed(const Inst* __restrict__ It, in
 // popcounts (wave prefix sums staged in LDS) places the pair ids, ascending
 // within the tile, after a single global atomicAdd per tile.  Chunks are
 // cleared as they are read.
+// Inverse of nonzero_bytes4 for 0/1 bytes: bit b of the low nibble -> byte b.
+__device__ __forceinline__ uint32_t spread_bytes4(uint32_t m) {
+    return (m & 1u) | ((m & 2u) << 7) | ((m & 4u) << 14) | ((m & 8u) << 21);
+}
+
 __device__ __forceinline__ uint32_t nonzero_bytes4(uint32_t w) {
     const uint32_t hb = (((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w) & 0x80808080u;
     return ((hb >> 7) & 1u) | ((hb >> 14) & 2u) | ((hb >> 21) & 4u) | ((hb >> 28) & 8u);
@@ -625,15 +636,25 @@ __device__ __forceinline__ uint32_t nonzero_bytes4(uint32_t w) {
 // super-tile's slots (device-scope atomics execute at the memory side and
 // serialise on the single counter, so fewer is better), then the ids are
 // written in ascending order.
-template <int NB, int C>
+// Bucket order (BK): only dirty pairs whose state key is <= `thr` are
+// listed and cleared; the others stay in the map for a later round.
+struct BucketSel {
+    const uint16_t* key;
+    uint32_t thr;
+    uint32_t K;
+};
+
+template <int NB, int C, bool BK = false>
 __device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_t nchunks, int64_t stile,
-                                             uint32_t* __restrict__ list, uint32_t* cnt, int* s_w, uint32_t* s_base) {
+                                             uint32_t* __restrict__ list, uint32_t* cnt, int* s_w, uint32_t* s_base,
+                                             BucketSel bs = BucketSel{nullptr, 0u, 1u}) {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     constexpr int NW = NB / kWave;
     const int t = threadIdx.x;
     const int w = t / kWave;
     GBF_GLOBAL u32x4* chunks = reinterpret_cast<GBF_GLOBAL u32x4*>(gp(dirty));
     uint32_t mask[C];
+    uint32_t keep[C];  // BK: dirty pairs left in the map
     int loc[C];
 #pragma unroll
     for (int i = 0; i < C; ++i) {
@@ -642,6 +663,19 @@ __device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_
         if (ci < nchunks) v = chunks[ci];
         mask[i] = nonzero_bytes4(v.x) | (nonzero_bytes4(v.y) << 4) | (nonzero_bytes4(v.z) << 8) |
                   (nonzero_bytes4(v.w) << 12);
+        keep[i] = 0;
+        if (BK && mask[i]) {
+            const uint32_t p0 = (uint32_t)(ci * 16);
+            uint32_t x = p0 / bs.K, r = p0 - x * bs.K;
+            const GBF_GLOBAL uint16_t* key = gp(bs.key);
+            uint32_t sel = 0;
+            for (int b = 0; b < 16; ++b) {
+                if (((mask[i] >> b) & 1u) && (uint32_t)key[x] <= bs.thr) sel |= 1u << b;
+                if (++r == bs.K) r = 0, ++x;
+            }
+            keep[i] = mask[i] & ~sel;
+            mask[i] = sel;
+        }
         const int c = __popc(mask[i]);
         const int incl = wave_incl_scan(c);
         loc[i] = incl - c;
@@ -671,8 +705,16 @@ __device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_
             uint32_t m = mask[i];
             if (m) {
                 const int64_t ci = (stile * C + i) * NB + t;
-                const u32x4 zero = {0u, 0u, 0u, 0u};
-                chunks[ci] = zero;
+                u32x4 rest = {0u, 0u, 0u, 0u};
+                if (BK) {
+                    // the bytes of pairs left for later stay 1
+                    const uint32_t k = keep[i];
+                    rest.x = spread_bytes4(k);
+                    rest.y = spread_bytes4(k >> 4);
+                    rest.z = spread_bytes4(k >> 8);
+                    rest.w = spread_bytes4(k >> 12);
+                }
+                chunks[ci] = rest;
                 uint32_t pos = base + (uint32_t)loc[i];
                 const uint32_t pbase = (uint32_t)(ci * 16);
                 while (m) {
@@ -697,6 +739,62 @@ __global__ __launch_bounds__(kBlock) void k_compact(Run R, int round) {
     const int64_t nst = (R.nchunks + kBlock * kCompactC - 1) / (kBlock * kCompactC);
     for (int64_t st = blockIdx.x; st < nst; st += gridDim.x)
         compact_tile<kBlock, kCompactC>(cur, R.nchunks, st, R.list, R.counts + round, s_w, &s_base);
+}
+
+// Bucket order: picks the lowest occupied bucket b0 and clears its flag (the
+// following compaction lists every dirty pair with key <= b0, so the bucket
+// is empty afterwards until a new mark flags it again).  Past the round cap
+// every bucket is selected, so the remaining pairs are dropped and flagged
+// in one round.  No bucket occupied: *thr = kNoBucket, nothing is listed.
+constexpr uint32_t kNoBucket = 0xFFFFFFFFu;
+constexpr int kBuckets = 65536;
+
+__global__ __launch_bounds__(1024) void k_bucket_select(Run R, int round) {
+    __shared__ uint32_t s_min;
+    if (round > 0 && R.counts[round - 1] == 0) return;  // frontier already empty
+    if (threadIdx.x == 0) s_min = kNoBucket;
+    __syncthreads();
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const GBF_GLOBAL u32x4* occ = reinterpret_cast<const GBF_GLOBAL u32x4*>(gp(R.occ));
+    uint32_t best = kNoBucket;
+    for (int i = threadIdx.x; i < kBuckets / 16; i += blockDim.x) {
+        const u32x4 v = occ[i];
+        const uint32_t m = nonzero_bytes4(v.x) | (nonzero_bytes4(v.y) << 4) | (nonzero_bytes4(v.z) << 8) |
+                           (nonzero_bytes4(v.w) << 12);
+        if (m) {
+            best = (uint32_t)i * 16u + (uint32_t)(__ffs(m) - 1);
+            break;  // i only grows: this is the thread's smallest
+        }
+    }
+    if (best != kNoBucket) atomicMin(&s_min, best);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t b0 = s_min;
+        if (round >= R.max_rounds) b0 = kNoBucket - 1;  // cap reached: list everything
+        else if (b0 != kNoBucket) gp(R.occ)[b0] = 0;
+        *gp(R.thr) = b0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_bucket(Run R, int round) {
+    __shared__ int s_w[kWavesPerBlock];
+    __shared__ uint32_t s_base;
+    if (round > 0 && R.counts[round - 1] == 0) return;
+    const uint32_t thr = *gp(R.thr);
+    if (thr == kNoBucket) return;
+    const BucketSel bs{R.key, thr, (uint32_t)R.keyK};
+    const int64_t nst = (R.nchunks + kBlock - 1) / kBlock;
+    for (int64_t st = blockIdx.x; st < nst; st += gridDim.x)
+        compact_tile<kBlock, 1, true>(R.dirty[0], R.nchunks, st, R.list, R.counts + round, s_w, &s_base, bs);
+}
+
+hipError_t launch_bucket_compact(const Run& R, int round, int grid, hipStream_t s) {
+    k_bucket_select<<<1, 1024, 0, s>>>(R, round);
+    const int64_t ntiles = (R.nchunks + kBlock - 1) / kBlock;
+    int g = (int)std::min<int64_t>(ntiles, grid > 0 ? grid : 2048);
+    if (g < 1) g = 1;
+    k_compact_bucket<<<g, kBlock, 0, s>>>(R, round);
+    return hipGetLastError();
 }
 
 hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s) {

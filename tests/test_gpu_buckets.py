@@ -1,0 +1,137 @@
+"""GPU parity of the bucket-ordered solve: whatever the bucket keys (good,
+random, constant or adversarial), the frontier order changes only how often
+pairs are re-evaluated, never the result.  Values and policies are compared
+with the oracle element by element; a hit round cap falls back to the plain
+order, which decides the status."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2001_06231_amd as gbf
+import synth
+from tests import golden_io
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    gbf.lib()
+
+
+def _case(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def _keys(prob, ref, kind):
+    """Bucket keys per state: from the exact values (width 16), random,
+    constant, or the exact-value keys reversed."""
+    n = prob.n
+    V = ref["V"].astype(np.float64)
+    fin = np.isfinite(V) if prob.dtype == "f32" else (ref["V"] != synth.INF_I32)
+    if kind == "exact":
+        lo = V[fin].min() if fin.any() else 0.0
+        k = np.where(fin, np.floor((V - lo) / 16.0), 65535)
+        return np.clip(k, 0, 65535).astype(np.uint16)
+    if kind == "reversed":
+        return (65535 - _keys(prob, ref, "exact")).astype(np.uint16)
+    if kind == "random":
+        return (synth.Stream(12345, 7).raw(n) % np.uint64(65536)).astype(np.uint16)
+    if kind == "coarse":
+        return (synth.Stream(777, 3).raw(n) % np.uint64(4)).astype(np.uint16)
+    return np.zeros(n, dtype=np.uint16)
+
+
+def _solve_buckets(prob, keys, encoding="csr", **kw):
+    import torch
+    kt = torch.from_numpy(keys.view(np.int16)).cuda()
+    gr = gbf.load_problem(prob, encoding=encoding)
+    status, st, V = gr.solve(order="buckets", bucket_key=kt, **kw)
+    pol, res = gr.policy()
+    status_p, st_p, Vp = gr.solve(order="plain")
+    gr.free()
+    return status, st, V, pol, res, st_p, Vp
+
+
+def _check(prob, ref, got, label):
+    status, st, V, pol, res, st_p, Vp = got
+    assert status == gbf.OK, (label, status)
+    assert st["fallback"] == 0, label
+    assert res == 0, (label, "residual", res)
+    bad = np.nonzero(V != ref["V"])[0]
+    assert bad.size == 0, (label, bad[:8], V[bad[:8]], ref["V"][bad[:8]])
+    badp = np.nonzero(pol != ref["policy"])[0]
+    assert badp.size == 0, (label, badp[:8])
+    assert np.array_equal(Vp, V), label
+
+
+@pytest.mark.parametrize("kind", ["exact", "random", "constant", "reversed", "coarse"])
+def test_buckets_grid2d(kind):
+    prob = synth.grid2d_small()
+    ref = oracle.solve(prob)
+    _case(f"buckets grid2d {kind}")
+    _check(prob, ref, _solve_buckets(prob, _keys(prob, ref, kind)), kind)
+
+
+@pytest.mark.parametrize("kind", ["exact", "random", "reversed"])
+@pytest.mark.parametrize("encoding", ["csr", "box"])
+def test_buckets_grid4d_small(kind, encoding):
+    prob = synth.grid4d(synth.instance_seed(50, 0), dims=(16, 14, 8, 5), K=16)
+    ref = oracle.solve(prob)
+    _case(f"buckets grid4d small {kind} {encoding}")
+    got = _solve_buckets(prob, _keys(prob, ref, kind), encoding=encoding)
+    _check(prob, ref, got, f"{kind}/{encoding}")
+    print(f"pair evaluations: buckets {got[1]['pair_evals']} plain {got[5]['pair_evals']}", flush=True)
+
+
+@pytest.mark.parametrize("kind", ["exact", "random"])
+def test_buckets_fp32(kind):
+    prob = synth.grid4d(synth.instance_seed(51, 0), dtype="f32", dims=(14, 12, 8, 5), K=12)
+    ref = oracle.solve(prob, precision="f32")
+    _case(f"buckets fp32 {kind}")
+    _check(prob, ref, _solve_buckets(prob, _keys(prob, ref, kind)), kind)
+
+
+def test_buckets_ragged_pairs():
+    """n*K not a multiple of 16: the last chunk of the byte map is partial."""
+    prob = synth.grid_problem((13, 11), 3, [synth.P_HALF, synth.P_HALF], seed=synth.instance_seed(52, 0),
+                              dtype="i32", phi_top=40.0, sigmas=(3, 3, 0, 0), target_extent=(3, 3),
+                              avoid="iid", avoid_frac=0.1)
+    assert (prob.n * prob.K) % 16 != 0
+    ref = oracle.solve(prob)
+    _case("buckets ragged")
+    _check(prob, ref, _solve_buckets(prob, _keys(prob, ref, "random")), "ragged")
+
+
+def test_buckets_fallback_on_cap():
+    """A negative cycle: the bucket schedule hits its cap, the plain order
+    reruns and reports the capped status; the result equals the plain run."""
+    import torch
+    prob, _, _ = golden_io.load("negcycle.txt")
+    _case("buckets fallback")
+    gr = gbf.load_problem(prob, encoding="csr")
+    kt = torch.zeros(prob.n, dtype=torch.int16, device="cuda")
+    status, st, V = gr.solve(order="buckets", bucket_key=kt)
+    assert status == gbf.ENEGCYCLE and st["fallback"] == 1
+    status_p, st_p, Vp = gr.solve(order="plain")
+    assert status_p == gbf.ENEGCYCLE and st_p["fallback"] == 0
+    assert np.array_equal(V, Vp)
+    gr.free()
+
+
+def test_buckets_rejects_bad_use():
+    import torch
+    prob = synth.grid2d_small()
+    gr = gbf.load_problem(prob, encoding="csr")
+    kt = torch.zeros(prob.n, dtype=torch.int16, device="cuda")
+    with pytest.raises(gbf.GbfError):
+        gr.solve(order="buckets", bucket_key=kt, mode="persistent")
+    with pytest.raises(ValueError):
+        gr.solve(order="buckets", bucket_key=kt[:10])
+    with pytest.raises(gbf.GbfError):
+        gr.solve(order="buckets")  # no key
+    gr.free()
