@@ -150,7 +150,7 @@ typedef struct gbf_stats {
     int32_t block_used;
     int32_t lanes_used;
     int32_t graph_used;     /* 1 = batched solve replayed from a HIP graph */
-    int32_t reserved[1];
+    int32_t sweeps;         /* bucket order: ascending passes over the buckets */
 } gbf_stats;
 
 typedef struct gbf_graph gbf_graph;

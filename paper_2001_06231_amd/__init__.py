@@ -64,7 +64,7 @@ class _Stats(ctypes.Structure):
                 ("solve_ms", ctypes.c_double), ("relax_ms", ctypes.c_double),
                 ("relax_launches", ctypes.c_int64), ("barrier_ms", ctypes.c_double), ("device_bytes", ctypes.c_int64),
                 ("mode_used", ctypes.c_int32), ("grid_used", ctypes.c_int32), ("block_used", ctypes.c_int32),
-                ("lanes_used", ctypes.c_int32), ("graph_used", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("lanes_used", ctypes.c_int32), ("graph_used", ctypes.c_int32), ("sweeps", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: (getattr(self, k) if k != "reserved" else None) for k, _ in self._fields_ if k != "reserved"}

@@ -361,7 +361,7 @@ struct SolveOut {
     unsigned long long ctr[6] = {0, 0, 0, 0, 0, 0};
     double solve_ms = 0, relax_ms = 0, barrier_ms = 0;
     int64_t relax_launches = 0;
-    int mode = 0, grid = 0, block = 0, lanes = 0, graph = 0;
+    int mode = 0, grid = 0, block = 0, lanes = 0, graph = 0, sweeps = 0;
     std::vector<int32_t> inst_status;
 };
 
@@ -468,13 +468,14 @@ static int enqueue_init(Scratch& S, const Plan& P, const std::vector<Inst>& inst
 
 // Statistics reduction and read-back of the status words into pinned host
 // memory (all capturable).  Layout of S.host: [0] rounds, [1] barrier error,
-// [16..27] counters (6 x u64), [64..] per-instance status.
+// [8] bucket sweeps, [16..27] counters (6 x u64), [64..] per-instance status.
 static int enqueue_readback(Scratch& S, const Plan& P, hipStream_t s) {
     int32_t* host = (int32_t*)S.host;
     HIPC(launch_sum_slots(S.slots, kMaxGrid, S.ctr, s));
     HIPC(hipMemcpyAsync(host, S.result, 4, hipMemcpyDeviceToHost, s));
     HIPC(hipMemcpyAsync(host + 1, S.error, 4, hipMemcpyDeviceToHost, s));
     HIPC(hipMemcpyAsync(host + 4, S.result + 2, 8, hipMemcpyDeviceToHost, s));
+    if (P.bucket) HIPC(hipMemcpyAsync(host + 8, S.thr + 2, 4, hipMemcpyDeviceToHost, s));
     HIPC(hipMemcpyAsync(host + 16, S.ctr, 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIPC(hipMemcpyAsync(host + 64, S.inst_status, 4 * P.ninst, hipMemcpyDeviceToHost, s));
     return GBF_OK;
@@ -491,6 +492,7 @@ static void read_host(const Scratch& S, const Plan& P, SolveOut& out, bool round
     std::memcpy(out.ctr, host + 16, 6 * sizeof(unsigned long long));
     out.inst_status.assign(P.ninst, 0);
     for (int i = 0; i < P.ninst; ++i) out.inst_status[i] = host[64 + i];
+    out.sweeps = P.bucket ? host[8] : 0;
     out.mode = P.mode;
     out.grid = P.grid;
     out.block = P.mode == GBF_MODE_PERSISTENT ? 1024 : 256;
@@ -616,6 +618,7 @@ static void fill_stats(gbf_stats* st, int status, const SolveOut& so, int64_t ro
     st->block_used = so.block;
     st->lanes_used = so.lanes;
     st->graph_used = so.graph;
+    st->sweeps = so.sweeps;
 }
 
 static int write_values(gbf_graph* g, void* V_out, int memspace, hipStream_t s) {

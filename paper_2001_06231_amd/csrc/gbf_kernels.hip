@@ -636,8 +636,13 @@ __device__ __forceinline__ uint32_t nonzero_bytes4(uint32_t w) {
 // super-tile's slots (device-scope atomics execute at the memory side and
 // serialise on the single counter, so fewer is better), then the ids are
 // written in ascending order.
-// Bucket order (BK): only dirty pairs whose state key is <= `thr` are
-// listed and cleared; the others stay in the map for a later round.
+// Bucket order (BK): only dirty pairs whose state key equals `thr` (every
+// dirty pair if thr == kAllBuckets) are listed and cleared; the others stay
+// in the map for a later round.
+constexpr uint32_t kNoBucket = 0xFFFFFFFFu;
+constexpr uint32_t kAllBuckets = 0xFFFFFFFEu;
+constexpr int kBuckets = 65536;
+
 struct BucketSel {
     const uint16_t* key;
     uint32_t thr;
@@ -670,7 +675,7 @@ __device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_
             const GBF_GLOBAL uint16_t* key = gp(bs.key);
             uint32_t sel = 0;
             for (int b = 0; b < 16; ++b) {
-                if (((mask[i] >> b) & 1u) && (uint32_t)key[x] <= bs.thr) sel |= 1u << b;
+                if (((mask[i] >> b) & 1u) && (bs.thr == kAllBuckets || (uint32_t)key[x] == bs.thr)) sel |= 1u << b;
                 if (++r == bs.K) r = 0, ++x;
             }
             keep[i] = mask[i] & ~sel;
@@ -741,38 +746,62 @@ __global__ __launch_bounds__(kBlock) void k_compact(Run R, int round) {
         compact_tile<kBlock, kCompactC>(cur, R.nchunks, st, R.list, R.counts + round, s_w, &s_base);
 }
 
-// Bucket order: picks the lowest occupied bucket b0 and clears its flag (the
-// following compaction lists every dirty pair with key <= b0, so the bucket
-// is empty afterwards until a new mark flags it again).  Past the round cap
-// every bucket is selected, so the remaining pairs are dropped and flagged
-// in one round.  No bucket occupied: *thr = kNoBucket, nothing is listed.
-constexpr uint32_t kNoBucket = 0xFFFFFFFFu;
-constexpr int kBuckets = 65536;
-
+// Bucket order, one round: the buckets are drained in ascending key order in
+// sweeps.  The bucket listed next is the lowest occupied one at or above the
+// bucket of the previous round; pairs marked in lower buckets wait for the
+// next sweep, which starts at the lowest occupied bucket.  (Going back down
+// at once would re-evaluate a low bucket after every improvement further
+// up whenever the keys are not exactly in dependency order.)  The selected
+// bucket's flag is cleared: the compaction lists all its pairs, and a later
+// mark sets the flag again.  Past the round cap every pair is listed, so the
+// remaining pairs are dropped and flagged in one round.  No bucket occupied:
+// kNoBucket, nothing is listed.  Words: thr[0] selected bucket, thr[1] the
+// sweep position, thr[2] number of sweeps.
 __global__ __launch_bounds__(1024) void k_bucket_select(Run R, int round) {
-    __shared__ uint32_t s_min;
+    __shared__ uint32_t s_up, s_all;
     if (round > 0 && R.counts[round - 1] == 0) return;  // frontier already empty
-    if (threadIdx.x == 0) s_min = kNoBucket;
+    if (threadIdx.x == 0) {
+        s_up = kNoBucket;
+        s_all = kNoBucket;
+    }
     __syncthreads();
+    GBF_GLOBAL uint32_t* thr = gp(R.thr);
+    const uint32_t pos = round == 0 ? 0u : thr[1];
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     const GBF_GLOBAL u32x4* occ = reinterpret_cast<const GBF_GLOBAL u32x4*>(gp(R.occ));
-    uint32_t best = kNoBucket;
+    uint32_t up = kNoBucket, all = kNoBucket;
     for (int i = threadIdx.x; i < kBuckets / 16; i += blockDim.x) {
         const u32x4 v = occ[i];
-        const uint32_t m = nonzero_bytes4(v.x) | (nonzero_bytes4(v.y) << 4) | (nonzero_bytes4(v.z) << 8) |
-                           (nonzero_bytes4(v.w) << 12);
+        uint32_t m = nonzero_bytes4(v.x) | (nonzero_bytes4(v.y) << 4) | (nonzero_bytes4(v.z) << 8) |
+                     (nonzero_bytes4(v.w) << 12);
+        if (!m) continue;
+        const uint32_t b = (uint32_t)i * 16u;
+        if (all == kNoBucket) all = b + (uint32_t)(__ffs(m) - 1);
+        if (b + 15u < pos) continue;
+        if (b < pos) m &= ~((1u << (pos - b)) - 1u);
         if (m) {
-            best = (uint32_t)i * 16u + (uint32_t)(__ffs(m) - 1);
-            break;  // i only grows: this is the thread's smallest
+            up = b + (uint32_t)(__ffs(m) - 1);
+            break;  // i only grows: the thread's smallest at or above pos
         }
     }
-    if (best != kNoBucket) atomicMin(&s_min, best);
+    if (up != kNoBucket) atomicMin(&s_up, up);
+    if (all != kNoBucket) atomicMin(&s_all, all);
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t b0 = s_min;
-        if (round >= R.max_rounds) b0 = kNoBucket - 1;  // cap reached: list everything
-        else if (b0 != kNoBucket) gp(R.occ)[b0] = 0;
-        *gp(R.thr) = b0;
+        uint32_t b0 = s_up;
+        if (b0 == kNoBucket && s_all != kNoBucket) {
+            b0 = s_all;  // next sweep
+            thr[2] = (round == 0 ? 0u : thr[2]) + 1u;
+        } else if (round == 0) {
+            thr[2] = 1u;
+        }
+        if (round >= R.max_rounds) {
+            b0 = kAllBuckets;
+        } else if (b0 != kNoBucket) {
+            gp(R.occ)[b0] = 0;
+            thr[1] = b0;
+        }
+        thr[0] = b0;
     }
 }
 
@@ -780,7 +809,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_bucket(Run R, int round) {
     __shared__ int s_w[kWavesPerBlock];
     __shared__ uint32_t s_base;
     if (round > 0 && R.counts[round - 1] == 0) return;
-    const uint32_t thr = *gp(R.thr);
+    const uint32_t thr = gp(R.thr)[0];
     if (thr == kNoBucket) return;
     const BucketSel bs{R.key, thr, (uint32_t)R.keyK};
     const int64_t nst = (R.nchunks + kBlock - 1) / kBlock;
