@@ -196,6 +196,67 @@ int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gbf_opts* opt
 /* Releases a handle (NULL is allowed). */
 void gbf_free_graph(gbf_graph* g);
 
+/* ---- frontier-ordering network -----------------------------------------
+ * A multilayer perceptron 4 -> 64 -> 64 -> 1 with ReLU, trained on value
+ * functions the solver produced, that predicts V from the coordinates of a
+ * grid cell.  Its predictions only order the frontier (GBF_ORDER_BUCKETS:
+ * the buckets are drained lowest first, which cuts re-evaluations of pairs
+ * whose successors are not final yet); the fixed point of Sect. III-C, and
+ * so every value and the policy, does not depend on them.
+ *
+ * Features of cell x = x0 + N0*(x1 + N1*(x2 + N2*x3)) of a grid with dims
+ * N: ((x0+.5-tcx)/N0, (x1+.5-tcy)/N1, (x2+.5)/N2, (x3+.5)/N3), where
+ * (tcx, tcy) is the centre of the target in cell units.  The network output
+ * is V/scale.  Parameters: 4545 floats, W1 [64][4], b1 [64], W2 [64][64]
+ * (W2[j][k] feeds hidden unit k of layer 1 into unit j of layer 2), b2 [64],
+ * W3 [64], b3.  They are kept as an fp32 master copy (trained with Adam,
+ * beta1 0.9, beta2 0.999, eps 1e-8) and a bfloat16 working copy (round to
+ * nearest even) that every forward and backward pass uses, accumulating in
+ * fp32.  Device arrays are on the current device; all work is ordered on
+ * the stream given at creation, and calls return after it has completed.
+ * Errors: GBF_EINVAL, GBF_ENOMEM, GBF_EHIP (message in gbf_last_error). */
+#define GBF_MLP_NPARAMS 4545
+typedef struct gbf_mlp gbf_mlp;
+
+/* New network with the given initial parameters (host [4545], finite). */
+int gbf_mlp_create(const float* params, void* hip_stream, gbf_mlp** out);
+/* Replaces the parameters (host [4545]) and resets the Adam state. */
+int gbf_mlp_set_params(gbf_mlp* net, const float* params);
+/* Copies the fp32 master copy and/or the bf16 working copy (bit patterns)
+ * to host arrays of 4545 entries (either may be NULL). */
+int gbf_mlp_get_params(gbf_mlp* net, float* master_out, uint16_t* bf16_out);
+/* Training samples: for each cells[s] (device int64 [count]) writes its
+ * features to feat_out (device float [count][4]) and, if target_out (device
+ * float [count]) is non-NULL, the label V[cell]/scale from V (device [n],
+ * v_dtype GBF_I32 or GBF_F32), NaN where V is INF (no label).  A cell
+ * outside the grid gives NaN features and no label. */
+int gbf_mlp_samples(gbf_mlp* net, const int32_t dims[4], float tcx, float tcy, const void* V, int32_t v_dtype,
+                    float scale, const int64_t* cells, int64_t count, float* feat_out, float* target_out);
+/* Network outputs (device float [count]) for feature rows (device float
+ * [count][4]). */
+int gbf_mlp_forward(gbf_mlp* net, const float* feat, int64_t count, float* out);
+/* Gradient of the mean squared error over the labelled samples (target not
+ * NaN) with respect to the bf16 parameters.  The samples are rows idx[s]
+ * (device int64 [count]; NULL = rows 0..count-1) of feat (device [rows][4])
+ * and target (device [rows]); an index outside [0, rows) is skipped.
+ * grad_out: host [4545] or NULL; loss_out / labels_out: host or NULL. */
+int gbf_mlp_grad(gbf_mlp* net, const float* feat, const float* target, int64_t rows, const int64_t* idx,
+                 int64_t count, float* grad_out, double* loss_out, int64_t* labels_out);
+/* One Adam step (learning rate lr) on the minibatch given as for
+ * gbf_mlp_grad; refreshes the bf16 working copy.  loss_out (host, or NULL
+ * to return without waiting for it) receives the minibatch loss before the
+ * step. */
+int gbf_mlp_train_step(gbf_mlp* net, const float* feat, const float* target, int64_t rows, const int64_t* idx,
+                       int64_t count, float lr, float* loss_out);
+/* Bucket keys for every cell of the grid (n = product of dims < 2^32):
+ * vhat = scale * output, key = clamp(floor((vhat - min vhat) / width), 0,
+ * 65535) into key_out (device uint16 [n]), usable as gbf_opts.bucket_key.
+ * vhat_out (device float [n]) and vhat_min_out (host) may be NULL. */
+int gbf_mlp_bucket_keys(gbf_mlp* net, const int32_t dims[4], float tcx, float tcy, float scale, float width,
+                        uint16_t* key_out, float* vhat_out, float* vhat_min_out);
+/* Releases a network (NULL is allowed). */
+void gbf_mlp_free(gbf_mlp* net);
+
 /* Message for the last failing call of this thread ("" if none). */
 const char* gbf_last_error(void);
 

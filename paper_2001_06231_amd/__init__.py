@@ -71,7 +71,9 @@ class _Stats(ctypes.Structure):
 
 
 EXPORTS = ("gbf_load_graph", "gbf_solve", "gbf_extract_policy", "gbf_solve_batch", "gbf_free_graph",
-           "gbf_last_error")
+           "gbf_last_error", "gbf_mlp_create", "gbf_mlp_set_params", "gbf_mlp_get_params", "gbf_mlp_samples",
+           "gbf_mlp_forward", "gbf_mlp_grad", "gbf_mlp_train_step", "gbf_mlp_bucket_keys", "gbf_mlp_free")
+MLP_NPARAMS = 4545
 
 _lock = threading.Lock()
 _lib = None
@@ -100,6 +102,23 @@ def lib():
             L.gbf_free_graph.restype = None
             L.gbf_last_error.argtypes = []
             L.gbf_last_error.restype = ctypes.c_char_p
+            I64, F, I = ctypes.c_int64, ctypes.c_float, ctypes.c_int32
+            D4 = ctypes.POINTER(ctypes.c_int32)
+            for name, args in (
+                    ("gbf_mlp_create", [P, P, ctypes.POINTER(P)]),
+                    ("gbf_mlp_set_params", [P, P]),
+                    ("gbf_mlp_get_params", [P, P, P]),
+                    ("gbf_mlp_samples", [P, D4, F, F, P, I, F, P, I64, P, P]),
+                    ("gbf_mlp_forward", [P, P, I64, P]),
+                    ("gbf_mlp_grad", [P, P, P, I64, P, I64, P, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(I64)]),
+                    ("gbf_mlp_train_step", [P, P, P, I64, P, I64, F, ctypes.POINTER(F)]),
+                    ("gbf_mlp_bucket_keys", [P, D4, F, F, F, F, P, P, ctypes.POINTER(F)])):
+                fn = getattr(L, name)
+                fn.argtypes = args
+                fn.restype = ctypes.c_int
+            L.gbf_mlp_free.argtypes = [P]
+            L.gbf_mlp_free.restype = None
             _lib = L
     return _lib
 
@@ -286,3 +305,122 @@ def solve_batch(graphs: Sequence[Graph], V_outs=None, *, mode="auto", max_rounds
     if rc < 0 or (check and rc not in (OK, ENEGCYCLE)):
         raise _err(L, rc)
     return rc, [s.as_dict() for s in st], V_outs
+
+
+# ---------------------------------------------------------------------------
+# Frontier-ordering network (gbf_mlp_*)
+# ---------------------------------------------------------------------------
+def _dev_ptr(t, what, dtype_size=None, numel=None):
+    if t is None:
+        return None
+    if not hasattr(t, "is_cuda") or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous device tensor")
+    if dtype_size is not None and t.element_size() != dtype_size:
+        raise ValueError(f"{what} has the wrong element size")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{what} is too small")
+    return t.data_ptr()
+
+
+def _dims4(dims):
+    d = list(dims) + [1] * (4 - len(dims))
+    return (ctypes.c_int32 * 4)(*[int(v) for v in d])
+
+
+class MLP:
+    """The frontier-ordering network (gbf_mlp_*): 4 -> 64 -> 64 -> 1, bf16
+    working weights, fp32 master weights trained with Adam.  Device arrays
+    are torch tensors on the GPU; work runs on `stream` (default: torch's
+    current stream)."""
+
+    def __init__(self, params, stream=None):
+        L = lib()
+        self._stream = current_stream() if stream is None else stream
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (MLP_NPARAMS,):
+            raise ValueError(f"params must have {MLP_NPARAMS} entries")
+        h = ctypes.c_void_p()
+        rc = L.gbf_mlp_create(p.ctypes.data, self._stream, ctypes.byref(h))
+        if rc != OK:
+            raise _err(L, rc)
+        self._h = h
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "_h", None):
+            if _lib is not None:
+                _lib.gbf_mlp_free(self._h)
+            self._h = None
+
+    def _check(self, rc):
+        if rc != OK:
+            raise _err(lib(), rc)
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (MLP_NPARAMS,):
+            raise ValueError(f"params must have {MLP_NPARAMS} entries")
+        self._check(lib().gbf_mlp_set_params(self._h, p.ctypes.data))
+
+    def params(self):
+        """(fp32 master copy, bf16 working copy as uint16 bit patterns)."""
+        m = np.empty(MLP_NPARAMS, np.float32)
+        b = np.empty(MLP_NPARAMS, np.uint16)
+        self._check(lib().gbf_mlp_get_params(self._h, m.ctypes.data, b.ctypes.data))
+        return m, b
+
+    def samples(self, dims, tc, cells, V=None, scale=1000.0):
+        """Features (and labels V/scale if V is given) of the cells."""
+        import torch
+        cnt = int(cells.numel())
+        feat = torch.empty((cnt, 4), dtype=torch.float32, device=cells.device)
+        tgt = torch.empty(cnt, dtype=torch.float32, device=cells.device) if V is not None else None
+        vdt = (F32 if V.dtype == torch.float32 else I32) if V is not None else I32
+        self._check(lib().gbf_mlp_samples(self._h, _dims4(dims), float(tc[0]), float(tc[1]),
+                                          _dev_ptr(V, "V", 4), vdt, float(scale),
+                                          _dev_ptr(cells, "cells", 8), cnt, _dev_ptr(feat, "feat"),
+                                          _dev_ptr(tgt, "target")))
+        return feat, tgt
+
+    def forward(self, feat):
+        import torch
+        cnt = int(feat.shape[0])
+        out = torch.empty(cnt, dtype=torch.float32, device=feat.device)
+        self._check(lib().gbf_mlp_forward(self._h, _dev_ptr(feat, "feat", 4, 4 * cnt), cnt, _dev_ptr(out, "out")))
+        return out
+
+    def grad(self, feat, target, idx=None):
+        rows = int(target.numel())
+        cnt = int(idx.numel()) if idx is not None else rows
+        g = np.empty(MLP_NPARAMS, np.float32)
+        loss = ctypes.c_double(0.0)
+        lab = ctypes.c_int64(0)
+        self._check(lib().gbf_mlp_grad(self._h, _dev_ptr(feat, "feat", 4, 4 * rows), _dev_ptr(target, "target", 4),
+                                       rows, _dev_ptr(idx, "idx", 8), cnt, g.ctypes.data, ctypes.byref(loss),
+                                       ctypes.byref(lab)))
+        return g, loss.value, lab.value
+
+    def train_step(self, feat, target, idx=None, lr=1e-3, want_loss=False):
+        rows = int(target.numel())
+        cnt = int(idx.numel()) if idx is not None else rows
+        loss = ctypes.c_float(0.0)
+        self._check(lib().gbf_mlp_train_step(self._h, _dev_ptr(feat, "feat", 4, 4 * rows),
+                                             _dev_ptr(target, "target", 4), rows, _dev_ptr(idx, "idx", 8), cnt,
+                                             float(lr), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def bucket_keys(self, dims, tc, scale=1000.0, width=16.0, keys=None, vhat=None):
+        """Bucket keys of every cell (device int16 tensor holding the uint16
+        keys, for Graph.solve(order="buckets", bucket_key=...)) and the
+        minimum prediction."""
+        import torch
+        n = int(np.prod([int(v) for v in dims]))
+        if keys is None:
+            keys = torch.empty(n, dtype=torch.int16, device="cuda")
+        vmin = ctypes.c_float(0.0)
+        self._check(lib().gbf_mlp_bucket_keys(self._h, _dims4(dims), float(tc[0]), float(tc[1]), float(scale),
+                                              float(width), _dev_ptr(keys, "keys", 2, n),
+                                              _dev_ptr(vhat, "vhat", 4, n), ctypes.byref(vmin)))
+        return keys, vmin.value

@@ -29,6 +29,8 @@ static int fail(int code, const std::string& msg) {
     return code;
 }
 
+int gbf::set_error(int code, const std::string& msg) { return fail(code, msg); }
+
 #define HIPC(expr)                                                                                 \
     do {                                                                                           \
         hipError_t e_ = (expr);                                                                    \

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace gbf {
 
 // One problem instance as the kernels see it.  Pair ids are global: pair p
@@ -55,6 +57,10 @@ struct Run {
     int32_t dtype;              // 0 int32, 1 fp32
     int32_t keyK;               // bucket order: inputs per state
 };
+
+// Records `msg` as the calling thread's last error (gbf_last_error) and
+// returns `code`.
+int set_error(int code, const std::string& msg);
 
 constexpr int kMaxBatch = 1024;
 constexpr int kMaxGrid = 8192;  // most blocks of any solver launch
