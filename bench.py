@@ -71,13 +71,145 @@ def read_traffic(kernel):
         return None
 
 
-def run(args):
+def _gen_learned(index):
+    import synth
+    return synth.learned_instance(index, with_csr=False)
+
+
+def _gen_batch(i):
+    import synth
+    return synth.batch_instance(i, 64, with_csr=False)
+
+
+def _gen_small(kind):
+    import synth
+    if kind == "grid2d":
+        return synth.grid2d_small()
+    return synth.grid4d(dtype="f32")
+
+
+def _median_solve(graph, reps, **kw):
+    """Median-time solve over `reps` runs (after one warm-up): stats dict."""
+    import numpy as np
+    graph.solve(**kw)
+    runs = [graph.solve(**kw)[1] for _ in range(reps)]
+    med = float(np.median([r["solve_ms"] for r in runs]))
+    best = min(runs, key=lambda r: abs(r["solve_ms"] - med))
+    return dict(best, solve_ms=med)
+
+
+def learned_compare(prob, params, untrained, reps=3):
+    """Plain vs network-bucketed order on one instance: solve times, MLP
+    inference time, relaxation counts, rounds; values compared bit for bit.
+    `untrained` is the control network (initial weights)."""
+    import torch
+
+    import paper_2001_06231_amd as gbf
+    from paper_2001_06231_amd import learn
+    g = gbf.load_problem(prob, encoding="csr")
+    Vp = torch.empty(prob.n, dtype=torch.int32, device="cuda")
+    Vb = torch.empty_like(Vp)
+    plain = _median_solve(g, reps, V_out=Vp)
+    pol_p, _ = g.policy()
+    tc = learn.target_centre(prob)
+    out = {"instance": prob.name, "n_states": prob.n, "pairs": prob.npairs,
+           "plain": {k: plain[k] for k in ("solve_ms", "rounds", "pair_evals", "edge_relax")}}
+    for label, par in (("learned", params), ("untrained", untrained)):
+        net = gbf.MLP(par)
+        keys = torch.empty(prob.n, dtype=torch.int16, device="cuda")
+        net.bucket_keys(prob.dims, tc, learn.SCALE, learn.WIDTH, keys=keys)  # warm-up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        mlp_ms = []
+        for _ in range(reps):
+            e0.record()
+            net.bucket_keys(prob.dims, tc, learn.SCALE, learn.WIDTH, keys=keys)
+            e1.record()
+            e1.synchronize()
+            mlp_ms.append(e0.elapsed_time(e1))
+        st = _median_solve(g, reps, V_out=Vb, order="buckets", bucket_key=keys)
+        pol_b, res = g.policy()
+        exact = bool(torch.equal(Vp, Vb)) and bool((pol_b == pol_p).all()) and res == 0
+        out[label] = {"solve_ms": st["solve_ms"], "mlp_ms": sorted(mlp_ms)[len(mlp_ms) // 2],
+                      "rounds": st["rounds"], "sweeps": st["sweeps"], "pair_evals": st["pair_evals"],
+                      "edge_relax": st["edge_relax"], "fallback": st["fallback"], "bit_exact": exact}
+        net.free()
+    g.free()
+    L, P = out["learned"], out["plain"]
+    out["wall_speedup_incl_mlp"] = P["solve_ms"] / (L["solve_ms"] + L["mlp_ms"])
+    out["relaxation_reduction"] = P["edge_relax"] / max(1, L["edge_relax"])
+    return out
+
+
+def batch_compare(probs, reps=3):
+    """One batched solve of all instances vs one plain solve per instance
+    (wall time around the calls, device outputs), and the persistent form
+    replayed from its HIP graph."""
+    import numpy as np
+    import torch
+
+    import paper_2001_06231_amd as gbf
+    graphs = [gbf.load_problem(p, encoding="csr") for p in probs]
+    outs = [torch.empty(p.n, dtype=torch.int32, device="cuda") for p in probs]
+    seq = [torch.empty_like(o) for o in outs]
+
+    def wall(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t0))
+        return float(np.median(ts)), r
+
+    def sequential():
+        return [gr.solve(v)[1] for gr, v in zip(graphs, seq)]
+
+    seq_ms, seq_stats = wall(sequential)
+    bat_ms, (_, bat_stats, _) = wall(lambda: gbf.solve_batch(graphs, outs))
+    per_ms, (_, per_stats, _) = wall(lambda: gbf.solve_batch(graphs, outs, mode="persistent"))
+    exact = all(bool(torch.equal(a, b)) for a, b in zip(outs, seq))
+    res = {"instances": len(probs), "n_states": int(sum(p.n for p in probs)),
+           "pairs": int(sum(p.npairs for p in probs)),
+           "sequential_ms": seq_ms, "batched_ms": bat_ms, "batched_mode": "hostloop",
+           "persistent_graph_ms": per_ms, "graph_used": int(per_stats[0]["graph_used"]),
+           "speedup": seq_ms / bat_ms,
+           "edge_relax_batched": int(bat_stats[0]["edge_relax"]),
+           "edge_relax_sequential": int(sum(s["edge_relax"] for s in seq_stats)),
+           "rounds_batched": int(bat_stats[0]["rounds"]), "bit_exact": exact}
+    for gr in graphs:
+        gr.free()
+    return res
+
+
+def config_line(prob, encoding, reps=5):
+    """Solve time, edge relaxations/s and device memory of one configuration."""
+    import torch
+
+    import paper_2001_06231_amd as gbf
+    g = gbf.load_problem(prob, encoding=encoding)
+    V = torch.empty(prob.n, dtype=torch.int32 if prob.dtype == "i32" else torch.float32, device="cuda")
+    st = _median_solve(g, reps, V_out=V)
+    g.free()
+    return {"solve_ms": st["solve_ms"], "edge_relax_per_s": st["edge_relax"] / (st["solve_ms"] * 1e-3),
+            "rounds": st["rounds"], "edge_relax": st["edge_relax"], "device_bytes": st["device_bytes"],
+            "encoding": encoding}
+
+
+def run(args, pool=None):
     import numpy as np
     import torch
 
     import paper_2001_06231_amd as gbf
     import synth
 
+    jobs = {}
+    if pool is not None and not args.no_extras:
+        jobs["learned"] = pool.apply_async(_gen_learned, (1000,))
+        jobs["batch"] = pool.map_async(_gen_batch, range(64))
+        jobs["grid2d"] = pool.apply_async(_gen_small, ("grid2d",))
+        jobs["grid4d_f32"] = pool.apply_async(_gen_small, ("grid4d_f32",))
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
     t0 = time.time()
@@ -169,10 +301,71 @@ def run(args):
         "device_bytes": int(stats[0]["device_bytes"]),
         "kernel_source_sha256_16": kernel_source_hash(),
     }
+    graph.free()
+    if jobs:
+        from paper_2001_06231_amd import learn
+        extras = {}
+        p2 = jobs["grid2d"].get()
+        pf = jobs["grid4d_f32"].get()
+        extras["grid2d_64x64_i32_csr"] = config_line(p2, "csr")
+        extras["grid4d_384k_f32_csr"] = config_line(pf, "csr")
+        extras["grid4d_384k_f32_box"] = config_line(pf, "box")
+        print("[bench] configs done", file=sys.stderr, flush=True)
+        out["configs"] = extras
+        out["batch64"] = batch_compare(jobs["batch"].get())
+        print("[bench] batch done", file=sys.stderr, flush=True)
+        if os.path.exists(learn.WEIGHTS):
+            out["learned"] = learned_compare(jobs["learned"].get(), learn.load_params(),
+                                             learn.init_params(1))
+        else:
+            out["learned"] = {"skipped": "no trained weights"}
+        print("[bench] learned done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_reps)
-    graph.free()
     return out
+
+
+def learned_eval(args, pool):
+    """Held-out evaluation of the trained network: instances 1000.. of the
+    60x60x30x12 K=16 family.  Prints one JSON object."""
+    import numpy as np
+    import torch
+
+    from paper_2001_06231_amd import learn
+    torch.cuda.set_device(0)
+    params = learn.load_params()
+    untrained = learn.init_params(1)
+    recs = []
+    idx = list(range(1000, 1000 + args.learned_eval))
+    gen = pool.imap(_gen_learned, idx) if pool is not None else map(_gen_learned, idx)
+    for i, prob in zip(idx, gen):
+        r = learned_compare(prob, params, untrained, reps=args.eval_reps)
+        recs.append(r)
+        print(f"[eval] {i}: plain {r['plain']['solve_ms']:.2f} ms / {r['plain']['edge_relax']:.3e} edges, "
+              f"learned {r['learned']['solve_ms']:.2f} (+{r['learned']['mlp_ms']:.2f}) ms / "
+              f"{r['learned']['edge_relax']:.3e}, untrained {r['untrained']['solve_ms']:.2f} ms, "
+              f"exact {r['learned']['bit_exact'] and r['untrained']['bit_exact']}", file=sys.stderr, flush=True)
+
+    def mean(f):
+        return float(np.mean([f(r) for r in recs]))
+    summary = {
+        "instances": len(recs),
+        "plain_solve_ms": mean(lambda r: r["plain"]["solve_ms"]),
+        "learned_solve_ms": mean(lambda r: r["learned"]["solve_ms"]),
+        "learned_mlp_ms": mean(lambda r: r["learned"]["mlp_ms"]),
+        "untrained_solve_ms": mean(lambda r: r["untrained"]["solve_ms"]),
+        "plain_edge_relax": mean(lambda r: r["plain"]["edge_relax"]),
+        "learned_edge_relax": mean(lambda r: r["learned"]["edge_relax"]),
+        "untrained_edge_relax": mean(lambda r: r["untrained"]["edge_relax"]),
+        "plain_rounds": mean(lambda r: r["plain"]["rounds"]),
+        "learned_rounds": mean(lambda r: r["learned"]["rounds"]),
+        "all_bit_exact": all(r["learned"]["bit_exact"] and r["untrained"]["bit_exact"] for r in recs),
+        "fallbacks": int(sum(r["learned"]["fallback"] + r["untrained"]["fallback"] for r in recs)),
+    }
+    summary["wall_speedup_incl_mlp"] = summary["plain_solve_ms"] / (summary["learned_solve_ms"] +
+                                                                     summary["learned_mlp_ms"])
+    summary["relaxation_reduction"] = summary["plain_edge_relax"] / summary["learned_edge_relax"]
+    return {"summary": summary, "instances": recs}
 
 
 def cpu_baseline(prob, reps):
@@ -203,12 +396,30 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true", help="run a 256 MiB device copy first (counter reference)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the main workload (no other configs, batch or learned comparison)")
+    ap.add_argument("--learned-eval", type=int, default=0,
+                    help="instead: evaluate the trained network on this many held-out instances")
+    ap.add_argument("--eval-reps", type=int, default=3)
+    ap.add_argument("--workers", type=int, default=8, help="generator processes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver has no multi-GPU "
-              "path in this build", file=sys.stderr)
+              "path", file=sys.stderr)
         sys.exit(2)
-    print(json.dumps(run(args)), flush=True)
+    # the generator workers are forked before the first GPU call
+    pool = None
+    if args.workers > 1 and (args.learned_eval or not args.no_extras):
+        import multiprocessing as mp
+        pool = mp.get_context("fork").Pool(args.workers)
+    try:
+        if args.learned_eval:
+            print(json.dumps(learned_eval(args, pool)), flush=True)
+        else:
+            print(json.dumps(run(args, pool)), flush=True)
+    finally:
+        if pool is not None:
+            pool.terminate()
 
 
 if __name__ == "__main__":

@@ -68,6 +68,7 @@ extern "C" {
 
 #define GBF_ORDER_PLAIN 0   /* frontier rounds as in Algorithm 1 */
 #define GBF_ORDER_BUCKETS 1 /* frontier drained in ascending bucket key */
+#define GBF_BUCKET_SPAN_DEFAULT 32
 
 #define GBF_MODE_AUTO 0       /* currently the host loop (faster on MI355X) */
 #define GBF_MODE_HOSTLOOP 1   /* one launch sequence per round from the host */
@@ -126,7 +127,11 @@ typedef struct gbf_opts {
     int32_t profile;        /* 1 = time every relax launch with HIP events */
     int32_t batch_hint;     /* host-loop mode: rounds launched before the first
                                frontier-size check; 0 = default (8) */
-    int32_t reserved[3];
+    int32_t bucket_span;    /* BUCKETS: k >= 1 = each round lists the dirty pairs
+                               of the k buckets from the lowest occupied one up;
+                               -1 = ascending sweeps, one bucket per round;
+                               0 = default (GBF_BUCKET_SPAN_DEFAULT) */
+    int32_t reserved[2];
 } gbf_opts;
 
 /* ---- statistics ------------------------------------------------------- */

@@ -53,7 +53,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("mode", ctypes.c_int32), ("bucket_key", ctypes.c_void_p),
                 ("max_rounds", ctypes.c_int64), ("lanes", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("v_memspace", ctypes.c_int32), ("profile", ctypes.c_int32), ("batch_hint", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("bucket_span", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class _Stats(ctypes.Structure):
@@ -171,9 +171,10 @@ class Graph:
                 L.gbf_free_graph(self._h)
             self._h = None
 
-    def _opts(self, order, mode, max_rounds, grid, profile, bucket_key, v_space, lanes=0):
+    def _opts(self, order, mode, max_rounds, grid, profile, bucket_key, v_space, lanes=0, bucket_span=0):
         o = _Opts()
         o.lanes = int(lanes)
+        o.bucket_span = int(bucket_span)
         o.order = _ORDERS[order]
         o.mode = _MODES[mode]
         o.max_rounds = int(max_rounds)
@@ -189,7 +190,7 @@ class Graph:
         return o
 
     def solve(self, V_out=None, *, order="plain", mode="auto", max_rounds=0, grid=0, profile=False,
-              bucket_key=None, lanes=0, check=True):
+              bucket_key=None, lanes=0, bucket_span=0, check=True):
         """Runs the solver; returns (status, stats dict, V_out).  V_out may be
         a numpy array (host) or a torch tensor on the GPU; if None a numpy
         array is allocated."""
@@ -197,7 +198,7 @@ class Graph:
         if V_out is None:
             V_out = np.empty(self.n, dtype=np.int32 if self.dtype == I32 else np.float32)
         vp, vs = _ptr(V_out)
-        o = self._opts(order, mode, max_rounds, grid, profile, bucket_key, vs, lanes)
+        o = self._opts(order, mode, max_rounds, grid, profile, bucket_key, vs, lanes, bucket_span)
         st = _Stats()
         rc = L.gbf_solve(self._h, ctypes.byref(o), vp, ctypes.byref(st))
         if rc < 0 or (check and rc not in (OK, ENEGCYCLE)):

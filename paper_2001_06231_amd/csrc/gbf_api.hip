@@ -410,9 +410,11 @@ static int plan_solve(Scratch& S, const std::vector<Inst>& insts, int dtype, con
         // relax step marks into the same map
         if (P.ninst != 1) return fail(GBF_EINVAL, "bucket order is for single solves");
         if (o.mode == GBF_MODE_PERSISTENT) return fail(GBF_EINVAL, "bucket order runs in host-loop mode");
+        if (o.bucket_span < -1) return fail(GBF_EINVAL, "bucket_span must be >= -1");
         R.dirty[1] = R.dirty[0];
         R.key = insts[0].key;
         R.keyK = insts[0].K;
+        R.bspan = o.bucket_span == 0 ? GBF_BUCKET_SPAN_DEFAULT : o.bucket_span;
         P.bucket = true;
     }
     R.nchunks = (total_pairs + 15) / 16;

@@ -56,6 +56,7 @@ struct Run {
     int32_t ninst;
     int32_t dtype;              // 0 int32, 1 fp32
     int32_t keyK;               // bucket order: inputs per state
+    int32_t bspan;              // bucket order: buckets per round (>= 1), or -1 = sweeps
 };
 
 // Records `msg` as the calling thread's last error (gbf_last_error) and

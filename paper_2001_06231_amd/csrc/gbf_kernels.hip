@@ -31,11 +31,11 @@
 #ifndef GBF_NT_MISC
 #define GBF_NT_MISC 0  // ... for list entries, row bounds, costs, reverse rows
 #endif
-#ifndef GBF_COMPACT_C
-#define GBF_COMPACT_C 1
-#endif
 #ifndef GBF_PBLOCKS
 #define GBF_PBLOCKS 2  // persistent kernel: 1024-thread blocks per CU
+#endif
+#ifndef GBF_COMPACT_GRID
+#define GBF_COMPACT_GRID 512  // blocks of a host-loop compaction
 #endif
 
 namespace gbf {
@@ -616,11 +616,12 @@ __global__ __launch_bounds__(kBlock) void k_seed(const Inst* __restrict__ It, in
 }
 
 // ------------------------------------------------------------------ compact
-// One tile = NB chunks of 16 bytes of the dirty byte map.  Each thread turns
-// its chunk into a 16-bit mask of dirty pairs; a block-wide scan of the mask
-// popcounts (wave prefix sums staged in LDS) places the pair ids, ascending
-// within the tile, after a single global atomicAdd per tile.  Chunks are
-// cleared as they are read.
+// A tile = one 16-byte chunk of the dirty byte map per thread of a block.
+// Each thread turns its chunk into a 16-bit mask of dirty pairs; a
+// block-wide scan of the mask popcounts (wave prefix sums staged in LDS)
+// places the pair ids, ascending, in the frontier list.  Listed bytes are
+// cleared.
+
 // Inverse of nonzero_bytes4 for 0/1 bytes: bit b of the low nibble -> byte b.
 __device__ __forceinline__ uint32_t spread_bytes4(uint32_t m) {
     return (m & 1u) | ((m & 2u) << 7) | ((m & 4u) << 14) | ((m & 8u) << 21);
@@ -631,35 +632,30 @@ __device__ __forceinline__ uint32_t nonzero_bytes4(uint32_t w) {
     return ((hb >> 7) & 1u) | ((hb >> 14) & 2u) | ((hb >> 21) & 4u) | ((hb >> 28) & 8u);
 }
 
-// A super-tile is C consecutive tiles of NB chunks: the counts of all C
-// tiles are scanned first, then one global atomicAdd reserves the whole
-// super-tile's slots (device-scope atomics execute at the memory side and
-// serialise on the single counter, so fewer is better), then the ids are
-// written in ascending order.
-// Bucket order (BK): only dirty pairs whose state key equals `thr` (every
-// dirty pair if thr == kAllBuckets) are listed and cleared; the others stay
-// in the map for a later round.
+// Bucket order: only dirty pairs whose state key lies in [lo, hi] are
+// listed and cleared; the others stay in the map for a later round.
 constexpr uint32_t kNoBucket = 0xFFFFFFFFu;
-constexpr uint32_t kAllBuckets = 0xFFFFFFFEu;
 constexpr int kBuckets = 65536;
 
 struct BucketSel {
     const uint16_t* key;
-    uint32_t thr;
+    uint32_t lo, hi;
     uint32_t K;
 };
 
-template <int NB, int C, bool BK = false>
+// Persistent-kernel compaction of one super-tile of C tiles of NB chunks:
+// the counts of all C tiles are scanned first, then one global atomicAdd
+// reserves the super-tile's slots, then the ids are written in ascending
+// order and the chunks cleared.
+template <int NB, int C>
 __device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_t nchunks, int64_t stile,
-                                             uint32_t* __restrict__ list, uint32_t* cnt, int* s_w, uint32_t* s_base,
-                                             BucketSel bs = BucketSel{nullptr, 0u, 1u}) {
+                                             uint32_t* __restrict__ list, uint32_t* cnt, int* s_w, uint32_t* s_base) {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     constexpr int NW = NB / kWave;
     const int t = threadIdx.x;
     const int w = t / kWave;
     GBF_GLOBAL u32x4* chunks = reinterpret_cast<GBF_GLOBAL u32x4*>(gp(dirty));
     uint32_t mask[C];
-    uint32_t keep[C];  // BK: dirty pairs left in the map
     int loc[C];
 #pragma unroll
     for (int i = 0; i < C; ++i) {
@@ -668,19 +664,6 @@ __device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_
         if (ci < nchunks) v = chunks[ci];
         mask[i] = nonzero_bytes4(v.x) | (nonzero_bytes4(v.y) << 4) | (nonzero_bytes4(v.z) << 8) |
                   (nonzero_bytes4(v.w) << 12);
-        keep[i] = 0;
-        if (BK && mask[i]) {
-            const uint32_t p0 = (uint32_t)(ci * 16);
-            uint32_t x = p0 / bs.K, r = p0 - x * bs.K;
-            const GBF_GLOBAL uint16_t* key = gp(bs.key);
-            uint32_t sel = 0;
-            for (int b = 0; b < 16; ++b) {
-                if (((mask[i] >> b) & 1u) && (bs.thr == kAllBuckets || (uint32_t)key[x] == bs.thr)) sel |= 1u << b;
-                if (++r == bs.K) r = 0, ++x;
-            }
-            keep[i] = mask[i] & ~sel;
-            mask[i] = sel;
-        }
         const int c = __popc(mask[i]);
         const int incl = wave_incl_scan(c);
         loc[i] = incl - c;
@@ -710,16 +693,8 @@ __device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_
             uint32_t m = mask[i];
             if (m) {
                 const int64_t ci = (stile * C + i) * NB + t;
-                u32x4 rest = {0u, 0u, 0u, 0u};
-                if (BK) {
-                    // the bytes of pairs left for later stay 1
-                    const uint32_t k = keep[i];
-                    rest.x = spread_bytes4(k);
-                    rest.y = spread_bytes4(k >> 4);
-                    rest.z = spread_bytes4(k >> 8);
-                    rest.w = spread_bytes4(k >> 12);
-                }
-                chunks[ci] = rest;
+                const u32x4 zero = {0u, 0u, 0u, 0u};
+                chunks[ci] = zero;
                 uint32_t pos = base + (uint32_t)loc[i];
                 const uint32_t pbase = (uint32_t)(ci * 16);
                 while (m) {
@@ -733,30 +708,142 @@ __device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_
     __syncthreads();
 }
 
-constexpr int kCompactC = GBF_COMPACT_C;  // tiles per super-tile, 256-thread blocks
 constexpr int kPCompactC = 1;  // tiles per super-tile, 1024-thread blocks
 
-__global__ __launch_bounds__(kBlock) void k_compact(Run R, int round) {
-    __shared__ int s_w[kCompactC * kWavesPerBlock];
-    __shared__ uint32_t s_base;
-    if (round > 0 && R.counts[round - 1] == 0) return;  // frontier already empty
-    uint8_t* cur = R.dirty[round & 1];
-    const int64_t nst = (R.nchunks + kBlock * kCompactC - 1) / (kBlock * kCompactC);
-    for (int64_t st = blockIdx.x; st < nst; st += gridDim.x)
-        compact_tile<kBlock, kCompactC>(cur, R.nchunks, st, R.list, R.counts + round, s_w, &s_base);
+// Selected pairs of one 16-byte chunk (bit b = pair 16*ci + b); BK: `keep`
+// receives the dirty pairs that stay in the map.
+template <bool BK>
+__device__ __forceinline__ uint32_t chunk_select(const uint32_t v4[4], int64_t ci, const BucketSel& bs,
+                                                 uint32_t* keep) {
+    uint32_t m = nonzero_bytes4(v4[0]) | (nonzero_bytes4(v4[1]) << 4) | (nonzero_bytes4(v4[2]) << 8) |
+                 (nonzero_bytes4(v4[3]) << 12);
+    *keep = 0;
+    if (BK && m) {
+        // the 16 pairs belong to consecutive states: one key load per state
+        const uint32_t p0 = (uint32_t)(ci * 16);
+        uint32_t x = p0 / bs.K, r = p0 - x * bs.K;
+        const GBF_GLOBAL uint16_t* key = gp(bs.key);
+        uint32_t sel = 0;
+        int b = 0;
+        while (b < 16) {
+            const uint32_t run = min(16u - (uint32_t)b, bs.K - r);  // pairs of state x in this chunk
+            const uint32_t bits = ((1u << run) - 1u) << b;
+            if (m & bits) {
+                const uint32_t k = key[x];
+                if (k >= bs.lo && k <= bs.hi) sel |= m & bits;
+            }
+            b += (int)run;
+            r = 0;
+            ++x;
+        }
+        *keep = m & ~sel;
+        m = sel;
+    }
+    return m;
 }
 
-// Bucket order, one round: the buckets are drained in ascending key order in
-// sweeps.  The bucket listed next is the lowest occupied one at or above the
-// bucket of the previous round; pairs marked in lower buckets wait for the
-// next sweep, which starts at the lowest occupied bucket.  (Going back down
-// at once would re-evaluate a low bucket after every improvement further
-// up whenever the keys are not exactly in dependency order.)  The selected
-// bucket's flag is cleared: the compaction lists all its pairs, and a later
-// mark sets the flag again.  Past the round cap every pair is listed, so the
-// remaining pairs are dropped and flagged in one round.  No bucket occupied:
-// kNoBucket, nothing is listed.  Words: thr[0] selected bucket, thr[1] the
-// sweep position, thr[2] number of sweeps.
+// Host-loop compaction.  Block b owns the contiguous tiles [t0, t1) of
+// kBlock chunks.  Pass 1 counts the pairs it will list; one atomicAdd per
+// block reserves their slots (device-scope atomics serialise at the memory
+// side, so the grid is kept small); pass 2 re-reads the chunks, now in L2,
+// and writes the ids in ascending order, clearing the listed bytes.
+template <bool BK>
+__device__ __forceinline__ void compact_range(uint8_t* __restrict__ dirty, int64_t nchunks, int64_t t0, int64_t t1,
+                                              uint32_t* __restrict__ list, uint32_t* cnt, const BucketSel& bs) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    __shared__ int s_w[kWavesPerBlock];
+    __shared__ uint32_t s_base;
+    const int t = threadIdx.x;
+    const int w = t / kWave;
+    GBF_GLOBAL u32x4* chunks = reinterpret_cast<GBF_GLOBAL u32x4*>(gp(dirty));
+    int c = 0;
+#pragma unroll 4
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t ci = tile * kBlock + t;
+        if (ci < nchunks) {
+            const u32x4 v = chunks[ci];
+            const uint32_t v4[4] = {v.x, v.y, v.z, v.w};
+            uint32_t keep;
+            c += __popc(chunk_select<BK>(v4, ci, bs, &keep));
+        }
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0) s_w[w] = c;
+    __syncthreads();
+    int total = 0;
+#pragma unroll
+    for (int k = 0; k < kWavesPerBlock; ++k) total += s_w[k];
+    if (total == 0) return;  // block-uniform
+    if (t == 0) s_base = atomicAdd(cnt, (uint32_t)total);
+    __syncthreads();
+    uint32_t off = s_base;
+    GBF_GLOBAL uint32_t* out = gp(list);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t ci = tile * kBlock + t;
+        uint32_t m = 0, keep = 0;
+        if (ci < nchunks) {
+            const u32x4 v = chunks[ci];
+            const uint32_t v4[4] = {v.x, v.y, v.z, v.w};
+            m = chunk_select<BK>(v4, ci, bs, &keep);
+        }
+        const int cc = __popc(m);
+        const int incl = wave_incl_scan(cc);
+        __syncthreads();  // s_w of the previous tile has been read
+        if (lane_id() == kWave - 1) s_w[w] = incl;
+        __syncthreads();
+        int wofs = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < kWavesPerBlock; ++k) {
+            const int vv = s_w[k];
+            wofs += k < w ? vv : 0;
+            tot += vv;
+        }
+        if (m) {
+            u32x4 rest = {0u, 0u, 0u, 0u};
+            if (BK) {
+                rest.x = spread_bytes4(keep);
+                rest.y = spread_bytes4(keep >> 4);
+                rest.z = spread_bytes4(keep >> 8);
+                rest.w = spread_bytes4(keep >> 12);
+            }
+            chunks[ci] = rest;
+            uint32_t pos = off + (uint32_t)(wofs + incl - cc);
+            const uint32_t pbase = (uint32_t)(ci * 16);
+            while (m) {
+                const int b = __ffs(m) - 1;
+                out[pos++] = pbase + (uint32_t)b;
+                m &= m - 1u;
+            }
+        }
+        off += (uint32_t)tot;
+    }
+}
+
+constexpr int kCompactGrid = GBF_COMPACT_GRID;
+
+__global__ __launch_bounds__(kBlock) void k_compact(Run R, int round) {
+    if (round > 0 && R.counts[round - 1] == 0) return;  // frontier already empty
+    const int64_t ntiles = (R.nchunks + kBlock - 1) / kBlock;
+    const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const int64_t t0 = blockIdx.x * per, t1 = min(ntiles, t0 + per);
+    compact_range<false>(R.dirty[round & 1], R.nchunks, t0, t1, R.list, R.counts + round,
+                         BucketSel{nullptr, 0u, 0u, 1u});
+}
+
+// Bucket order, one round: picks the range of buckets [lo, hi] whose dirty
+// pairs the compaction lists (all of them, so those buckets are empty
+// afterwards: their occupancy flags are cleared here, and a later mark sets
+// a flag again).  Two schedules (R.bspan):
+//   bspan >= 1: window.  lo = the lowest occupied bucket, hi = lo + bspan - 1.
+//     Pairs marked below the window are taken in the next round.
+//   bspan == -1: sweeps.  One bucket per round, the lowest occupied one at or
+//     above the previous round's; pairs marked in lower buckets wait for
+//     the next sweep, which starts again at the lowest occupied bucket.
+// Past the round cap every pair is listed, so the remaining pairs are
+// dropped and flagged in one round.  No bucket occupied: lo = kNoBucket and
+// nothing is listed.  Words: thr[0] lo, thr[1] sweep position, thr[2]
+// number of sweeps (window: rounds that found the range empty below the
+// previous one), thr[3] hi.
 __global__ __launch_bounds__(1024) void k_bucket_select(Run R, int round) {
     __shared__ uint32_t s_up, s_all;
     if (round > 0 && R.counts[round - 1] == 0) return;  // frontier already empty
@@ -787,48 +874,54 @@ __global__ __launch_bounds__(1024) void k_bucket_select(Run R, int round) {
     if (up != kNoBucket) atomicMin(&s_up, up);
     if (all != kNoBucket) atomicMin(&s_all, all);
     __syncthreads();
+    uint32_t lo, hi;
+    if (R.bspan < 0) {
+        lo = s_up != kNoBucket ? s_up : s_all;
+        hi = lo;
+    } else {
+        lo = s_all;
+        hi = lo == kNoBucket ? lo : min(lo + (uint32_t)R.bspan - 1u, (uint32_t)kBuckets - 1u);
+    }
+    const bool cap = round >= R.max_rounds;
+    if (lo != kNoBucket && !cap)
+        for (uint32_t b = lo + threadIdx.x; b <= hi; b += blockDim.x) gp(R.occ)[b] = 0;
     if (threadIdx.x == 0) {
-        uint32_t b0 = s_up;
-        if (b0 == kNoBucket && s_all != kNoBucket) {
-            b0 = s_all;  // next sweep
-            thr[2] = (round == 0 ? 0u : thr[2]) + 1u;
-        } else if (round == 0) {
-            thr[2] = 1u;
+        const bool wrap = R.bspan < 0 ? (s_up == kNoBucket && s_all != kNoBucket) : (round > 0 && lo < pos);
+        thr[2] = (round == 0 ? 1u : thr[2]) + (wrap ? 1u : 0u);
+        if (cap) {
+            lo = 0;
+            hi = kBuckets - 1;  // list everything
+        } else if (lo != kNoBucket) {
+            thr[1] = lo;
         }
-        if (round >= R.max_rounds) {
-            b0 = kAllBuckets;
-        } else if (b0 != kNoBucket) {
-            gp(R.occ)[b0] = 0;
-            thr[1] = b0;
-        }
-        thr[0] = b0;
+        thr[0] = lo;
+        thr[3] = hi;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_compact_bucket(Run R, int round) {
-    __shared__ int s_w[kWavesPerBlock];
-    __shared__ uint32_t s_base;
     if (round > 0 && R.counts[round - 1] == 0) return;
-    const uint32_t thr = gp(R.thr)[0];
-    if (thr == kNoBucket) return;
-    const BucketSel bs{R.key, thr, (uint32_t)R.keyK};
-    const int64_t nst = (R.nchunks + kBlock - 1) / kBlock;
-    for (int64_t st = blockIdx.x; st < nst; st += gridDim.x)
-        compact_tile<kBlock, 1, true>(R.dirty[0], R.nchunks, st, R.list, R.counts + round, s_w, &s_base, bs);
+    const uint32_t lo = gp(R.thr)[0], hi = gp(R.thr)[3];
+    if (lo == kNoBucket) return;
+    const BucketSel bs{R.key, lo, hi, (uint32_t)R.keyK};
+    const int64_t ntiles = (R.nchunks + kBlock - 1) / kBlock;
+    const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const int64_t t0 = blockIdx.x * per, t1 = min(ntiles, t0 + per);
+    compact_range<true>(R.dirty[0], R.nchunks, t0, t1, R.list, R.counts + round, bs);
 }
 
 hipError_t launch_bucket_compact(const Run& R, int round, int grid, hipStream_t s) {
     k_bucket_select<<<1, 1024, 0, s>>>(R, round);
     const int64_t ntiles = (R.nchunks + kBlock - 1) / kBlock;
-    int g = (int)std::min<int64_t>(ntiles, grid > 0 ? grid : 2048);
+    int g = (int)std::min<int64_t>(ntiles, grid > 0 ? grid : kCompactGrid);
     if (g < 1) g = 1;
     k_compact_bucket<<<g, kBlock, 0, s>>>(R, round);
     return hipGetLastError();
 }
 
 hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s) {
-    const int64_t ntiles = (R.nchunks + kBlock * kCompactC - 1) / (kBlock * kCompactC);
-    int g = (int)std::min<int64_t>(ntiles, grid > 0 ? grid : 2048);
+    const int64_t ntiles = (R.nchunks + kBlock - 1) / kBlock;
+    int g = (int)std::min<int64_t>(ntiles, grid > 0 ? grid : kCompactGrid);
     if (g < 1) g = 1;
     k_compact<<<g, kBlock, 0, s>>>(R, round);
     return hipGetLastError();

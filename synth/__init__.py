@@ -506,25 +506,26 @@ def grid2d(seed: int, dims=(128, 128), K: int = 4, **kw) -> Problem:
                         avoid_frac=0.10, name=f"grid2d_{'x'.join(map(str, dims))}_k{K}", **kw)
 
 
+def batch_instance(i: int, count: int = 64, with_csr: bool = True) -> Problem:
+    """Instance i of the uneven batch of `count` (see batch_mix)."""
+    q = count // 4
+    s = instance_seed(4, i)
+    if i < q:
+        return grid2d(s, with_csr=with_csr)
+    if i < 2 * q:
+        return grid3d(s, with_csr=with_csr)
+    j = i - 2 * q
+    nj = max(1, count - 2 * q - 1)
+    t = j / nj
+    dims = tuple(int(round(a + (b - a) * t)) for a, b in zip((20, 20, 12, 6), (40, 40, 24, 10)))
+    K = 8 if (j % 2 == 0) else 12
+    return grid4d(s, "i32", dims=dims, K=K, with_csr=with_csr)
+
+
 def batch_mix(count: int = 64, with_csr: bool = True):
     """The uneven batch: 1/4 2-D 128x128 (K=4), 1/4 3-D 48x48x24 (K=6), 1/2
     4-D grids interpolated from 20x20x12x6 to 40x40x24x10 (K alternating 8/12)."""
-    out = []
-    q = count // 4
-    for i in range(count):
-        s = instance_seed(4, i)
-        if i < q:
-            out.append(grid2d(s, with_csr=with_csr))
-        elif i < 2 * q:
-            out.append(grid3d(s, with_csr=with_csr))
-        else:
-            j = i - 2 * q
-            nj = max(1, count - 2 * q - 1)
-            t = j / nj
-            dims = tuple(int(round(a + (b - a) * t)) for a, b in zip((20, 20, 12, 6), (40, 40, 24, 10)))
-            K = 8 if (j % 2 == 0) else 12
-            out.append(grid4d(s, "i32", dims=dims, K=K, with_csr=with_csr))
-    return out
+    return [batch_instance(i, count, with_csr) for i in range(count)]
 
 
 def learned_instance(index: int, with_csr: bool = True, dims=(60, 60, 30, 12)) -> Problem:

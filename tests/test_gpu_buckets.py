@@ -48,6 +48,17 @@ def _keys(prob, ref, kind):
     return np.zeros(n, dtype=np.uint16)
 
 
+@pytest.mark.parametrize("span", [1, 2, 5, 64, -1])
+@pytest.mark.parametrize("kind", ["exact", "coarse", "reversed"])
+def test_bucket_schedules(span, kind):
+    """Every schedule (window of `span` buckets from the lowest occupied one,
+    or ascending sweeps) reaches the same fixed point."""
+    prob = synth.grid4d(synth.instance_seed(54, 0), dims=(12, 10, 6, 4), K=12)
+    ref = oracle.solve(prob)
+    _case(f"bucket schedule span={span} {kind}")
+    _check(prob, ref, _solve_buckets(prob, _keys(prob, ref, kind), bucket_span=span), f"{kind}/{span}")
+
+
 def _solve_buckets(prob, keys, encoding="csr", **kw):
     import torch
     kt = torch.from_numpy(keys.view(np.int16)).cuda()
@@ -148,4 +159,6 @@ def test_buckets_rejects_bad_use():
         gr.solve(order="buckets", bucket_key=kt[:10])
     with pytest.raises(gbf.GbfError):
         gr.solve(order="buckets")  # no key
+    with pytest.raises(gbf.GbfError):
+        gr.solve(order="buckets", bucket_key=kt, bucket_span=-2)
     gr.free()
