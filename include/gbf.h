@@ -105,10 +105,14 @@ typedef struct gbf_problem {
      * derives from the boxes (a superset of pred, allowed by Sect. V-B). */
     int32_t dims[4];
     const uint64_t* box; /* [n*K] */
-    /* GBF_BOX only: 1 = expand the boxes into explicit successor lists on the
-     * device at load time and solve with those (faster, ~8 bytes per
-     * successor more memory); 0 = keep the implicit encoding (Sect. IV-B:
-     * keeping images of F and pred in memory vs recomputing them). */
+    /* GBF_BOX only (Sect. IV-B: keeping images of F and pred in memory vs
+     * recomputing them):
+     *   0 = implicit: successors decoded from the boxes, predecessors
+     *       searched in per-input windows (least memory);
+     *   1 = expand the boxes into explicit successor lists and a reverse
+     *       CSR on the device at load time (~8 bytes per successor);
+     *   2 = successors decoded from the boxes, predecessors from a reverse
+     *       CSR built at load time (~4 bytes per successor). */
     int32_t expand_box;
     int32_t reserved[3];
 } gbf_problem;
@@ -163,7 +167,8 @@ typedef struct gbf_graph gbf_graph;
 /* Validates a problem, copies it to device memory owned by the handle and
  * builds what the solver needs: the reverse adjacency pred (Sect. IV-A,
  * pred(x,u) = { y : x in F(y,u) }) as a pair-level reverse CSR for
- * GBF_CSR, or per-input predecessor windows for GBF_BOX; pairs that can
+ * GBF_CSR (and GBF_BOX with expand_box 1 or 2), or per-input predecessor
+ * windows for GBF_BOX with expand_box 0; pairs that can
  * never improve a value (g = INF, avoid source, or a successor in the avoid
  * set) are pruned.  `hip_stream` is a hipStream_t (NULL = default stream)
  * on which all later work of this handle is ordered.

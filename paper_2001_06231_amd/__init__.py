@@ -254,7 +254,7 @@ def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=
         d = list(dims) + [1] * (4 - len(dims))
         for a in range(4):
             p.dims[a] = int(d[a])
-        p.expand_box = 1 if expand_box else 0
+        p.expand_box = int(expand_box)
     if len(spaces) > 1:
         raise ValueError("problem arrays must all be host arrays or all device tensors")
     p.memspace = spaces.pop() if spaces else HOST
@@ -269,10 +269,14 @@ def load_problem(prob, encoding="csr", stream=None) -> Graph:
     """Loads an object with the fields of an optimal control problem
     (n, K, dtype, G, g, avoid, succ_ptr/succ_idx or dims/box_packed()).
     encoding: "csr" (explicit lists; expanded from the boxes on the device
-    when the object carries no lists), "box" (implicit) or "box->csr"."""
+    when the object carries no lists), "box" (implicit), "box->csr" or
+    "box+rev" (box successors, reverse CSR for the predecessors)."""
+    if encoding == "box+rev":
+        return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="box", avoid=prob.avoid,
+                          dims=prob.dims, box=prob.box_packed(), expand_box=2, stream=stream)
     if encoding == "box->csr" or (encoding == "csr" and getattr(prob, "succ_ptr", None) is None):
         return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="box", avoid=prob.avoid,
-                          dims=prob.dims, box=prob.box_packed(), expand_box=True, stream=stream)
+                          dims=prob.dims, box=prob.box_packed(), expand_box=1, stream=stream)
     if encoding == "csr":
         return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="csr", avoid=prob.avoid,
                           succ_ptr=prob.succ_ptr, succ_idx=prob.succ_idx, stream=stream)

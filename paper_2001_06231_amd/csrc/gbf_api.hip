@@ -168,6 +168,8 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
     if (p->n_states <= 0 || p->n_inputs <= 0) return fail(GBF_EINVAL, "n_states and n_inputs must be positive");
     if (p->dtype != GBF_I32 && p->dtype != GBF_F32) return fail(GBF_EINVAL, "dtype must be GBF_I32 or GBF_F32");
     if (p->encoding != GBF_CSR && p->encoding != GBF_BOX) return fail(GBF_EINVAL, "bad encoding");
+    if (p->encoding == GBF_BOX && (p->expand_box < 0 || p->expand_box > 2))
+        return fail(GBF_EINVAL, "expand_box must be 0, 1 or 2");
     if (p->memspace != GBF_HOST && p->memspace != GBF_DEVICE) return fail(GBF_EINVAL, "bad memspace");
     if (!p->G || !p->g) return fail(GBF_EINVAL, "G and g are required");
     const int64_t n = p->n_states, K = p->n_inputs, np = n * K;
@@ -272,6 +274,9 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
         return fail(GBF_EINVAL, msg);
     }
 
+    // expand_box 2 (HYB): successors stay boxes, predecessors become a
+    // reverse CSR built from a temporary expansion
+    const bool hyb = p->encoding == GBF_BOX && p->expand_box == 2;
     if (p->encoding == GBF_BOX && p->expand_box) {
         // materialise F as successor lists on the device (then as CSR below)
         uint32_t *sizes, *sptr, *tmp;
@@ -296,8 +301,10 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
         M.release(sizes, (np + 1) * 4);
         M.release(tmp, nb * 4);
         M.release(tot64, 8);
-        M.release((void*)I.box, np * 8);
-        I.box = nullptr;
+        if (!hyb) {
+            M.release((void*)I.box, np * 8);
+            I.box = nullptr;
+        }
         I.sptr = sptr;
         I.sidx = sidx;
         I.enc = GBF_CSR;
@@ -329,6 +336,14 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
         if (sptr64) M.release(sptr64, (np + 1) * 8);
         M.release(cnt, (n + 1) * 4);
         M.release(tmp, nb * 4);
+        if (hyb) {
+            M.release(const_cast<uint32_t*>(I.sptr), (np + 1) * 4);
+            M.release(const_cast<int32_t*>(I.sidx), (size_t)m * 4);
+            I.sptr = nullptr;
+            I.sidx = nullptr;
+            I.enc = 2;
+            gr->enc = 2;
+        }
     } else {
         HIPC(launch_prune(I, p->dtype, s));
         int32_t* win;
@@ -385,7 +400,7 @@ static int plan_solve(Scratch& S, const std::vector<Inst>& insts, int dtype, con
         total_pairs = std::max<int64_t>(total_pairs, I.pair_base + I.n * I.K);
         P.max_rounds = std::max<int64_t>(P.max_rounds, I.max_rounds);
         P.max_states = std::max<int64_t>(P.max_states, I.n);
-        P.enc_mask |= I.enc == 0 ? 1 : 2;
+        P.enc_mask |= I.enc == 0 ? 1 : I.enc == 1 ? 2 : 4;
     }
     const int nevents = o.profile ? 2 * (int)std::min<int64_t>(P.max_rounds + 2, 4096) + 2 : 4;
     int rc = ensure_scratch(S, total_pairs, P.max_rounds, P.ninst, nevents);

@@ -28,7 +28,7 @@ struct Inst {
     int64_t pair_base;      // first global pair id
     int64_t max_rounds;     // round cap of this instance
     int32_t K;
-    int32_t enc;            // 0 CSR, 1 BOX
+    int32_t enc;            // 0 CSR, 1 BOX, 2 HYB (box successors, reverse CSR)
     int32_t dims[4];
     int32_t strides[4];
     int32_t index;          // position in the batch

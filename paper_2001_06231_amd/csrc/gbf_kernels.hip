@@ -510,6 +510,18 @@ __device__ __forceinline__ void mark_pair(const Inst& I, uint8_t* __restrict__ d
     }
 }
 
+// Encodings.  Template ENC: 1 = CSR, 2 = BOX, 4 = box successors with a
+// reverse CSR for the predecessors (HYB), 3 = decided per instance from
+// Inst.enc (0 CSR, 1 BOX, 2 HYB).
+template <int ENC>
+__device__ __forceinline__ bool fwd_csr(const Inst& I) {
+    return ENC == 1 || (ENC == 3 && I.enc == 0);
+}
+template <int ENC>
+__device__ __forceinline__ bool rev_csr(const Inst& I) {
+    return ENC == 1 || ENC == 4 || (ENC == 3 && I.enc != 1);
+}
+
 // Whole-wave expansion of one state y (wave-uniform arguments): every live
 // pair (x',u') with y in F(x',u') is marked.  CSR: the (sorted) reverse row
 // of y is streamed by the wave.  BOX: for every input the predecessor
@@ -518,7 +530,7 @@ template <int ENC>
 __device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint8_t* __restrict__ dirty, Acc& acc) {
     const int lane = lane_id();
     const uint32_t base = (uint32_t)I.pair_base;
-    if (ENC == 1 || (ENC == 3 && I.enc == 0)) {
+    if (rev_csr<ENC>(I)) {
         const GBF_GLOBAL uint32_t* rptr = gp(I.rptr);
         const GBF_GLOBAL uint32_t* rev = gp(I.rev);
         const uint32_t s0 = rptr[y], len = rptr[y + 1] - s0;
@@ -967,7 +979,7 @@ __device__ __forceinline__ PairCtx load_pair(const Inst* __restrict__ It, const 
     }
     c.s0 = 0;
     c.len = 0;
-    if (c.valid && (ENC == 1 || (ENC == 3 && I.enc == 0))) {
+    if (c.valid && fwd_csr<ENC>(I)) {
         const GBF_GLOBAL uint32_t* sptr = gp(I.sptr);
         c.s0 = ldx<GBF_NT_MISC>(sptr + c.p);
         c.len = ldx<GBF_NT_MISC>(sptr + c.p + 1) - c.s0;
@@ -996,7 +1008,7 @@ __device__ __forceinline__ void relax_pairs(const Inst* __restrict__ It, const P
     K mx = (K)T::LOWEST;
     uint32_t len = c.len;
     if (c.valid) {
-        if (ENC == 1 || (ENC == 3 && I.enc == 0)) {
+        if (fwd_csr<ENC>(I)) {
             const GBF_GLOBAL int32_t* row = gp(I.sidx) + c.s0;
             uint32_t t = (uint32_t)sub;
             for (; t + G < len; t += 2 * G) {
@@ -1006,19 +1018,25 @@ __device__ __forceinline__ void relax_pairs(const Inst* __restrict__ It, const P
             }
             if (t < len) mx = T::max2(mx, V[ldx<GBF_NT_ROWS>(row + t)]);
         } else {
+            // the box is w1*w2*w3 rows of w0 consecutive cells along axis 0;
+            // the G lanes of the group take the rows in turn
             const BoxDec d = decode_box(ldx<GBF_NT_MISC>(gp(I.box) + c.p));
             const uint32_t w0 = d.e[0] + 1, w1 = d.e[1] + 1, w2 = d.e[2] + 1;
             const uint32_t lo = (uint32_t)d.lo, st1 = (uint32_t)I.strides[1], st2 = (uint32_t)I.strides[2],
                            st3 = (uint32_t)I.strides[3];
-            len = w0 * w1 * w2 * (uint32_t)(d.e[3] + 1);
-            for (uint32_t t = (uint32_t)sub; t < len; t += G) {
-                const uint32_t rr = t / w0;
-                const uint32_t j0 = t - rr * w0;
-                const uint32_t r2 = rr / w1;
-                const uint32_t j1 = rr - r2 * w1;
+            const uint32_t nrows = w1 * w2 * (uint32_t)(d.e[3] + 1);
+            len = w0 * nrows;
+            for (uint32_t r = (uint32_t)sub; r < nrows; r += G) {
+                const uint32_t r2 = r / w1;
+                const uint32_t j1 = r - r2 * w1;
                 const uint32_t j3 = r2 / w2;
                 const uint32_t j2 = r2 - j3 * w2;
-                mx = T::max2(mx, V[lo + j0 + j1 * st1 + j2 * st2 + j3 * st3]);
+                const GBF_GLOBAL K* row = V + (lo + j1 * st1 + j2 * st2 + j3 * st3);
+                K m0 = row[0];
+                if (w0 > 1) m0 = T::max2(m0, row[1]);
+                if (w0 > 2) m0 = T::max2(m0, row[2]);
+                for (uint32_t j0 = 3; j0 < w0; ++j0) m0 = T::max2(m0, row[j0]);
+                mx = T::max2(mx, m0);
             }
         }
     }
@@ -1227,14 +1245,17 @@ static void pick(int G, RelaxFn* rf, PersistFn* pf) {
     }
 }
 
+// enc_mask: bit 0 = some instance uses CSR, bit 1 = BOX, bit 2 = HYB.
 template <class T>
 static void pick_t(bool multi, int enc_mask, int G, RelaxFn* rf, PersistFn* pf) {
     if (multi) {
         if (enc_mask == 1) pick<T, true, 1>(G, rf, pf);
         else if (enc_mask == 2) pick<T, true, 2>(G, rf, pf);
+        else if (enc_mask == 4) pick<T, true, 4>(G, rf, pf);
         else pick<T, true, 3>(G, rf, pf);
     } else {
         if (enc_mask == 2) pick<T, false, 2>(G, rf, pf);
+        else if (enc_mask == 4) pick<T, false, 4>(G, rf, pf);
         else pick<T, false, 1>(G, rf, pf);
     }
 }
@@ -1248,8 +1269,12 @@ hipError_t launch_seed(const Inst* dI, int ninst, const Run& R, int64_t max_stat
                        hipStream_t s) {
     const int grid = grid_for((max_states + kWave - 1) / kWave, kWavesPerBlock, 4096);
     SeedFn f;
-    if (dtype == 1) f = enc_mask == 1 ? k_seed<TF32, 1> : enc_mask == 2 ? k_seed<TF32, 2> : k_seed<TF32, 3>;
-    else f = enc_mask == 1 ? k_seed<TI32, 1> : enc_mask == 2 ? k_seed<TI32, 2> : k_seed<TI32, 3>;
+    if (dtype == 1)
+        f = enc_mask == 1 ? k_seed<TF32, 1> : enc_mask == 2 ? k_seed<TF32, 2> : enc_mask == 4 ? k_seed<TF32, 4>
+                                                                                         : k_seed<TF32, 3>;
+    else
+        f = enc_mask == 1 ? k_seed<TI32, 1> : enc_mask == 2 ? k_seed<TI32, 2> : enc_mask == 4 ? k_seed<TI32, 4>
+                                                                                         : k_seed<TI32, 3>;
     f<<<grid, kBlock, 0, s>>>(dI, ninst, R);
     return hipGetLastError();
 }

@@ -38,6 +38,7 @@ def _small_mix(dtype="i32"):
     out.append((synth.grid4d(s(2), dtype=dtype, dims=(10, 9, 6, 4), K=8), "box->csr"))
     out.append((synth.grid4d(s(3), dtype=dtype, dims=(12, 10, 6, 4), K=12), "csr"))
     out.append((synth.grid4d(s(4), dtype=dtype, dims=(8, 8, 4, 3), K=12), "box"))
+    out.append((synth.grid4d(s(5), dtype=dtype, dims=(11, 9, 5, 4), K=8), "box+rev"))
     return out
 
 
@@ -66,6 +67,13 @@ def _check_batch(items, mode, precision=None, reps=1):
 def test_batch_mixed_int32(mode):
     _case(f"batch mixed int32 {mode}")
     _check_batch(_small_mix("i32"), mode)
+
+
+@pytest.mark.parametrize("mode", ["hostloop", "persistent"])
+def test_batch_all_hybrid(mode):
+    """A batch whose instances all use box successors with a reverse CSR."""
+    _case(f"batch hybrid {mode}")
+    _check_batch([(p, "box+rev") for p, _ in _small_mix("i32")], mode)
 
 
 @pytest.mark.parametrize("mode", ["hostloop", "persistent"])

@@ -94,7 +94,7 @@ def test_buckets_grid2d(kind):
 
 
 @pytest.mark.parametrize("kind", ["exact", "random", "reversed"])
-@pytest.mark.parametrize("encoding", ["csr", "box"])
+@pytest.mark.parametrize("encoding", ["csr", "box", "box+rev"])
 def test_buckets_grid4d_small(kind, encoding):
     prob = synth.grid4d(synth.instance_seed(50, 0), dims=(16, 14, 8, 5), K=16)
     ref = oracle.solve(prob)

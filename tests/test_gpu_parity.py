@@ -113,7 +113,7 @@ def grid2d():
     return prob, oracle.solve(prob)
 
 
-@pytest.mark.parametrize("encoding", ["csr", "box"])
+@pytest.mark.parametrize("encoding", ["csr", "box", "box+rev"])
 @pytest.mark.parametrize("mode", MODES)
 def test_grid2d_64x64(grid2d, encoding, mode):
     prob, ref = grid2d
@@ -127,12 +127,12 @@ def test_grid2d_launch_shapes(grid2d, grid, lanes):
     race would show as a launch-shape dependence)."""
     prob, ref = grid2d
     _case(f"grid2d grid={grid} lanes={lanes}")
-    for enc in ("csr", "box"):
+    for enc in ("csr", "box", "box+rev"):
         _assert_exact(prob, ref, _gpu_solve(prob, enc, "hostloop", grid=grid, lanes=lanes), f"grid{grid}")
         _assert_exact(prob, ref, _gpu_solve(prob, enc, "persistent", grid=grid, lanes=lanes), f"pgrid{grid}")
 
 
-@pytest.mark.parametrize("encoding", ["csr", "box"])
+@pytest.mark.parametrize("encoding", ["csr", "box", "box+rev"])
 def test_grid4d_small(encoding):
     prob = synth.grid4d(synth.instance_seed(2, 11), dims=(14, 12, 8, 5))
     _case(f"grid4d 14x12x8x5 {encoding}")
@@ -146,7 +146,7 @@ def grid4d_full():
     return prob, oracle.solve(prob)
 
 
-@pytest.mark.parametrize("encoding", ["csr", "box"])
+@pytest.mark.parametrize("encoding", ["csr", "box", "box+rev"])
 @pytest.mark.parametrize("mode", MODES)
 def test_grid4d_40x40x24x10_int32(grid4d_full, encoding, mode):
     prob, ref = grid4d_full
@@ -167,7 +167,7 @@ def grid4d_f32():
     return prob, oracle.solve(prob, precision="f32"), oracle.solve(prob, precision="f64")
 
 
-@pytest.mark.parametrize("encoding", ["csr", "box"])
+@pytest.mark.parametrize("encoding", ["csr", "box", "box+rev"])
 def test_grid4d_40x40x24x10_fp32(grid4d_f32, encoding):
     prob, ref32, ref64 = grid4d_f32
     _case(f"grid4d 40x40x24x10 fp32 {encoding}")
