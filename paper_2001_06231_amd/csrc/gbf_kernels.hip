@@ -34,11 +34,20 @@
 #ifndef GBF_PBLOCKS
 #define GBF_PBLOCKS 2  // persistent kernel: 1024-thread blocks per CU
 #endif
+#ifndef GBF_EXP_BATCH
+#define GBF_EXP_BATCH 4  // reverse-row slices of 64 loaded together when expanding a state
+#endif
+#ifndef GBF_ROW_BATCH
+#define GBF_ROW_BATCH 4  // successor indices loaded together per lane (CSR relax)
+#endif
 #ifndef GBF_COMPACT_GRID
 #define GBF_COMPACT_GRID 512  // blocks of a host-loop compaction
 #endif
 
 namespace gbf {
+
+constexpr int kExpBatch = GBF_EXP_BATCH;
+constexpr int kRowBatch = GBF_ROW_BATCH;
 
 template <bool NT, class P>
 __device__ __forceinline__ P ldx(const GBF_GLOBAL P* p) {
@@ -538,11 +547,26 @@ __device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint8_t* 
             acc.expanded += 1;
             acc.marks += len;
         }
-        for (uint32_t t0 = 0; t0 < len; t0 += kWave) {
-            const uint32_t t = t0 + (uint32_t)lane;
-            const bool v = t < len;
-            const uint32_t q = v ? ldx<GBF_NT_MISC>(rev + s0 + t) : 0u;
-            mark_pair(I, dirty, base, q, v);
+        // kExpBatch slices of 64 entries per step: all their reverse
+        // entries, then all their dirty bytes, are loaded before any store
+        for (uint32_t t0 = 0; t0 < len; t0 += kWave * kExpBatch) {
+            uint32_t q[kExpBatch];
+            bool v[kExpBatch];
+#pragma unroll
+            for (int k = 0; k < kExpBatch; ++k) {
+                const uint32_t t = t0 + (uint32_t)(k * kWave + lane);
+                v[k] = t < len;
+                q[k] = v[k] ? ldx<GBF_NT_MISC>(rev + s0 + t) : 0u;
+            }
+            uint8_t b[kExpBatch];
+#pragma unroll
+            for (int k = 0; k < kExpBatch; ++k) b[k] = v[k] ? gp(dirty)[base + q[k]] : (uint8_t)1;
+#pragma unroll
+            for (int k = 0; k < kExpBatch; ++k)
+                if (b[k] == 0) {
+                    gp(dirty)[base + q[k]] = 1;
+                    if (I.key) gp(I.occ)[gp(I.key)[q[k] / (uint32_t)I.K]] = 1;
+                }
         }
         return;
     }
@@ -1009,14 +1033,19 @@ __device__ __forceinline__ void relax_pairs(const Inst* __restrict__ It, const P
     uint32_t len = c.len;
     if (c.valid) {
         if (fwd_csr<ENC>(I)) {
+            // kRowBatch successor indices per lane in flight, then their values
             const GBF_GLOBAL int32_t* row = gp(I.sidx) + c.s0;
-            uint32_t t = (uint32_t)sub;
-            for (; t + G < len; t += 2 * G) {
-                const int32_t y0 = ldx<GBF_NT_ROWS>(row + t), y1 = ldx<GBF_NT_ROWS>(row + t + G);
-                const K v0 = V[y0], v1 = V[y1];
-                mx = T::max2(mx, T::max2(v0, v1));
+            for (uint32_t t = (uint32_t)sub; t < len; t += kRowBatch * G) {
+                int32_t y[kRowBatch];
+#pragma unroll
+                for (int k = 0; k < kRowBatch; ++k) {
+                    const uint32_t tk = t + (uint32_t)(k * G);
+                    y[k] = tk < len ? ldx<GBF_NT_ROWS>(row + tk) : -1;
+                }
+#pragma unroll
+                for (int k = 0; k < kRowBatch; ++k)
+                    if (y[k] >= 0) mx = T::max2(mx, V[y[k]]);
             }
-            if (t < len) mx = T::max2(mx, V[ldx<GBF_NT_ROWS>(row + t)]);
         } else {
             // the box is w1*w2*w3 rows of w0 consecutive cells along axis 0;
             // the G lanes of the group take the rows in turn
