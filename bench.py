@@ -308,7 +308,10 @@ def run(args, pool=None):
         p2 = jobs["grid2d"].get()
         pf = jobs["grid4d_f32"].get()
         extras["grid2d_64x64_i32_csr"] = config_line(p2, "csr")
+        extras["grid4d_384k_i32_box+rev"] = config_line(prob, "box+rev")
+        extras["grid4d_384k_i32_box"] = config_line(prob, "box")
         extras["grid4d_384k_f32_csr"] = config_line(pf, "csr")
+        extras["grid4d_384k_f32_box+rev"] = config_line(pf, "box+rev")
         extras["grid4d_384k_f32_box"] = config_line(pf, "box")
         print("[bench] configs done", file=sys.stderr, flush=True)
         out["configs"] = extras
