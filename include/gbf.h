@@ -203,6 +203,19 @@ int gbf_extract_policy(gbf_graph* g, int32_t* policy_out, int32_t memspace, int6
 int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gbf_opts* opts,
                     void* const* V_outs, gbf_stats* st);
 
+/* Autotuner: times gbf_solve (count == 1) or gbf_solve_batch (count > 1)
+ * on the given handles for each candidate launch configuration (lanes per
+ * pair 2/4/8 x relax grid 4/8/16 blocks per CU in host-loop mode, lanes
+ * 2/4/8 in persistent mode) and writes the fastest into *best (the other
+ * fields are copied from `base`, which may be NULL).  Each candidate runs
+ * one untimed and `reps` (0 = 3) timed solves; the median decides.
+ * best_ms (may be NULL) receives its median solve time.  The handles keep
+ * the last candidate's solve.  The encoding is fixed by the handles: load
+ * an instance in several encodings to choose between them.
+ * Errors: GBF_EINVAL, GBF_EHIP (no candidate ran). */
+int gbf_tune(gbf_graph* const* graphs, int32_t count, const gbf_opts* base, int32_t reps, gbf_opts* best,
+             double* best_ms);
+
 /* Releases a handle (NULL is allowed). */
 void gbf_free_graph(gbf_graph* g);
 

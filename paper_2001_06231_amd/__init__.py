@@ -70,7 +70,7 @@ class _Stats(ctypes.Structure):
         return {k: (getattr(self, k) if k != "reserved" else None) for k, _ in self._fields_ if k != "reserved"}
 
 
-EXPORTS = ("gbf_load_graph", "gbf_solve", "gbf_extract_policy", "gbf_solve_batch", "gbf_free_graph",
+EXPORTS = ("gbf_load_graph", "gbf_solve", "gbf_extract_policy", "gbf_solve_batch", "gbf_tune", "gbf_free_graph",
            "gbf_last_error", "gbf_mlp_create", "gbf_mlp_set_params", "gbf_mlp_get_params", "gbf_mlp_samples",
            "gbf_mlp_forward", "gbf_mlp_grad", "gbf_mlp_train_step", "gbf_mlp_bucket_keys", "gbf_mlp_free")
 MLP_NPARAMS = 4545
@@ -98,6 +98,9 @@ def lib():
             L.gbf_solve_batch.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(_Opts),
                                           ctypes.POINTER(P), P]
             L.gbf_solve_batch.restype = ctypes.c_int
+            L.gbf_tune.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(_Opts), ctypes.c_int32,
+                                   ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_double)]
+            L.gbf_tune.restype = ctypes.c_int
             L.gbf_free_graph.argtypes = [P]
             L.gbf_free_graph.restype = None
             L.gbf_last_error.argtypes = []
@@ -310,6 +313,25 @@ def solve_batch(graphs: Sequence[Graph], V_outs=None, *, mode="auto", max_rounds
     if rc < 0 or (check and rc not in (OK, ENEGCYCLE)):
         raise _err(L, rc)
     return rc, [s.as_dict() for s in st], V_outs
+
+
+_MODE_NAMES = {v: k for k, v in _MODES.items()}
+
+
+def tune(graphs: Sequence[Graph], reps=3, order="plain", bucket_key=None, bucket_span=0):
+    """gbf_tune: the fastest launch configuration for these handles (one
+    instance, or a batch).  Returns (options dict for Graph.solve /
+    solve_batch, median solve ms)."""
+    L = lib()
+    cnt = len(graphs)
+    base = graphs[0]._opts(order, "auto", 0, 0, False, bucket_key, DEVICE, 0, bucket_span)
+    best = _Opts()
+    ms = ctypes.c_double(0.0)
+    hs = (ctypes.c_void_p * cnt)(*[gr._h for gr in graphs])
+    rc = L.gbf_tune(hs, cnt, ctypes.byref(base), int(reps), ctypes.byref(best), ctypes.byref(ms))
+    if rc != OK:
+        raise _err(L, rc)
+    return {"mode": _MODE_NAMES[best.mode], "lanes": best.lanes, "grid": best.grid}, ms.value
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,67 @@
+"""Autotuner: picks the successor encoding and the launch configuration for
+a problem set (one problem, or the instances of a batch).
+
+For each candidate encoding the set is loaded and gbf_tune (include/gbf.h)
+times the launch configurations on the device; the fastest (encoding,
+configuration) wins.  Results can be kept in a JSON cache keyed by the
+shape of the set (grid dims, inputs and value type of every instance), so a
+workload is tuned once.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+from . import load_problem, tune
+
+ENCODINGS = ("csr", "box+rev")
+
+
+def signature(probs) -> str:
+    """Shape of a problem set: dims, inputs and value type per instance."""
+    parts = [f"{tuple(int(d) for d in p.dims)}:{int(p.K)}:{p.dtype}" for p in probs]
+    return hashlib.sha1(";".join(parts).encode()).hexdigest()[:20]
+
+
+def _measure(probs, encoding, reps):
+    graphs = [load_problem(p, encoding=encoding) for p in probs]
+    try:
+        return tune(graphs, reps=reps)
+    finally:
+        for g in graphs:
+            g.free()
+
+
+def _load_cache(path):
+    if path and os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def autotune(probs, encodings=ENCODINGS, reps=3, cache=None, log=None):
+    """Returns {"encoding", "mode", "lanes", "grid", "ms"} for the set.
+    `cache`: path of a JSON file (read and updated), or None."""
+    key = signature(probs)
+    table = _load_cache(cache)
+    if key in table:
+        return table[key]
+    best = None
+    for enc in encodings:
+        if enc != "csr" and any(getattr(p, "box_lo", None) is None for p in probs):
+            continue  # no boxes: only explicit successor lists
+        opts, ms = _measure(probs, enc, reps)
+        if log:
+            log(f"tune {enc}: {opts} {ms:.3f} ms")
+        if best is None or ms < best["ms"]:
+            best = dict(opts, encoding=enc, ms=ms)
+    if best is None:
+        raise ValueError("no encoding could be tuned")
+    if cache:
+        table[key] = best
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return best

@@ -890,3 +890,62 @@ extern "C" int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gb
     if (worst != GBF_OK) fail(worst, "round cap reached in some instance");
     return worst;
 }
+
+// ------------------------------------------------------------------ autotuner
+// Times every candidate launch configuration on the given handles and keeps
+// the fastest: lanes per listed pair {2, 4, 8} x relax grid {4, 8, 16}
+// blocks per CU in host-loop mode, and lanes {2, 4, 8} in persistent mode
+// (its grid is fixed by co-residency).  Each candidate runs one untimed and
+// `reps` timed solves; the median HIP-event solve time decides.  Candidates
+// that fail (e.g. a persistent grid that is not co-resident) are skipped.
+extern "C" int gbf_tune(gbf_graph* const* graphs, int32_t count, const gbf_opts* base, int32_t reps,
+                        gbf_opts* best, double* best_ms) {
+    if (!graphs || count <= 0 || !best) return fail(GBF_EINVAL, "NULL graphs or output, or empty set");
+    for (int i = 0; i < count; ++i)
+        if (!graphs[i]) return fail(GBF_EINVAL, "NULL graph");
+    if (reps <= 0) reps = 3;
+    gbf_opts o = base ? *base : default_opts();
+    o.profile = 0;
+    o.v_memspace = GBF_DEVICE;
+    const int cus = graphs[0]->cus;
+    struct Cand {
+        int mode, lanes, grid;
+    };
+    std::vector<Cand> cands;
+    for (int lanes : {2, 4, 8})
+        for (int per_cu : {4, 8, 16}) cands.push_back({GBF_MODE_HOSTLOOP, lanes, per_cu * cus});
+    if (o.order == GBF_ORDER_PLAIN)
+        for (int lanes : {2, 4, 8}) cands.push_back({GBF_MODE_PERSISTENT, lanes, 0});
+    double best_t = 1e300;
+    gbf_opts bo = o;
+    bool found = false;
+    std::vector<gbf_stats> st(count);
+    for (const Cand& c : cands) {
+        gbf_opts t = o;
+        t.mode = c.mode;
+        t.lanes = c.lanes;
+        t.grid = c.grid;
+        std::vector<double> ms;
+        bool ok = true;
+        for (int r = 0; r <= reps && ok; ++r) {
+            int rc = count == 1 ? gbf_solve(graphs[0], &t, nullptr, st.data())
+                                : gbf_solve_batch(graphs, count, &t, nullptr, st.data());
+            if (rc < 0) ok = false;
+            else if (r > 0) ms.push_back(st[0].solve_ms);
+        }
+        if (!ok) continue;
+        std::sort(ms.begin(), ms.end());
+        const double med = ms[ms.size() / 2];
+        if (med < best_t) {
+            best_t = med;
+            bo = t;
+            found = true;
+        }
+    }
+    if (!found) return fail(GBF_EHIP, "no candidate configuration ran");
+    bo.v_memspace = base ? base->v_memspace : GBF_HOST;
+    bo.profile = base ? base->profile : 0;
+    *best = bo;
+    if (best_ms) *best_ms = best_t;
+    return GBF_OK;
+}

@@ -1,0 +1,49 @@
+"""The autotuner on the device: the configuration it picks solves exactly."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2001_06231_amd as gbf
+import synth
+from paper_2001_06231_amd import autotune
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    gbf.lib()
+
+
+def test_tune_single():
+    print("\n[case] tune single", flush=True)
+    prob = synth.grid4d(synth.instance_seed(60, 0), dims=(12, 10, 6, 4))
+    ref = oracle.solve(prob)
+    g = gbf.load_problem(prob, encoding="csr")
+    opts, ms = gbf.tune([g], reps=2)
+    assert opts["mode"] in ("hostloop", "persistent") and opts["lanes"] in (2, 4, 8) and ms > 0
+    st, _, V = g.solve(**opts)
+    assert st == gbf.OK and np.array_equal(V, ref["V"])
+    g.free()
+
+
+def test_autotune_batch(tmp_path):
+    print("\n[case] autotune batch", flush=True)
+    import torch
+    probs = [synth.grid4d(synth.instance_seed(61, i), dims=(8 + i, 7, 5, 3), K=8) for i in range(4)]
+    cache = str(tmp_path / "t.json")
+    best = autotune.autotune(probs, reps=2, cache=cache)
+    assert best["encoding"] in autotune.ENCODINGS
+    graphs = [gbf.load_problem(p, encoding=best["encoding"]) for p in probs]
+    outs = [torch.empty(p.n, dtype=torch.int32, device="cuda") for p in probs]
+    st, _, _ = gbf.solve_batch(graphs, outs, mode=best["mode"], lanes=best["lanes"], grid=best["grid"])
+    assert st == gbf.OK
+    for p, v in zip(probs, outs):
+        assert np.array_equal(v.cpu().numpy(), oracle.solve(p)["V"])
+    for g in graphs:
+        g.free()
+    assert autotune.autotune(probs, cache=cache) == best

@@ -1,0 +1,44 @@
+"""Host logic of the autotuner: signatures, encoding choice and the JSON
+cache (the device timing is replaced by a stub)."""
+import json
+
+import synth
+from paper_2001_06231_amd import autotune as T
+
+
+def test_signature_depends_on_shape_only():
+    a = synth.grid2d_small()
+    b = synth.grid2d_small(seed=synth.instance_seed(1, 5))
+    c = synth.grid3d(synth.instance_seed(1, 6), dims=(8, 6, 4), K=6)
+    assert T.signature([a]) == T.signature([b])
+    assert T.signature([a]) != T.signature([c])
+    assert T.signature([a, c]) != T.signature([c, a])
+
+
+def test_choice_and_cache(tmp_path, monkeypatch):
+    calls = []
+
+    def fake(probs, enc, reps):
+        calls.append(enc)
+        return ({"mode": "hostloop", "lanes": 4 if enc == "csr" else 2, "grid": 2048},
+                {"csr": 5.0, "box+rev": 4.0}[enc])
+
+    monkeypatch.setattr(T, "_measure", fake)
+    probs = [synth.grid2d_small()]
+    cache = str(tmp_path / "tune.json")
+    best = T.autotune(probs, cache=cache)
+    assert best["encoding"] == "box+rev" and best["lanes"] == 2 and best["ms"] == 4.0
+    assert calls == ["csr", "box+rev"]
+    table = json.load(open(cache))
+    assert table[T.signature(probs)] == best
+    again = T.autotune(probs, cache=cache)
+    assert again == best and calls == ["csr", "box+rev"]  # served from the cache
+
+
+def test_lists_only_problem_skips_box(monkeypatch):
+    prob = synth.explicit_problem(2, 1, [[1], [1]], [1, 0], [2**31 - 1, 0])
+    seen = []
+    monkeypatch.setattr(T, "_measure", lambda p, e, r: (seen.append(e) or ({"mode": "hostloop", "lanes": 4,
+                                                                            "grid": 0}, 1.0)))
+    assert T.autotune([prob])["encoding"] == "csr"
+    assert seen == ["csr"]
