@@ -40,6 +40,9 @@
 #ifndef GBF_ROW_BATCH
 #define GBF_ROW_BATCH 4  // successor indices loaded together per lane (CSR relax)
 #endif
+#ifndef GBF_ILP
+#define GBF_ILP 1  // wave steps whose gathers a host-loop relax wave keeps in flight together (2+ measured slower)
+#endif
 #ifndef GBF_COMPACT_GRID
 #define GBF_COMPACT_GRID 512  // blocks of a host-loop compaction
 #endif
@@ -48,6 +51,7 @@ namespace gbf {
 
 constexpr int kExpBatch = GBF_EXP_BATCH;
 constexpr int kRowBatch = GBF_ROW_BATCH;
+constexpr int kILP = GBF_ILP;
 
 template <bool NT, class P>
 __device__ __forceinline__ P ldx(const GBF_GLOBAL P* p) {
@@ -1011,17 +1015,23 @@ __device__ __forceinline__ PairCtx load_pair(const Inst* __restrict__ It, const 
     return c;
 }
 
-// Relaxes the pairs of one wave step (64/G pairs, G lanes each).
+// What a lane group gathered for its pair: the running max over the
+// successors (this lane's share), W(x), the raw cost and |F(x,u)|.
+template <class T>
+struct PairVal {
+    typename T::key_t mx, cur;
+    int32_t graw;
+    uint32_t len;
+};
+
+// Gather phase of one wave step (64/G pairs, G lanes each): loads only, so
+// the gathers of several wave steps can be in flight together.
 template <class T, bool MULTI, int ENC, int G>
-__device__ __forceinline__ void relax_pairs(const Inst* __restrict__ It, const PairCtx& c, int round,
-                                            uint8_t* __restrict__ next, Acc& acc) {
+__device__ __forceinline__ PairVal<T> pair_gather(const Inst* __restrict__ It, const PairCtx& c) {
     using K = typename T::key_t;
-    constexpr int W = kWave / G;
-    const int lane = lane_id();
-    const int sub = lane & (G - 1);
-    const int grp = lane / G;
+    const int sub = lane_id() & (G - 1);
     const Inst& I = It[c.ii];
-    GBF_GLOBAL K* V = gp(static_cast<K*>(I.V));
+    const GBF_GLOBAL K* V = gp(static_cast<const K*>(I.V));
     const uint32_t x = c.p / (uint32_t)I.K;
     K cur = (K)T::INF;
     int32_t graw = 0;
@@ -1069,7 +1079,26 @@ __device__ __forceinline__ void relax_pairs(const Inst* __restrict__ It, const P
             }
         }
     }
-    mx = group_max<T, G>(mx);
+    return PairVal<T>{mx, cur, graw, len};
+}
+
+// Commit phase: max over the group, backup, one candidate per state, strict
+// improvement, expansion.
+template <class T, bool MULTI, int ENC, int G>
+__device__ __forceinline__ void pair_commit(const Inst* __restrict__ It, const PairCtx& c, const PairVal<T>& pv,
+                                            uint8_t* __restrict__ next, Acc& acc) {
+    using K = typename T::key_t;
+    constexpr int W = kWave / G;
+    const int lane = lane_id();
+    const int sub = lane & (G - 1);
+    const int grp = lane / G;
+    const Inst& I = It[c.ii];
+    GBF_GLOBAL K* V = gp(static_cast<K*>(I.V));
+    const uint32_t x = c.p / (uint32_t)I.K;
+    const K cur = pv.cur;
+    const int32_t graw = pv.graw;
+    const uint32_t len = pv.len;
+    const K mx = group_max<T, G>(pv.mx);
     // candidate value of this pair (INF if it cannot improve V(x))
     K d = (K)T::INF;
     if (c.valid) {
@@ -1121,17 +1150,26 @@ __device__ __forceinline__ void relax_pairs(const Inst* __restrict__ It, const P
     }
 }
 
-template <class T, bool MULTI, int ENC, int G>
+// One round over the listed pairs.  Each wave takes ILP consecutive wave
+// steps at a time: their loads are issued before any commit, so ILP times
+// as many gathers are in flight per wave.
+template <class T, bool MULTI, int ENC, int G, int ILP>
 __device__ __forceinline__ void relax_round(const Inst* __restrict__ It, const int64_t* bases, const Run& R,
                                             uint32_t count, int round, Acc& acc) {
     constexpr uint32_t W = kWave / G;  // pairs per wave and step
     uint8_t* next = R.dirty[(round + 1) & 1];
     const uint32_t wpb = blockDim.x / kWave;
     const uint32_t wave = blockIdx.x * wpb + threadIdx.x / kWave;
-    const uint32_t stride = gridDim.x * wpb * W;
-    for (uint32_t first = wave * W; first < count; first += stride) {
-        const PairCtx c = load_pair<MULTI, ENC, G>(It, bases, R, count, first, round);
-        relax_pairs<T, MULTI, ENC, G>(It, c, round, next, acc);
+    const uint32_t stride = gridDim.x * wpb * W * ILP;
+    for (uint32_t first = wave * W * ILP; first < count; first += stride) {
+        PairCtx c[ILP];
+        PairVal<T> v[ILP];
+#pragma unroll
+        for (int i = 0; i < ILP; ++i) c[i] = load_pair<MULTI, ENC, G>(It, bases, R, count, first + i * W, round);
+#pragma unroll
+        for (int i = 0; i < ILP; ++i) v[i] = pair_gather<T, MULTI, ENC, G>(It, c[i]);
+#pragma unroll
+        for (int i = 0; i < ILP; ++i) pair_commit<T, MULTI, ENC, G>(It, c[i], v[i], next, acc);
     }
 }
 
@@ -1147,7 +1185,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(const Inst* __restrict__ It, R
     __shared__ AccLds s_acc;
     acc_init(s_acc);
     Acc acc;
-    relax_round<T, MULTI, ENC, G>(It, s_bases, R, count, round, acc);
+    relax_round<T, MULTI, ENC, G, kILP>(It, s_bases, R, count, round, acc);
     flush_acc(acc, s_acc, R.slots);
 }
 
@@ -1244,7 +1282,7 @@ void k_persistent(const Inst* __restrict__ It, Run R) {
             if (blockIdx.x == 0 && threadIdx.x == 0) R.result[0] = round;
             break;
         }
-        relax_round<T, MULTI, ENC, G>(It, s_bases, R, count, round, acc);
+        relax_round<T, MULTI, ENC, G, 1>(It, s_bases, R, count, round, acc);
         fold_acc(acc, s_acc);
         t0 = wall_clock64();
         const bool ok2 = grid_barrier(R.barrier, R.error, gridDim.x, R.timeout_ticks);
