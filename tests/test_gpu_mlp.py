@@ -239,3 +239,32 @@ def test_learned_keys_drive_exact_solve():
           f"rounds {st['rounds']} vs {st_p['rounds']}", flush=True)
     g.free()
     net.free()
+
+
+@pytest.mark.timeout(600)
+def test_learned_order_full_size():
+    """The learned-ordering workload at full size (60x60x30x12, 16 inputs,
+    1.296 M cells; held-out instance 1000) with the trained weights and the
+    default bucket window: values and policy equal the oracle's everywhere,
+    and the relaxation count is below the plain order's."""
+    _case("learned order, full size")
+    import torch
+    prob = synth.learned_instance(1000, with_csr=False)
+    ref = oracle.solve(prob)
+    print("oracle done", flush=True)
+    net = gbf.MLP(learn.load_params())
+    g = gbf.load_problem(prob, encoding="csr")
+    keys, _ = net.bucket_keys(prob.dims, learn.target_centre(prob), learn.SCALE, learn.WIDTH)
+    V = torch.empty(prob.n, dtype=torch.int32, device="cuda")
+    status, st, _ = g.solve(V, order="buckets", bucket_key=keys)
+    pol, res = g.policy()
+    assert status == gbf.OK and st["fallback"] == 0 and res == 0
+    Vh = V.cpu().numpy()
+    bad = np.nonzero(Vh != ref["V"])[0]
+    assert bad.size == 0, (bad[:8], Vh[bad[:8]], ref["V"][bad[:8]])
+    assert np.array_equal(pol, ref["policy"])
+    _, st_p, _ = g.solve(V)
+    print(f"edge relaxations: learned {st['edge_relax']} plain {st_p['edge_relax']}", flush=True)
+    assert st["edge_relax"] < st_p["edge_relax"]
+    g.free()
+    net.free()
