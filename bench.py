@@ -263,8 +263,9 @@ def run(args, pool=None):
 
     ms_per_step = 1e3 * elapsed / args.steps
     edges = float(np.mean([s["edge_relax"] for s in stats]))
-    mode_used = "persistent" if stats[0]["mode_used"] == gbf.MODE_PERSISTENT else "hostloop"
-    kernel = "k_persistent" if mode_used == "persistent" else "k_relax"
+    mode_used = {gbf.MODE_PERSISTENT: "persistent", gbf.MODE_SINGLE_BLOCK: "single_block"}.get(
+        stats[0]["mode_used"], "hostloop")
+    kernel = {"persistent": "k_persistent", "single_block": "k_single"}.get(mode_used, "k_relax")
     launches = sum(s["relax_launches"] for s in stats)
     kern_ms = sum(s["relax_ms"] for s in stats) / max(1, launches)
     total_bytes = sum(algorithmic_bytes(s, prob.npairs, mode_used, s["rounds"]) for s in stats)
@@ -405,7 +406,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="auto", choices=["persistent", "hostloop", "auto"])
+    ap.add_argument("--mode", default="auto", choices=["persistent", "hostloop", "single_block", "auto"])
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")

@@ -70,9 +70,10 @@ extern "C" {
 #define GBF_ORDER_BUCKETS 1 /* frontier drained in ascending bucket key */
 #define GBF_BUCKET_SPAN_DEFAULT 32
 
-#define GBF_MODE_AUTO 0       /* currently the host loop (faster on MI355X) */
+#define GBF_MODE_AUTO 0       /* single block up to 65536 pairs (one instance), else host loop */
 #define GBF_MODE_HOSTLOOP 1   /* one launch sequence per round from the host */
 #define GBF_MODE_PERSISTENT 2 /* all rounds in one cooperative launch */
+#define GBF_MODE_SINGLE_BLOCK 3 /* all rounds in one workgroup (small single instances) */
 
 /* policy sentinels (Algorithm 1 leaves mu(x) = U for such states) */
 #define GBF_HANDOVER (-1) /* V(x) = G(x): hand over now */

@@ -27,11 +27,12 @@ I32, F32 = 0, 1
 CSR, BOX = 0, 1
 HOST, DEVICE = 0, 1
 ORDER_PLAIN, ORDER_BUCKETS = 0, 1
-MODE_AUTO, MODE_HOSTLOOP, MODE_PERSISTENT = 0, 1, 2
+MODE_AUTO, MODE_HOSTLOOP, MODE_PERSISTENT, MODE_SINGLE_BLOCK = 0, 1, 2, 3
 HANDOVER, NONE = -1, -2
 INF_I32 = 2**31 - 1
 
-_MODES = {"auto": MODE_AUTO, "hostloop": MODE_HOSTLOOP, "persistent": MODE_PERSISTENT}
+_MODES = {"auto": MODE_AUTO, "hostloop": MODE_HOSTLOOP, "persistent": MODE_PERSISTENT,
+          "single_block": MODE_SINGLE_BLOCK}
 _ORDERS = {"plain": ORDER_PLAIN, "buckets": ORDER_BUCKETS}
 
 

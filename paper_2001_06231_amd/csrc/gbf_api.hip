@@ -24,6 +24,13 @@ static thread_local std::string t_err;
 #endif
 constexpr int kPersistentBlocksPerCU = GBF_PBLOCKS;
 
+// AUTO solves a single instance with at most this many (x,u) pairs in one
+// workgroup (measured crossover on MI355X).
+#ifndef GBF_SINGLE_BLOCK_MAX_PAIRS
+#define GBF_SINGLE_BLOCK_MAX_PAIRS 65536
+#endif
+constexpr int64_t kSingleBlockMaxPairs = GBF_SINGLE_BLOCK_MAX_PAIRS;
+
 static int fail(int code, const std::string& msg) {
     t_err = msg;
     return code;
@@ -424,7 +431,8 @@ static int plan_solve(Scratch& S, const std::vector<Inst>& insts, int dtype, con
         // one byte map: the selection leaves unlisted pairs in place and the
         // relax step marks into the same map
         if (P.ninst != 1) return fail(GBF_EINVAL, "bucket order is for single solves");
-        if (o.mode == GBF_MODE_PERSISTENT) return fail(GBF_EINVAL, "bucket order runs in host-loop mode");
+        if (o.mode == GBF_MODE_PERSISTENT || o.mode == GBF_MODE_SINGLE_BLOCK)
+            return fail(GBF_EINVAL, "bucket order runs in host-loop mode");
         if (o.bucket_span < -1) return fail(GBF_EINVAL, "bucket_span must be >= -1");
         R.dirty[1] = R.dirty[0];
         R.key = insts[0].key;
@@ -444,6 +452,14 @@ static int plan_solve(Scratch& S, const std::vector<Inst>& insts, int dtype, con
                   ? o.lanes
                   : 4;
     P.mode = P.bucket ? GBF_MODE_HOSTLOOP : o.mode;
+    if (P.mode == GBF_MODE_SINGLE_BLOCK && P.ninst != 1)
+        return fail(GBF_EINVAL, "single-block mode solves one instance");
+    if (P.mode == GBF_MODE_AUTO && P.ninst == 1 && total_pairs <= kSingleBlockMaxPairs)
+        P.mode = GBF_MODE_SINGLE_BLOCK;  // measured: fastest below this size
+    if (P.mode == GBF_MODE_SINGLE_BLOCK) {
+        P.grid = 1;
+        return GBF_OK;
+    }
     if (P.mode != GBF_MODE_HOSTLOOP) {
         const int per_cu = persistent_blocks_per_cu(R, P.lanes, dtype, P.enc_mask);
         if (per_cu <= 0) {
@@ -514,7 +530,7 @@ static void read_host(const Scratch& S, const Plan& P, SolveOut& out, bool round
     out.sweeps = P.bucket ? host[8] : 0;
     out.mode = P.mode;
     out.grid = P.grid;
-    out.block = P.mode == GBF_MODE_PERSISTENT ? 1024 : 256;
+    out.block = P.mode == GBF_MODE_HOSTLOOP ? 256 : 1024;
     out.lanes = P.lanes;
 }
 
@@ -578,6 +594,21 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
     HIPC(hipEventRecord(S.events[0], s));
     HIPC(hipMemcpyAsync(S.dinst, insts.data(), sizeof(Inst) * P.ninst, hipMemcpyHostToDevice, s));
     if ((rc = enqueue_init(S, P, insts, s))) return rc;
+    if (P.mode == GBF_MODE_SINGLE_BLOCK) {
+        if (o.profile) HIPC(hipEventRecord(S.events[2], s));
+        HIPC(launch_single(S.dinst, P.R, P.lanes, dtype, P.enc_mask, s));
+        if (o.profile) HIPC(hipEventRecord(S.events[3], s));
+        if ((rc = enqueue_readback(S, P, s))) return rc;
+        HIPC(hipStreamSynchronize(s));
+        read_host(S, P, out, true, clock_khz);
+        if (o.profile) {
+            float ms = 0;
+            HIPC(hipEventElapsedTime(&ms, S.events[2], S.events[3]));
+            out.relax_ms = ms;
+            out.relax_launches = 1;
+        }
+        return GBF_OK;
+    }
     if (P.mode == GBF_MODE_PERSISTENT) {
         if (o.profile) HIPC(hipEventRecord(S.events[2], s));
         HIPC(launch_persistent(S.dinst, P.R, P.grid, P.lanes, dtype, P.enc_mask, false, s));

@@ -1084,7 +1084,7 @@ __device__ __forceinline__ PairVal<T> pair_gather(const Inst* __restrict__ It, c
 
 // Commit phase: max over the group, backup, one candidate per state, strict
 // improvement, expansion.
-template <class T, bool MULTI, int ENC, int G>
+template <class T, bool MULTI, int ENC, int G, int SCOPE = __HIP_MEMORY_SCOPE_AGENT>
 __device__ __forceinline__ void pair_commit(const Inst* __restrict__ It, const PairCtx& c, const PairVal<T>& pv,
                                             uint8_t* __restrict__ next, Acc& acc) {
     using K = typename T::key_t;
@@ -1132,7 +1132,7 @@ __device__ __forceinline__ void pair_commit(const Inst* __restrict__ It, const P
     // wrong: marks are idempotent)
     bool expand = false;
     if (head && T::less(d, cur)) {
-        __hip_atomic_fetch_min(V + x, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_min(V + x, d, __ATOMIC_RELAXED, SCOPE);
         acc.impr += 1;
         expand = true;
     }
@@ -1153,7 +1153,7 @@ __device__ __forceinline__ void pair_commit(const Inst* __restrict__ It, const P
 // One round over the listed pairs.  Each wave takes ILP consecutive wave
 // steps at a time: their loads are issued before any commit, so ILP times
 // as many gathers are in flight per wave.
-template <class T, bool MULTI, int ENC, int G, int ILP>
+template <class T, bool MULTI, int ENC, int G, int ILP, int SCOPE = __HIP_MEMORY_SCOPE_AGENT>
 __device__ __forceinline__ void relax_round(const Inst* __restrict__ It, const int64_t* bases, const Run& R,
                                             uint32_t count, int round, Acc& acc) {
     constexpr uint32_t W = kWave / G;  // pairs per wave and step
@@ -1169,7 +1169,7 @@ __device__ __forceinline__ void relax_round(const Inst* __restrict__ It, const i
 #pragma unroll
         for (int i = 0; i < ILP; ++i) v[i] = pair_gather<T, MULTI, ENC, G>(It, c[i]);
 #pragma unroll
-        for (int i = 0; i < ILP; ++i) pair_commit<T, MULTI, ENC, G>(It, c[i], v[i], next, acc);
+        for (int i = 0; i < ILP; ++i) pair_commit<T, MULTI, ENC, G, SCOPE>(It, c[i], v[i], next, acc);
     }
 }
 
@@ -1293,6 +1293,38 @@ void k_persistent(const Inst* __restrict__ It, Run R) {
     flush_acc(acc, s_acc, R.slots);
 }
 
+// ------------------------------------------------------------------ single block
+// Small instances: all rounds in one 1024-thread workgroup.  The rounds are
+// separated by block barriers only (workgroup-scope ordering; V is updated
+// with workgroup-scope atomics, so the whole solve stays inside one CU's
+// caches), which makes a round cost a few microseconds instead of two
+// kernel launches or a grid barrier.
+template <class T, int ENC, int G>
+__global__ __launch_bounds__(kPBlock) void k_single(const Inst* __restrict__ It, Run R) {
+    __shared__ int s_w[kPBlock / kWave];
+    __shared__ uint32_t s_base;
+    __shared__ AccLds s_acc;
+    acc_init(s_acc);
+    Acc acc;
+    const int64_t ntiles = (R.nchunks + kPBlock - 1) / kPBlock;
+    for (int round = 0;; ++round) {
+        uint8_t* cur = R.dirty[round & 1];
+        for (int64_t tile = 0; tile < ntiles; ++tile)
+            compact_tile<kPBlock, 1>(cur, R.nchunks, tile, R.list, R.counts + round, s_w, &s_base);
+        // compact_tile ends with a block barrier; the count was formed by
+        // device-scope atomics
+        const uint32_t count = __hip_atomic_load(R.counts + round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (count == 0) {
+            if (threadIdx.x == 0) R.result[0] = round;
+            break;
+        }
+        relax_round<T, false, ENC, G, 1, __HIP_MEMORY_SCOPE_WORKGROUP>(It, nullptr, R, count, round, acc);
+        fold_acc(acc, s_acc);
+        __syncthreads();
+    }
+    flush_acc(acc, s_acc, R.slots);
+}
+
 // ------------------------------------------------------------------ dispatch
 // Kernel variants: value type (int32 / fp32 key), single or batched
 // instance table, encoding (1 CSR, 2 BOX, 3 mixed batch) and lanes per pair.
@@ -1343,6 +1375,33 @@ hipError_t launch_seed(const Inst* dI, int ninst, const Run& R, int64_t max_stat
         f = enc_mask == 1 ? k_seed<TI32, 1> : enc_mask == 2 ? k_seed<TI32, 2> : enc_mask == 4 ? k_seed<TI32, 4>
                                                                                          : k_seed<TI32, 3>;
     f<<<grid, kBlock, 0, s>>>(dI, ninst, R);
+    return hipGetLastError();
+}
+
+using SingleFn = void (*)(const Inst*, Run);
+
+template <class T, int ENC>
+static SingleFn pick_single(int G) {
+    switch (G) {
+        case 1: return k_single<T, ENC, 1>;
+        case 2: return k_single<T, ENC, 2>;
+        case 8: return k_single<T, ENC, 8>;
+        case 16: return k_single<T, ENC, 16>;
+        case 32: return k_single<T, ENC, 32>;
+        default: return k_single<T, ENC, 4>;
+    }
+}
+
+template <class T>
+static SingleFn pick_single_t(int enc_mask, int G) {
+    if (enc_mask == 2) return pick_single<T, 2>(G);
+    if (enc_mask == 4) return pick_single<T, 4>(G);
+    return pick_single<T, 1>(G);
+}
+
+hipError_t launch_single(const Inst* dI, const Run& R, int lanes, int dtype, int enc_mask, hipStream_t s) {
+    const SingleFn f = dtype == 1 ? pick_single_t<TF32>(enc_mask, lanes) : pick_single_t<TI32>(enc_mask, lanes);
+    f<<<1, kPBlock, 0, s>>>(dI, R);
     return hipGetLastError();
 }
 

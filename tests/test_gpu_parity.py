@@ -21,6 +21,7 @@ pytestmark = pytest.mark.gpu
 
 INF_I32 = 2**31 - 1
 MODES = ["hostloop", "persistent"]
+SMALL_MODES = MODES + ["single_block"]  # the one-workgroup solver, for small instances
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -55,7 +56,7 @@ def _assert_exact(prob, ref, got, label):
 
 
 # ------------------------------------------------------------------ worked example
-@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("mode", SMALL_MODES)
 def test_fig2_example(mode):
     prob, inputs, facts = golden_io.load("fig2_example.txt")
     _case(f"fig2 {mode}")
@@ -63,7 +64,7 @@ def test_fig2_example(mode):
     _assert_exact(prob, ref, _gpu_solve(prob, mode=mode), "fig2")
 
 
-@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("mode", SMALL_MODES)
 def test_negative_cycle_status(mode):
     prob, _, _ = golden_io.load("negcycle.txt")
     _case(f"negcycle {mode}")
@@ -81,7 +82,7 @@ def test_tiny_potential_form(seed):
     prob = synth.potential_small(6000 + seed, n, K)
     _case(f"tiny potential seed={seed} n={n} K={K}")
     ref = oracle.solve(prob)
-    _assert_exact(prob, ref, _gpu_solve(prob, mode=MODES[seed % 2]), f"tiny{seed}")
+    _assert_exact(prob, ref, _gpu_solve(prob, mode=SMALL_MODES[seed % 3]), f"tiny{seed}")
 
 
 @pytest.mark.parametrize("seed", range(24))
@@ -93,14 +94,14 @@ def test_tiny_arbitrary_costs(seed):
     prob = synth.random_small(7000 + seed, n, K)
     _case(f"tiny arbitrary seed={seed} n={n} K={K}")
     gr = gbf.load_problem(prob)
-    status, stats, V = gr.solve(mode=MODES[seed % 2])
+    status, stats, V = gr.solve(mode=SMALL_MODES[seed % 3])
     try:
         kl, _ = brute.kleene(prob)
     except brute.Diverged:
         assert status == gbf.ENEGCYCLE
         return
     if status == gbf.ENEGCYCLE:
-        status, stats, V = gr.solve(mode=MODES[seed % 2], max_rounds=100 * n)
+        status, stats, V = gr.solve(mode=SMALL_MODES[seed % 3], max_rounds=100 * n)
     assert status == gbf.OK
     assert [math.inf if v == INF_I32 else int(v) for v in V] == kl
     gr.free()
@@ -114,7 +115,7 @@ def grid2d():
 
 
 @pytest.mark.parametrize("encoding", ["csr", "box", "box+rev"])
-@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("mode", SMALL_MODES)
 def test_grid2d_64x64(grid2d, encoding, mode):
     prob, ref = grid2d
     _case(f"grid2d 64x64 {encoding} {mode}")
@@ -133,11 +134,20 @@ def test_grid2d_launch_shapes(grid2d, grid, lanes):
 
 
 @pytest.mark.parametrize("encoding", ["csr", "box", "box+rev"])
-def test_grid4d_small(encoding):
+@pytest.mark.parametrize("mode", ["persistent", "single_block"])
+def test_grid4d_small(encoding, mode):
     prob = synth.grid4d(synth.instance_seed(2, 11), dims=(14, 12, 8, 5))
-    _case(f"grid4d 14x12x8x5 {encoding}")
+    _case(f"grid4d 14x12x8x5 {encoding} {mode}")
     ref = oracle.solve(prob)
-    _assert_exact(prob, ref, _gpu_solve(prob, encoding, "persistent"), "grid4d-small")
+    _assert_exact(prob, ref, _gpu_solve(prob, encoding, mode), "grid4d-small")
+
+
+@pytest.mark.parametrize("lanes", [1, 4, 32])
+def test_single_block_fp32_and_lanes(lanes):
+    prob = synth.grid4d(synth.instance_seed(2, 12), dtype="f32", dims=(12, 10, 6, 4))
+    _case(f"single block fp32 lanes={lanes}")
+    ref = oracle.solve(prob, precision="f32")
+    _assert_exact(prob, ref, _gpu_solve(prob, "csr", "single_block", lanes=lanes), "single-fp32")
 
 
 @pytest.fixture(scope="module")
