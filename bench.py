@@ -45,10 +45,10 @@ def algorithmic_bytes(st, npairs, mode, rounds):
     W(x) 4) + 8 B per edge (successor index 4, W(y) 4);
     expand: 8 B per expanded state (reverse-row bounds) + 5 B per marked
     predecessor pair (reverse entry 4, dirty byte 1);
-    compact (part of the persistent round kernel only): the dirty byte map
+    compact (part of the persistent and single-block kernels only): the dirty byte map
     is read once per round (npairs B) + 4 B per listed pair."""
     b = 20 * st["pair_evals"] + 8 * st["edge_relax"] + 8 * st["expansions"] + 5 * st["marks"]
-    if mode == "persistent":
+    if mode in ("persistent", "single_block"):
         b += (rounds + 1) * npairs + 4 * st["pair_evals"]
     return b
 

@@ -207,7 +207,8 @@ int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gbf_opts* opt
 /* Autotuner: times gbf_solve (count == 1) or gbf_solve_batch (count > 1)
  * on the given handles for each candidate launch configuration (lanes per
  * pair 2/4/8 x relax grid 4/8/16 blocks per CU in host-loop mode, lanes
- * 2/4/8 in persistent mode) and writes the fastest into *best (the other
+ * 2/4/8 in persistent mode, and for one instance of at most 262144 pairs
+ * lanes 2/4/8 in single-block mode) and writes the fastest into *best (the other
  * fields are copied from `base`, which may be NULL).  Each candidate runs
  * one untimed and `reps` (0 = 3) timed solves; the median decides.
  * best_ms (may be NULL) receives its median solve time.  The handles keep

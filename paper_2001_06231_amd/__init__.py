@@ -316,7 +316,7 @@ def solve_batch(graphs: Sequence[Graph], V_outs=None, *, mode="auto", max_rounds
     return rc, [s.as_dict() for s in st], V_outs
 
 
-_MODE_NAMES = {v: k for k, v in _MODES.items()}
+_MODE_NAMES = {v: k for k, v in _MODES.items()}  # includes "single_block"
 
 
 def tune(graphs: Sequence[Graph], reps=3, order="plain", bucket_key=None, bucket_span=0):

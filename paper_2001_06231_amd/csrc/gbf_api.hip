@@ -947,6 +947,9 @@ extern "C" int gbf_tune(gbf_graph* const* graphs, int32_t count, const gbf_opts*
         for (int per_cu : {4, 8, 16}) cands.push_back({GBF_MODE_HOSTLOOP, lanes, per_cu * cus});
     if (o.order == GBF_ORDER_PLAIN)
         for (int lanes : {2, 4, 8}) cands.push_back({GBF_MODE_PERSISTENT, lanes, 0});
+    // one workgroup is only worth timing on small single instances
+    if (o.order == GBF_ORDER_PLAIN && count == 1 && graphs[0]->n * graphs[0]->K <= 4 * kSingleBlockMaxPairs)
+        for (int lanes : {2, 4, 8}) cands.push_back({GBF_MODE_SINGLE_BLOCK, lanes, 0});
     double best_t = 1e300;
     gbf_opts bo = o;
     bool found = false;
