@@ -30,6 +30,9 @@
  *     failing call of the calling thread.
  *   - All device work is ordered on the HIP stream given at load time.
  *     Calls return after their work has completed.
+ *   - A handle must not be used by two threads at once; gbf_solve_batch
+ *     calls are serialised inside the library.  Freeing a handle also drops
+ *     the batch state (and captured HIP graph) of every batch it was in.
  *   - "Memory space" arguments say whether a pointer is host (GBF_HOST) or
  *     device (GBF_DEVICE) memory of the current device.
  */

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -371,9 +372,14 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
     return GBF_OK;
 }
 
+static void forget_batches_of(gbf_graph* g);
+
 extern "C" void gbf_free_graph(gbf_graph* g) {
     if (!g) return;
     (void)hipStreamSynchronize(g->stream);
+    // batch contexts (and their captured graphs) that refer to this handle
+    // would otherwise be reused for a new handle at the same address
+    forget_batches_of(g);
     delete g;
 }
 
@@ -774,7 +780,23 @@ struct BatchCtx {
         if (priv) (void)hipStreamDestroy(priv);
     }
 };
+// Batch contexts by the ordered set of handles.  One lock guards the map;
+// a batch call holds it for its whole duration (a context's scratch and
+// graph are not shared between concurrent calls).
 static std::map<std::vector<gbf_graph*>, std::unique_ptr<BatchCtx>> g_batches;
+static std::mutex g_batches_lock;
+
+static void forget_batches_of(gbf_graph* g) {
+    std::lock_guard<std::mutex> lk(g_batches_lock);
+    for (auto it = g_batches.begin(); it != g_batches.end();) {
+        if (std::find(it->first.begin(), it->first.end(), g) != it->first.end()) {
+            if (it->second->priv) (void)hipStreamSynchronize(it->second->priv);
+            it = g_batches.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
 
 static bool same_opts(const gbf_opts& a, const gbf_opts& b) {
     return a.mode == b.mode && a.max_rounds == b.max_rounds && a.lanes == b.lanes && a.grid == b.grid &&
@@ -828,6 +850,7 @@ extern "C" int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gb
             return fail(GBF_EINVAL, "batch spans streams or devices");
     }
     std::vector<gbf_graph*> key(graphs, graphs + count);
+    std::lock_guard<std::mutex> lk(g_batches_lock);
     auto& ctx = g_batches[key];
     if (!ctx) {
         ctx.reset(new BatchCtx());

@@ -135,3 +135,22 @@ def test_batch64_vs_single_solves(batch64):
         assert np.array_equal(outs[i].cpu().numpy(), ref["V"]), batch64[i].name
     for gr in graphs:
         gr.free()
+
+
+def test_batch_after_free_and_reload():
+    """Freeing the handles of a batch drops its captured graph: a new batch
+    (whose handles may reuse the old addresses) is solved from scratch and
+    exactly."""
+    _case("batch after free and reload")
+    import torch
+    for rep in range(3):
+        items = _small_mix("i32")[:3] if rep % 2 == 0 else _small_mix("i32")[2:]
+        graphs = [gbf.load_problem(p, encoding=e) for p, e in items]
+        outs = [torch.empty(p.n, dtype=torch.int32, device="cuda") for p, _ in items]
+        for _ in range(2):
+            status, stats, _ = gbf.solve_batch(graphs, outs, mode="persistent")
+            assert status == gbf.OK
+            for (p, e), V in zip(items, outs):
+                assert np.array_equal(V.cpu().numpy(), oracle.solve(p)["V"]), (rep, p.name, e)
+        for gr in graphs:
+            gr.free()
