@@ -687,7 +687,10 @@ struct BucketSel {
 // the counts of all C tiles are scanned first, then one global atomicAdd
 // reserves the super-tile's slots, then the ids are written in ascending
 // order and the chunks cleared.
-template <int NB, int C>
+// LOCAL: the whole map is compacted by this one block, tile after tile, so
+// the slots are reserved from a running total in LDS (*s_base, which the
+// caller zeroes) instead of a device-scope atomic on `cnt`.
+template <int NB, int C, bool LOCAL = false>
 __device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_t nchunks, int64_t stile,
                                              uint32_t* __restrict__ list, uint32_t* cnt, int* s_w, uint32_t* s_base) {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -724,7 +727,7 @@ __device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_
         run += tot;
     }
     if (run != 0) {
-        if (t == 0) *s_base = atomicAdd(cnt, (uint32_t)run);
+        if (!LOCAL && t == 0) *s_base = atomicAdd(cnt, (uint32_t)run);
         __syncthreads();
         const uint32_t base = *s_base;
         GBF_GLOBAL uint32_t* out = gp(list);
@@ -743,6 +746,10 @@ __device__ __forceinline__ void compact_tile(uint8_t* __restrict__ dirty, int64_
                     m &= m - 1u;
                 }
             }
+        }
+        if (LOCAL) {
+            __syncthreads();  // every thread has read the base
+            if (t == 0) *s_base = base + (uint32_t)run;
         }
     }
     __syncthreads();
@@ -1309,11 +1316,12 @@ __global__ __launch_bounds__(kPBlock) void k_single(const Inst* __restrict__ It,
     const int64_t ntiles = (R.nchunks + kPBlock - 1) / kPBlock;
     for (int round = 0;; ++round) {
         uint8_t* cur = R.dirty[round & 1];
+        if (threadIdx.x == 0) s_base = 0;
+        __syncthreads();
         for (int64_t tile = 0; tile < ntiles; ++tile)
-            compact_tile<kPBlock, 1>(cur, R.nchunks, tile, R.list, R.counts + round, s_w, &s_base);
-        // compact_tile ends with a block barrier; the count was formed by
-        // device-scope atomics
-        const uint32_t count = __hip_atomic_load(R.counts + round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            compact_tile<kPBlock, 1, true>(cur, R.nchunks, tile, R.list, R.counts + round, s_w, &s_base);
+        const uint32_t count = s_base;  // compact_tile ends with a block barrier
+        if (threadIdx.x == 0) R.counts[round] = count;
         if (count == 0) {
             if (threadIdx.x == 0) R.result[0] = round;
             break;
