@@ -233,11 +233,11 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
     for (int a = 0; a < 4; ++a) gr->dims[a] = I.dims[a];
 
     int rc;
-    int32_t *G, *g, *stamp, *err;
+    int32_t *G, *g, *err;
     uint8_t* avoid;
     void* V;
     if ((rc = M.alloc((void**)&G, n * 4)) || (rc = M.alloc((void**)&g, np * 4)) ||
-        (rc = M.alloc((void**)&avoid, n)) || (rc = M.alloc(&V, n * 4)) || (rc = M.alloc((void**)&stamp, n * 4)) ||
+        (rc = M.alloc((void**)&avoid, n)) || (rc = M.alloc(&V, n * 4)) ||
         (rc = M.alloc((void**)&err, 64)))
         return rc;
     HIPC(hipMemcpyAsync(G, p->G, n * 4, kind, s));
@@ -249,7 +249,6 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
     I.g = g;
     I.avoid = avoid;
     I.V = V;
-    I.stamp = stamp;
 
     int64_t* sptr64 = nullptr;
     if (p->encoding == GBF_CSR) {

@@ -20,7 +20,6 @@ struct Inst {
     const int32_t* g;       // running cost bits [nK] (pruned pairs = INF)
     const uint8_t* avoid;   // [n]
     void* V;                // value words [n] (int32 or fp32 key)
-    int32_t* stamp;         // last round in which the state was expanded [n]
     const int32_t* win;     // BOX: per input 8 ints: min (lo-x) per axis, max (hi-x) per axis
     const uint16_t* key;    // bucket order: bucket key of each state [n], else NULL
     uint8_t* occ;           // bucket order: occupancy flag per bucket [65536]

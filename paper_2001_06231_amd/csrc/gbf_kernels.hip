@@ -485,15 +485,12 @@ hipError_t launch_box_fill(const Inst& I, const uint32_t* sptr, int32_t* sidx, h
 }
 
 // ------------------------------------------------------------------ init
-// W <- G (Algorithm 1 initialisation), avoid cells pinned to INF; stamps
-// cleared.
+// W <- G (Algorithm 1 initialisation), avoid cells pinned to INF.
 template <class T>
 __global__ void k_init(Inst I) {
     auto* V = static_cast<typename T::key_t*>(I.V);
-    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < I.n; x += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < I.n; x += (int64_t)gridDim.x * blockDim.x)
         V[x] = (I.avoid && I.avoid[x]) ? T::INF : T::from_raw(I.G[x]);
-        I.stamp[x] = -1;
-    }
 }
 
 hipError_t launch_init(const Inst* dI, const Inst& I, int dtype, hipStream_t s) {
