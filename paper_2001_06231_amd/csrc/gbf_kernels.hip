@@ -1210,10 +1210,14 @@ static_assert((2 + kBarGroups) * kBarLine * 4 <= 4096, "barrier words exceed the
 __device__ __forceinline__ bool grid_barrier(uint32_t* bar, int32_t* err, uint32_t nblocks, uint64_t timeout_ticks) {
     __shared__ int s_ok;
     // the block barrier completes every wave's stores; one agent-scope
-    // fence per block (not per wave) then publishes them device-wide
+    // release fence per block (not per wave) then publishes them
+    // device-wide, and one acquire fence after the wait makes the other
+    // blocks' stores visible
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
+        // release: this block's stores (completed by the block barrier)
+        // are written back to memory before the arrival is seen
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         int ok = 1;
         uint32_t* top = bar;
         uint32_t* gen_w = bar + kBarLine;
@@ -1247,7 +1251,9 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* bar, int32_t* err, uint32
         }
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
         s_ok = ok;
-        __threadfence();
+        // acquire: stale lines of other blocks' data are dropped before the
+        // block reads again
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     return s_ok != 0;
