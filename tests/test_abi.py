@@ -44,4 +44,37 @@ def test_error_paths_without_gpu_work():
     assert L.gbf_solve(None, None, None, None) == gbf.EINVAL
     assert L.gbf_extract_policy(None, None, 0, None) == gbf.EINVAL
     assert L.gbf_solve_batch(None, 0, None, None, None) == gbf.EINVAL
+    assert L.gbf_tune(None, 0, None, 0, None, None) == gbf.EINVAL
     L.gbf_free_graph(None)
+    # a box problem with an unknown expansion mode is rejected before any
+    # device work
+    p.n_states = 4
+    p.n_inputs = 1
+    p.dtype = gbf.I32
+    p.encoding = gbf.BOX
+    p.memspace = gbf.HOST
+    p.expand_box = 3
+    G = (ctypes.c_int32 * 4)(0, 1, 1, 1)
+    g = (ctypes.c_int32 * 4)(1, 1, 1, 1)
+    p.G = ctypes.cast(G, ctypes.c_void_p)
+    p.g = ctypes.cast(g, ctypes.c_void_p)
+    assert L.gbf_load_graph(ctypes.byref(p), None, ctypes.byref(h)) == gbf.EINVAL
+    assert b"expand_box" in L.gbf_last_error()
+
+
+def test_mlp_error_paths_without_gpu_work():
+    L = gbf.lib()
+    h = ctypes.c_void_p()
+    assert L.gbf_mlp_create(None, None, ctypes.byref(h)) == gbf.EINVAL
+    bad = (ctypes.c_float * gbf.MLP_NPARAMS)()
+    bad[7] = float("nan")
+    assert L.gbf_mlp_create(ctypes.cast(bad, ctypes.c_void_p), None, ctypes.byref(h)) == gbf.EINVAL
+    assert b"non-finite" in L.gbf_last_error()
+    dims = (ctypes.c_int32 * 4)(4, 4, 1, 1)
+    assert L.gbf_mlp_samples(None, dims, 0.0, 0.0, None, 0, 1.0, None, 1, None, None) == gbf.EINVAL
+    assert L.gbf_mlp_forward(None, None, 1, None) == gbf.EINVAL
+    assert L.gbf_mlp_grad(None, None, None, 1, None, 1, None, None, None) == gbf.EINVAL
+    assert L.gbf_mlp_train_step(None, None, None, 1, None, 1, 1e-3, None) == gbf.EINVAL
+    vmin = ctypes.c_float(0)
+    assert L.gbf_mlp_bucket_keys(None, dims, 0.0, 0.0, 1.0, 16.0, None, None, ctypes.byref(vmin)) == gbf.EINVAL
+    L.gbf_mlp_free(None)
