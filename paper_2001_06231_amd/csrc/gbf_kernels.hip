@@ -2,23 +2,27 @@
 //
 // The hot path is one pass of the while loop of Algorithm 1 (Sect. IV-A),
 // restated for a data-parallel machine:
-//   compact : the dirty-pair bitmap of the active frontier is turned into a
-//             list of pair ids (ballot-free popcount scan per block, one
-//             global atomic per block) and cleared;
-//   relax   : for every listed pair (x,u) the max of W over F(x,u) is formed
-//             with all 64 lanes of a wave streaming the concatenated
-//             successor rows of 64 pairs (coalesced reads, per-segment max in
-//             LDS), then d = g(x,u) + max is compared with W(x) and applied
-//             by atomicMin (the strict-improvement update);
-//   expand  : the first improvement of a state in a round marks every pair
-//             (x',u') with that state in F(x',u') in the upcoming frontier's
-//             bitmap (pair-level refinement of pred(x,u), Sect. IV-A).
+//   compact : the dirty-pair byte map of the active frontier is turned into
+//             an ascending list of pair ids (per-thread 16-byte chunks, wave
+//             prefix sums staged in LDS, one global atomic per block) and
+//             the listed bytes are cleared;
+//   relax   : G lanes per listed pair (x,u) form the max of W over F(x,u)
+//             (a CSR row, or the rows of a box along axis 0) and reduce it
+//             with lane shuffles; d = g(x,u) + max is reduced to one
+//             candidate per state of a wave step and applied by atomicMin on
+//             order-preserving words (the strict-improvement update);
+//   expand  : every improved state marks, with plain byte stores, each pair
+//             (x',u') that has it in F(x',u') in the next frontier's byte map
+//             (the reverse CSR row of the state, or the per-input predecessor
+//             windows of the box encoding; pair-level pred of Sect. IV-A).
 // Pairs are the frontier's unit (not states as in the paper's F1 x U): a pair
 // whose successors did not change cannot improve, so only pairs with a
 // changed successor are evaluated.  Any evaluation order reaches the same
 // maximal fixed point (Sect. IV-A: the processing order is irrelevant; the
 // operator is monotone and every pair is re-evaluated after its last
-// successor change).
+// successor change).  That is also what lets the bucket order (a schedule
+// over the byte map driven by per-state keys) change only the work, never
+// the result.
 #include <cstring>
 
 #include "gbf_device.h"
@@ -975,8 +979,8 @@ hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s) {
 // G lanes per listed pair: the group streams the pair's successor row (CSR,
 // coalesced) or walks its box (BOX), folds V[y] into a running max and
 // reduces it across the group with lane shuffles.  The group leader forms
-// d = g(x,u) + max and applies the strict improvement with atomicMin.  The
-// first improvement of a state in a round expands it with the whole wave.
+// d = g(x,u) + max and applies the strict improvement with atomicMin.  Each
+// improved state of a wave step is then expanded by the whole wave.
 template <class T, int G>
 __device__ __forceinline__ typename T::key_t group_max(typename T::key_t v) {
 #pragma unroll
