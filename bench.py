@@ -242,6 +242,10 @@ def run(args, pool=None):
     load_s = time.time() - t0
     V = torch.empty(prob.n, dtype=torch.int32, device="cuda")
     pol = torch.empty(prob.n, dtype=torch.int32, device="cuda")
+    # the other workloads are generated in worker processes; let them finish
+    # first so that they do not compete with the host side of the timed loop
+    for j in jobs.values():
+        j.wait()
 
     def step():
         status, st, _ = graph.solve(V, mode=args.mode, lanes=args.lanes, grid=args.grid, profile=True)
