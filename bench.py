@@ -88,6 +88,19 @@ def _gen_small(kind):
     return synth.grid4d(dtype="f32")
 
 
+class _Done:
+    """A finished job (generation without worker processes)."""
+
+    def __init__(self, value):
+        self.value = value
+
+    def wait(self):
+        pass
+
+    def get(self):
+        return self.value
+
+
 def _median_solve(graph, reps, **kw):
     """Median-time solve over `reps` runs (after one warm-up): stats dict."""
     import numpy as np
@@ -217,11 +230,17 @@ def run(args, pool=None):
     import synth
 
     jobs = {}
-    if pool is not None and not args.no_extras:
-        jobs["learned"] = pool.apply_async(_gen_learned, (1000,))
-        jobs["batch"] = pool.map_async(_gen_batch, range(64))
-        jobs["grid2d"] = pool.apply_async(_gen_small, ("grid2d",))
-        jobs["grid4d_f32"] = pool.apply_async(_gen_small, ("grid4d_f32",))
+    if not args.no_extras:
+        if pool is not None:
+            jobs["learned"] = pool.apply_async(_gen_learned, (1000,))
+            jobs["batch"] = pool.map_async(_gen_batch, range(64))
+            jobs["grid2d"] = pool.apply_async(_gen_small, ("grid2d",))
+            jobs["grid4d_f32"] = pool.apply_async(_gen_small, ("grid4d_f32",))
+        else:
+            jobs["learned"] = _Done(_gen_learned(1000))
+            jobs["batch"] = _Done([_gen_batch(i) for i in range(64)])
+            jobs["grid2d"] = _Done(_gen_small("grid2d"))
+            jobs["grid4d_f32"] = _Done(_gen_small("grid4d_f32"))
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
     t0 = time.time()
@@ -421,7 +440,8 @@ def main():
     ap.add_argument("--learned-eval", type=int, default=0,
                     help="instead: evaluate the trained network on this many held-out instances")
     ap.add_argument("--eval-reps", type=int, default=3)
-    ap.add_argument("--workers", type=int, default=8, help="generator processes")
+    ap.add_argument("--workers", type=int, default=8,
+                    help="generator processes (1 = generate in this process, e.g. under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver has no multi-GPU "
