@@ -16,6 +16,7 @@
 // feeds h1[k] into unit j), b2 [64], W3 [64], b3.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -90,23 +91,133 @@ __device__ __forceinline__ float forward(const float* w, const float f[4], float
 }
 
 // ------------------------------------------------------------------ inference
-// vhat[c] = scale * out(features(c)); per-block minimum into bmin.
+// vhat[c] = scale * out(features(c)) for every cell; per-block minimum into
+// bmin.  Each wave evaluates 32 cells per step with its contractions on the
+// matrix cores, in the orientation units x cells, so that every layer's
+// accumulator is, as it stands, the operand of the next layer:
+//   layer 1  D1 (64 units x 32 cells) = W1 (64 x 4) F^T (4 x 32) + b1, fp32:
+//            per 32-unit block, two v_mfma_f32_32x32x2_f32 over the feature
+//            pairs and one that adds b1 (A = b1, B = 1 in the first half,
+//            A = B = 0 in the second);
+//   layer 2  D2 (64 x 32) = W2 (64 x 64) bf16(relu(D1)) + b2: per output
+//            block, four v_mfma_f32_32x32x16_bf16 steps, accumulator
+//            started at b2; h1 is rounded to bf16 (nearest even), W2 is
+//            the bf16 working copy, the sums are fp32;
+//   layer 3  out = b3 + W3 . relu(D2): fp32 fmas over the 32 units a lane
+//            holds, then one exchange between the two halves of the wave.
+// Operand layouts (wave64, lane l, half h = l/32): v_mfma_f32_32x32x2_f32
+// takes A[i = l%32][k = h] and B[k = h][j = l%32]; v_mfma_f32_32x32x16_bf16
+// takes A[i = l%32][k = 8h + e] and B[k = 8h + e][j = l%32], e = 0..7; both
+// leave accumulator r (0..15) of lane l at D[i = 8(r/4) + 4h + r%4][j = l%32].
+// So lane l always works on cell l%32, and register r of output block b
+// holds unit acc_unit(b, r, h).  The K index of layer 2 is permuted to
+// follow that: step s takes registers 8(s%2)..8(s%2)+7 of D1 block s/2, and
+// the W2 operand is gathered with the same permutation (k_unit).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kCellsPerWave = 32;
+
+__device__ __forceinline__ int acc_unit(int b, int r, int h) { return 32 * b + 8 * (r >> 2) + 4 * h + (r & 3); }
+__device__ __forceinline__ int k_unit(int s, int h, int e) { return acc_unit(s >> 1, 8 * (s & 1) + e, h); }
+
 __global__ __launch_bounds__(256) void k_vhat(const uint16_t* __restrict__ wbf, Grid g, uint32_t n, float scale,
                                               float* __restrict__ vhat, float* __restrict__ bmin) {
-    __shared__ float w[NP];
+    __shared__ float s_b2[H], s_w3[H];
     __shared__ float s_min[256 / kWave];
-    load_weights(wbf, w);
+    for (int i = threadIdx.x; i < H; i += blockDim.x) {
+        s_b2[i] = bf16_to_f32(gp(wbf)[oB2 + i]);
+        s_w3[i] = bf16_to_f32(gp(wbf)[oW3 + i]);
+    }
+    const int lane = lane_id();
+    const int h = lane >> 5, col = lane & 31;
+    // loop-invariant operands in registers
+    float a1w[2][2], a1b[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) a1w[b][t] = bf16_to_f32(gp(wbf)[oW1 + (32 * b + col) * 4 + 2 * t + h]);
+        a1b[b] = h == 0 ? bf16_to_f32(gp(wbf)[oB1 + 32 * b + col]) : 0.f;
+    }
+    const float one_h = h == 0 ? 1.f : 0.f;
+    bf16x8 a2w[2][4];
+#pragma unroll
+    for (int bo = 0; bo < 2; ++bo)
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            s16x8 t;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) t[e] = (short)gp(wbf)[oW2 + (32 * bo + col) * H + k_unit(st, h, e)];
+            a2w[bo][st] = __builtin_bit_cast(bf16x8, t);
+        }
+    const float b3 = bf16_to_f32(gp(wbf)[oB3]);
+    __syncthreads();
+    const uint32_t wv = threadIdx.x / kWave;
     float mn = INFINITY;
-    const uint32_t c = blockIdx.x * 256u + threadIdx.x;
-    if (c < n) {
-        float f[4], h1[H];
-        cell_features(g, c, f);
-        const float v = scale * forward(w, f, h1);
-        gp(vhat)[c] = v;
-        mn = v;
+    const uint32_t cstep = gridDim.x * (256 / kWave) * kCellsPerWave;
+    for (uint32_t c0 = (blockIdx.x * (256 / kWave) + wv) * kCellsPerWave; c0 < n; c0 += cstep) {
+        // keep b2 and W3 in LDS: without this the compiler hoists all 128
+        // of them into registers and the kernel loses occupancy
+        __asm__ volatile("" ::: "memory");
+        const uint32_t c = c0 + (uint32_t)col;
+        float f[4];
+        cell_features(g, c < n ? c : n - 1, f);
+        const float fa = h ? f[1] : f[0], fb = h ? f[3] : f[2];
+        // layer 1
+        f32x16 d1[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            f32x16 z = {};
+            z = __builtin_amdgcn_mfma_f32_32x32x2f32(a1w[b][0], fa, z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_32x32x2f32(a1w[b][1], fb, z, 0, 0, 0);
+            d1[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1b[b], one_h, z, 0, 0, 0);
+        }
+        // layer 2, accumulators started at b2
+        f32x16 d2[2];
+#pragma unroll
+        for (int bo = 0; bo < 2; ++bo)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 v = *reinterpret_cast<const float4*>(&s_b2[32 * bo + 8 * q + 4 * h]);
+                d2[bo][4 * q + 0] = v.x;
+                d2[bo][4 * q + 1] = v.y;
+                d2[bo][4 * q + 2] = v.z;
+                d2[bo][4 * q + 3] = v.w;
+            }
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            bf16x8 x;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float a = d1[st >> 1][8 * (st & 1) + e];
+                x[e] = (__bf16)(a > 0.f ? a : 0.f);  // relu leaves no NaN; nearest even
+            }
+            d2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2w[0][st], x, d2[0], 0, 0, 0);
+            d2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2w[1][st], x, d2[1], 0, 0, 0);
+        }
+        // layer 3
+        float v = 0.f;
+#pragma unroll
+        for (int bo = 0; bo < 2; ++bo)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 w3 = *reinterpret_cast<const float4*>(&s_w3[32 * bo + 8 * q + 4 * h]);
+                const float* wq = &w3.x;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float a = d2[bo][4 * q + t];
+                    v = __builtin_fmaf(wq[t], a > 0.f ? a : 0.f, v);
+                }
+            }
+        v += __shfl_xor(v, 32, kWave);
+        if (h == 0 && c < n) {
+            const float val = scale * (b3 + v);
+            gp(vhat)[c] = val;
+            mn = fminf(mn, val);
+        }
     }
     for (int d = kWave / 2; d > 0; d >>= 1) mn = fminf(mn, __shfl_xor(mn, d, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0) s_min[threadIdx.x / kWave] = mn;
+    if (lane == 0) s_min[wv] = mn;
     __syncthreads();
     if (threadIdx.x == 0) {
         float m = s_min[0];
@@ -400,6 +511,10 @@ struct gbf_mlp {
 namespace {
 int mfail(int code, const std::string& msg) { return gbf::set_error(code, msg); }
 
+#ifndef GBF_VHAT_BLOCKS
+#define GBF_VHAT_BLOCKS 1024
+#endif
+
 #define MHIPC(expr)                                                                                    \
     do {                                                                                               \
         hipError_t e_ = (expr);                                                                        \
@@ -622,7 +737,9 @@ extern "C" int gbf_mlp_bucket_keys(gbf_mlp* m, const int32_t dims[4], float tcx,
         }
         vh = m->scratch_v;
     }
-    const int64_t nb = (n + 255) / 256;
+    // blocks of the key kernel: 4 waves x 32 cells per step, at most
+    // GBF_VHAT_BLOCKS (each block loads the weights into LDS once)
+    const int64_t nb = std::min<int64_t>((n + 127) / 128, GBF_VHAT_BLOCKS);
     if (m->bmin_blocks < nb + 1) {
         if (m->bmin) dfree(m, m->bmin);
         m->bmin = nullptr;
@@ -636,7 +753,7 @@ extern "C" int gbf_mlp_bucket_keys(gbf_mlp* m, const int32_t dims[4], float tcx,
     MHIPC(hipGetLastError());
     k_min<<<1, 1024, 0, m->stream>>>(m->bmin, (int)nb, m->bmin + nb);
     MHIPC(hipGetLastError());
-    k_keys<<<(unsigned)nb, 256, 0, m->stream>>>(vh, m->bmin + nb, (uint32_t)n, width, key_out);
+    k_keys<<<(unsigned)((n + 255) / 256), 256, 0, m->stream>>>(vh, m->bmin + nb, (uint32_t)n, width, key_out);
     MHIPC(hipGetLastError());
     if (vhat_min_out) MHIPC(hipMemcpyAsync(m->host + NP + 4, m->bmin + nb, 4, hipMemcpyDeviceToHost, m->stream));
     MHIPC(hipStreamSynchronize(m->stream));
