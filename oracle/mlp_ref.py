@@ -19,19 +19,18 @@ it by hand:
             0, 65535) as a 16-bit bucket index
 
 The keys are evaluated for every cell of an instance; there the library
-rounds h1 to bfloat16 before the second layer (a bf16 x bf16 product
-summed in fp32, the matrix-core form; the first layer stays fp32).  forward_bf16_hidden does that
-rounding on the fp64 h1, and bf16_hidden_error_bound bounds how far the
-library's fp32 evaluation may land from it, including the cells where fp32
-rounding of a1 can tip h1 to the neighbouring bf16 value.
+feeds h1 to the second layer as two bfloat16 terms (hi + lo, products with
+the bf16 weights summed in fp32: the matrix-core form of an fp32 product).
+split_hidden_error_bound bounds how far that evaluation may land from the
+fp64 forward pass.
 
 Parameter vector layout (4545 values): W1 [64][4] row-major, b1 [64],
 W2 [64][64] row-major (W2[j][k] multiplies h1[k] into unit j), b2 [64],
 W3 [64], b3 [1].
 
 Pins (tests/test_oracle_mlp.py): bf16 rounding against hand-worked ties and
-torch's conversion; the bf16-hidden forward against hand-worked ties in h1
-and torch's conversion, and its bound against an fp32 evaluation; the forward pass against a hand-built network with a
+torch's conversion; the two-term bf16 split against hand-worked values and
+its bound against an emulated fp32 evaluation; the forward pass against a hand-built network with a
 closed-form output and against torch.nn.functional in fp64; the gradient
 against central finite differences and against torch.autograd; Adam
 against its closed-form first step and torch.optim.Adam; the features and
@@ -183,53 +182,35 @@ def out_error_bound(theta_bf16, F):
     return 2.0 * e3
 
 
-def forward_bf16_hidden(theta_bf16, F):
-    """The forward pass with h1 rounded to bfloat16 (from fp32, ties to
-    even) before the second layer; everything else in fp64.  Returns
-    (out, a1)."""
-    W1, b1, W2, b2, W3, b3 = unpack(theta_bf16)
-    F = np.asarray(F, dtype=np.float64)
-    a1 = F @ W1.T + b1
-    h1 = bf16_round(np.maximum(a1, 0.0).astype(np.float32)).astype(np.float64)
-    h2 = np.maximum(h1 @ W2.T + b2, 0.0)
-    return h2 @ W3 + b3[0], a1
 
+def split_hidden_error_bound(theta_bf16, F):
+    """A bound on |library out - forward out| per row of F for the per-cell
+    key evaluation, which works as follows: each feature takes two fp32
+    roundings (a subtraction and a division); a1 is formed from them in fp32
+    in any order (4 products and 5 additions, each rounded at most once);
+    h1 = relu(a1) enters the second layer as two bf16 terms hi = bf16(h1),
+    lo = bf16(h1 - hi), whose products with the bf16 weights are exact and
+    are summed with b2 in fp32 in any order; the third layer is fp32 in any
+    order.
 
-def bf16_hidden_error_bound(theta_bf16, F):
-    """A bound on |library out - forward_bf16_hidden out| per row of F, for a
-    library that forms each feature with two fp32 roundings (a subtraction
-    and a division), forms a1 from them in fp32 in any order (4 products and
-    5 additions, each rounded at most once), rounds relu(a1) to bf16, and
-    sums the exact bf16 products of the later layers in fp32, in any order.
-
-    With u = 2^-24 the library's a1 then lies within e1 = 3 NIN u |a1|_abs
-    of the exact a1 (|.|_abs: the same sum over absolute values; 11 u to
-    first order, 12 u leaves room for the second-order terms).  Rounding to
-    fp32 and then to bf16 are both monotone, so the library's h1 lies
-    between the bf16 values of relu(a1 - e1) and relu(a1 + e1); where these
-    differ the unit may land one bf16 step away from the reference, an
-    error dh1 that is carried through |W2| and |W3| as it stands.  The fp32
-    sums of the later layers add (H+2) u times their absolute magnitude.  A
-    factor 2 covers the second-order terms."""
+    With u = 2^-24, exact activations h1, h2 (fp64 forward pass) and |.| of
+    weights taken elementwise:
+      a1:  within e1 = 3 NIN u (|F| |W1|^T + |b1|) (11 u to first order);
+      h1:  relu is 1-Lipschitz and |h1 - hi - lo| <= 2^-16 |h1| (hi is h1 to
+           8 significant bits, lo the rest to 8 more), so hi + lo is within
+           eh = e1 + 2^-16 (h1 + e1) of the exact h1;
+      a2:  2H + 1 fp32 additions of terms whose absolute sum is at most
+           m2 = (1 + 2^-8) |W2| (h1 + e1) + |b2|: e2 = (2H + 2) u m2 + |W2| eh;
+      out: m3 = |W3| (h2 + e2) + |b3|: e3 = (H + 2) u m3 + |W3| e2.
+    A factor 2 covers the second-order terms."""
     W1, b1, W2, b2, W3, b3 = unpack(theta_bf16)
     u = 2.0 ** -24
     F = np.asarray(F, dtype=np.float64)
-    a1 = F @ W1.T + b1
+    _, (_, a1, h1, a2, h2) = forward(theta_bf16, F)
     e1 = 3 * NIN * u * (np.abs(F) @ np.abs(W1).T + np.abs(b1))
-
-    def hb(x):
-        return bf16_round(np.maximum(x, 0.0).astype(np.float32)).astype(np.float64)
-
-    ref, lo, hi = hb(a1), hb(a1 - e1), hb(a1 + e1)
-    dh1 = np.maximum(hi - ref, ref - lo)
-    m2 = hi @ np.abs(W2).T + np.abs(b2)
-    e2 = (H + 2) * u * m2 + dh1 @ np.abs(W2).T
-    m3 = m2 @ np.abs(W3) + abs(b3[0])
+    eh = e1 + 2.0 ** -16 * (h1 + e1)
+    m2 = (1 + 2.0 ** -8) * ((h1 + e1) @ np.abs(W2).T) + np.abs(b2)
+    e2 = (2 * H + 2) * u * m2 + eh @ np.abs(W2).T
+    m3 = (h2 + e2) @ np.abs(W3) + abs(b3[0])
     e3 = (H + 2) * u * m3 + e2 @ np.abs(W3)
     return 2.0 * e3
-
-
-def vhat_bf16_hidden(theta_bf16, F, scale=1000.0):
-    """(scale * out of forward_bf16_hidden, scale * its error bound)."""
-    out, _ = forward_bf16_hidden(theta_bf16, F)
-    return scale * out, scale * bf16_hidden_error_bound(theta_bf16, F)

@@ -193,56 +193,46 @@ def test_error_bound_covers_fp32_evaluation():
     assert (err <= 2 * bound).all()
 
 
-def test_bf16_hidden_ties_by_hand():
-    """b1 puts ties and near-ties into h1 (all weights of layer 1 zero); W2
-    is the identity and W3 sums, so out = sum of the rounded h1 + b3."""
-    th = np.zeros(M.NPARAMS)
-    W1, b1, W2, b2, W3, b3 = M.unpack(th)
-    b1[0] = 1.0 + 2.0 ** -8            # tie -> 1.0
-    b1[1] = 1.0 + 3 * 2.0 ** -8        # tie -> 1 + 2^-6
-    b1[2] = 2.0 + 2.0 ** -7            # step 2^-6 above 2: tie -> even 2.0
-    b1[3] = -0.75                      # relu -> 0
-    b1[4] = 0.5 + 2.0 ** -9 + 2.0 ** -20   # above the tie -> 0.5 + 2^-8
-    W2[:] = np.eye(64)
-    W3[:] = 1.0
-    b3[0] = 0.125
-    out, a1 = M.forward_bf16_hidden(th, np.zeros((3, 4)))
-    want = 1.0 + (1.0 + 2.0 ** -6) + 2.0 + 0.0 + (0.5 + 2.0 ** -8) + 0.125
-    assert np.all(out == want)
-    ex, _ = M.forward(th, np.zeros((1, 4)))
-    assert ex[0] != want  # the rounding is visible
+def test_split_by_hand():
+    """hi = bf16(h), lo = bf16(h - hi): hand-worked values, and the residual
+    bound |h - hi - lo| <= 2^-16 |h| on many values."""
+    def split(h):
+        h = np.float32(h)
+        hi = M.bf16_round(h).reshape(-1)[0]
+        lo = M.bf16_round(np.float32(h - hi)).reshape(-1)[0]
+        return float(hi), float(lo)
+    # 1 + 2^-8 + 2^-20: hi rounds up to 1 + 2^-7; the rest, -(2^-8 - 2^-20),
+    # has 12 significant bits and rounds to -2^-8
+    assert split(1.0 + 2.0 ** -8 + 2.0 ** -20) == (1.0 + 2.0 ** -7, -(2.0 ** -8))
+    # 3 + 2^-10: hi = 3 (the tail is below half a bf16 step), lo = 2^-10 exactly
+    assert split(3.0 + 2.0 ** -10) == (3.0, 2.0 ** -10)
+    # a bf16 value splits into itself and zero
+    assert split(-2.5) == (-2.5, 0.0)
+    h = (synth.Stream(91, 1).uniform(20000).astype(np.float32) * np.float32(50))
+    hi = M.bf16_round(h)
+    lo = M.bf16_round((h - hi).astype(np.float32))
+    r = np.abs(h.astype(np.float64) - hi.astype(np.float64) - lo.astype(np.float64))
+    assert (r <= 2.0 ** -16 * np.abs(h.astype(np.float64))).all()
+    assert r.max() > 2.0 ** -19 * np.abs(h).max()   # and is not far from tight
 
 
-def test_bf16_hidden_matches_library_conversion():
-    """The same network with h1 converted by torch (fp32 -> bfloat16) and
-    the rest in fp64 torch ops."""
-    th = M.bf16_round(_theta(71, scale=0.5)).astype(np.float64)
-    F = _feats(72, 400)
-    out, _ = M.forward_bf16_hidden(th, F)
-    W1, b1, W2, b2, W3, b3 = (torch.from_numpy(np.ascontiguousarray(a)) for a in M.unpack(th))
-    Ft = torch.from_numpy(F)
-    h1 = torch.relu(Ft @ W1.T + b1).to(torch.float32).to(torch.bfloat16).to(torch.float64)
-    o = torch.relu(h1 @ W2.T + b2) @ W3 + b3[0]
-    assert np.allclose(out, o.numpy(), rtol=0, atol=1e-12)
-    ex, _ = M.forward(th, F)
-    assert not np.array_equal(ex, out)
-
-
-def test_bf16_hidden_bound_covers_fp32_evaluation():
-    """The bound holds for an fp32 evaluation in the library's shape: fp32
-    features, a1 by fused multiply-adds (emulated: the exact fp64 product-sum
-    rounded to fp32 once per step), relu, bf16 rounding, fp32 sums of the
-    exact products of the later layers in a pairwise order."""
+def test_split_bound_covers_fp32_evaluation():
+    """The bound holds for an evaluation in the key kernel's shape: fp32
+    features, a1 by fused multiply-adds (emulated: the exact fp64
+    product-sum rounded to fp32 once per step), relu, the two-term bf16
+    split, fp32 pairwise sums of the exact products of the later layers."""
     th = M.bf16_round(_theta(81, scale=0.5)).astype(np.float64)
     n = 3000
     F = _feats(82, n)
     F32 = F.astype(np.float32).astype(np.float64)
-    out, _ = M.forward_bf16_hidden(th, F)
+    out, _ = M.forward(th, F)
     W1, b1, W2, b2, W3, b3 = M.unpack(th)
     a1 = np.tile(b1.astype(np.float32).astype(np.float64), (n, 1))
     for i in range(4):
         a1 = (a1 + F32[:, i:i + 1] * W1[:, i]).astype(np.float32).astype(np.float64)
-    h1 = M.bf16_round(np.maximum(a1, 0).astype(np.float32)).astype(np.float64)
+    h1 = np.maximum(a1, 0).astype(np.float32)
+    hi = M.bf16_round(h1)
+    lo = M.bf16_round((h1 - hi).astype(np.float32))
 
     def sum32(terms):   # pairwise fp32 sum along the last axis
         t = terms.astype(np.float32)
@@ -250,15 +240,22 @@ def test_bf16_hidden_bound_covers_fp32_evaluation():
             t = (t[..., 0::2] + t[..., 1::2]).astype(np.float32)
         return t[..., 0].astype(np.float64)
 
-    a2 = (sum32(h1[:, None, :] * W2[None, :, :]) + b2).astype(np.float32).astype(np.float64)
+    prods = np.concatenate([hi.astype(np.float64)[:, None, :] * W2[None, :, :],
+                            lo.astype(np.float64)[:, None, :] * W2[None, :, :]], axis=2)
+    a2 = (sum32(prods) + b2).astype(np.float32).astype(np.float64)
     h2 = np.maximum(a2, 0)
     o = (sum32(h2 * W3) + b3[0]).astype(np.float32).astype(np.float64)
     err = np.abs(o - out)
-    bound = M.bf16_hidden_error_bound(th, F)
+    bound = M.split_hidden_error_bound(th, F)
     assert (err <= bound).all()
-    # the bound is not vacuous: far below the network's output scale except
-    # on the few rows where a unit of h1 may tip to the neighbouring bf16
-    assert np.median(bound) < 1e-3 * np.abs(out).max()
+    # the bound is far below the output scale, for every row, and below
+    # what a single bf16 rounding of h1 would cost on many rows
+    assert bound.max() < 5e-3 * np.abs(out).max()
+    # and the split evaluation is much closer than a single bf16 rounding of h1
+    h1b = hi.astype(np.float64)
+    o1 = np.maximum(h1b @ W2.T + b2, 0) @ W3 + b3[0]
+    assert err.max() < 0.05 * np.abs(o1 - out).max()
+    assert (np.abs(o1 - out) > bound).mean() > 0.1
 
 
 @pytest.mark.parametrize("n", [1, 5])
