@@ -99,10 +99,12 @@ __device__ __forceinline__ float forward(const float* w, const float f[4], float
 //            per 32-unit block, two v_mfma_f32_32x32x2_f32 over the feature
 //            pairs and one that adds b1 (A = b1, B = 1 in the first half,
 //            A = B = 0 in the second);
-//   layer 2  D2 (64 x 32) = W2 (64 x 64) bf16(relu(D1)) + b2: per output
-//            block, four v_mfma_f32_32x32x16_bf16 steps, accumulator
-//            started at b2; h1 is rounded to bf16 (nearest even), W2 is
-//            the bf16 working copy, the sums are fp32;
+//   layer 2  D2 (64 x 32) = W2 (64 x 64) relu(D1) + b2: per output block,
+//            eight v_mfma_f32_32x32x16_bf16 steps, accumulator started at
+//            b2.  W2 is the bf16 working copy; h1 = relu(D1) enters as the
+//            two bf16 terms hi + lo of its fp32 value (relative residual
+//            below 2^-16, so the keys match the fp32 network's), and the
+//            sums are fp32;
 //   layer 3  out = b3 + W3 . relu(D2): fp32 fmas over the 32 units a lane
 //            holds, then one exchange between the two halves of the wave.
 // Operand layouts (wave64, lane l, half h = l/32): v_mfma_f32_32x32x2_f32
@@ -186,14 +188,21 @@ __global__ __launch_bounds__(256) void k_vhat(const uint16_t* __restrict__ wbf, 
             }
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
-            bf16x8 x;
+            // h1 = hi + lo + r with hi = bf16(h1), lo = bf16(h1 - hi) (the
+            // difference is exact in fp32) and |r| <= 2^-16 |h1|; both
+            // halves go through the bf16 products, whose sums are fp32
+            bf16x8 xh, xl;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const float a = d1[st >> 1][8 * (st & 1) + e];
-                x[e] = (__bf16)(a > 0.f ? a : 0.f);  // relu leaves no NaN; nearest even
+                const float hv = a > 0.f ? a : 0.f;  // relu leaves no NaN
+                xh[e] = (__bf16)hv;                   // nearest even
+                xl[e] = (__bf16)(hv - (float)xh[e]);
             }
-            d2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2w[0][st], x, d2[0], 0, 0, 0);
-            d2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2w[1][st], x, d2[1], 0, 0, 0);
+            d2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2w[0][st], xh, d2[0], 0, 0, 0);
+            d2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2w[1][st], xh, d2[1], 0, 0, 0);
+            d2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2w[0][st], xl, d2[0], 0, 0, 0);
+            d2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2w[1][st], xl, d2[1], 0, 0, 0);
         }
         // layer 3
         float v = 0.f;
