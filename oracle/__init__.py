@@ -7,7 +7,8 @@ benchmark may import this package.  It shares no code with the HIP library
 Contents
   gbf_oracle.c   Algorithm 1 of the paper (Sect. IV-A), single-threaded C,
                  plus the canonical policy / residual pass, a box decoder and
-                 an independent min-max Dijkstra for non-negative costs.
+                 an independent min-max Dijkstra for non-negative costs;
+                 running costs per pair, plus optional per-edge costs.
   brute.py       Brute force from the definitions of Sect. III: the operator
                  P, Kleene iteration, policy evaluation and enumeration of
                  memoryless strategies (tiny problems only).
@@ -67,15 +68,15 @@ def lib():
             i64 = ctypes.c_int64
             for nm in ("oracle_solve_i32", "oracle_solve_f64", "oracle_solve_f32"):
                 f = getattr(L, nm)
-                f.argtypes = [i64, i64, P, P, P, P, P, i64, P, P, ctypes.POINTER(Counters), P, P]
+                f.argtypes = [i64, i64, P, P, P, P, P, P, i64, P, P, ctypes.POINTER(Counters), P, P]
                 f.restype = ctypes.c_int
             for nm in ("oracle_policy_i32", "oracle_policy_f64", "oracle_policy_f32"):
                 f = getattr(L, nm)
-                f.argtypes = [i64, i64, P, P, P, P, P, P, P]
+                f.argtypes = [i64, i64, P, P, P, P, P, P, P, P]
                 f.restype = i64
             L.oracle_box_to_csr.argtypes = [P, i64, P, P, P]
             L.oracle_box_to_csr.restype = i64
-            L.oracle_dijkstra_i32.argtypes = [i64, i64, P, P, P, P, P, P]
+            L.oracle_dijkstra_i32.argtypes = [i64, i64, P, P, P, P, P, P, P]
             L.oracle_dijkstra_i32.restype = ctypes.c_int
             _lib = L
     return _lib
@@ -93,6 +94,16 @@ def _inputs(prob):
         idx = np.ascontiguousarray(prob.succ_idx, dtype=np.int32)
     av = np.ascontiguousarray(prob.avoid, dtype=np.uint8)
     return ptr, idx, av
+
+
+def _edge_costs(prob, dtype):
+    """Per-edge costs h (one per successor-list entry), or None."""
+    h = getattr(prob, "g_edge", None)
+    if h is None:
+        return None
+    if prob.succ_ptr is None:
+        raise ValueError("per-edge costs need explicit successor lists")
+    return np.ascontiguousarray(h, dtype=dtype)
 
 
 def _precision(prob, precision):
@@ -113,11 +124,13 @@ def solve(prob, precision: str | None = None, max_rounds: int = 0) -> dict:
     if prec == "i32":
         g = np.ascontiguousarray(prob.g, dtype=np.int32)
         G = np.ascontiguousarray(prob.G, dtype=np.int32)
+        h = _edge_costs(prob, np.int32)
         W = np.empty(n, dtype=np.int32)
         fs, fp = L.oracle_solve_i32, L.oracle_policy_i32
     else:
         g = np.ascontiguousarray(prob.g, dtype=np.float32)
         G = np.ascontiguousarray(prob.G, dtype=np.float32)
+        h = _edge_costs(prob, np.float32)
         W = np.empty(n, dtype=np.float64 if prec == "f64" else np.float32)
         fs, fp = (L.oracle_solve_f64, L.oracle_policy_f64) if prec == "f64" else \
                  (L.oracle_solve_f32, L.oracle_policy_f32)
@@ -125,12 +138,12 @@ def solve(prob, precision: str | None = None, max_rounds: int = 0) -> dict:
     c = Counters()
     front = np.empty(n, dtype=np.int32)
     flen = np.zeros(1, dtype=np.int64)
-    st = fs(n, K, _p(ptr), _p(idx), _p(g), _p(G), _p(av), int(max_rounds), _p(W), _p(mu), ctypes.byref(c),
-            _p(front), _p(flen))
+    st = fs(n, K, _p(ptr), _p(idx), _p(g), _p(h), _p(G), _p(av), int(max_rounds), _p(W), _p(mu),
+            ctypes.byref(c), _p(front), _p(flen))
     if st < 0:
         raise ValueError(f"oracle rejected the problem (status {st})")
     pol = np.empty(n, dtype=np.int32)
-    bad = fp(n, K, _p(ptr), _p(idx), _p(g), _p(G), _p(av), _p(W), _p(pol))
+    bad = fp(n, K, _p(ptr), _p(idx), _p(g), _p(h), _p(G), _p(av), _p(W), _p(pol))
     return {"V": W, "mu": mu, "policy": pol, "residual": int(bad), "status": int(st),
             "counters": c.as_dict(), "precision": prec, "frontier": front[:int(flen[0])].copy()}
 
@@ -144,15 +157,17 @@ def residual(prob, V, precision: str | None = None):
     if prec == "i32":
         g = np.ascontiguousarray(prob.g, dtype=np.int32)
         G = np.ascontiguousarray(prob.G, dtype=np.int32)
+        h = _edge_costs(prob, np.int32)
         W = np.ascontiguousarray(V, dtype=np.int32)
         f = L.oracle_policy_i32
     else:
         g = np.ascontiguousarray(prob.g, dtype=np.float32)
         G = np.ascontiguousarray(prob.G, dtype=np.float32)
+        h = _edge_costs(prob, np.float32)
         W = np.ascontiguousarray(V, dtype=np.float64 if prec == "f64" else np.float32)
         f = L.oracle_policy_f64 if prec == "f64" else L.oracle_policy_f32
     pol = np.empty(prob.n, dtype=np.int32)
-    bad = f(prob.n, prob.K, _p(ptr), _p(idx), _p(g), _p(G), _p(av), _p(W), _p(pol))
+    bad = f(prob.n, prob.K, _p(ptr), _p(idx), _p(g), _p(h), _p(G), _p(av), _p(W), _p(pol))
     return int(bad), pol
 
 
@@ -177,8 +192,9 @@ def dijkstra(prob) -> np.ndarray:
     ptr, idx, av = _inputs(prob)
     g = np.ascontiguousarray(prob.g, dtype=np.int32)
     G = np.ascontiguousarray(prob.G, dtype=np.int32)
+    h = _edge_costs(prob, np.int32)
     W = np.empty(prob.n, dtype=np.int32)
-    st = L.oracle_dijkstra_i32(prob.n, prob.K, _p(ptr), _p(idx), _p(g), _p(G), _p(av), _p(W))
+    st = L.oracle_dijkstra_i32(prob.n, prob.K, _p(ptr), _p(idx), _p(g), _p(h), _p(G), _p(av), _p(W))
     if st != 0:
         raise ValueError(f"dijkstra rejected the problem (status {st})")
     return W

@@ -4,8 +4,10 @@ These functions restate Sect. III of the paper directly and are used to pin
 the C oracle (Algorithm 1) to something other than itself:
 
   apply_P       the dynamic programming operator of Sect. III-C,
-                P(W)(x) = min{G(x), min_u max_{y in F(x,u)} g(x,u) + W(y)},
-                in exact Python arithmetic (ints, or floats with math.inf).
+                P(W)(x) = min{G(x), min_u max_{y in F(x,u)} g(x,y,u) + W(y)},
+                with g(x,y,u) = g(x,u) + h(x,y,u) (h = 0 without per-edge
+                costs), in exact Python arithmetic (ints, or floats with
+                math.inf).
   kleene        its iterates P^k(G) from the top; V is the limit (the maximal
                 fixed point, Theorem on dynamic programming, Sect. III-C).
   evaluate      closed-loop performance L(., mu) of a memoryless controller
@@ -36,13 +38,24 @@ class Diverged(Exception):
 
 
 def _vals(prob):
+    """(G, g, rows, avoid): rows[p] lists (y, h) for y in F(x,u), with h the
+    per-edge part of the running cost g(x,y,u) = g(x,u) + h (0 if the
+    problem has no per-edge costs)."""
     if prob.dtype == "i32":
         G = [INF if int(v) >= INF_I32 else int(v) for v in prob.G]
         g = [INF if int(v) >= INF_I32 else int(v) for v in prob.g]
     else:
         G = [float(v) for v in prob.G]
         g = [float(v) for v in prob.g]
-    rows = [list(prob.succ_idx[prob.succ_ptr[p]:prob.succ_ptr[p + 1]]) for p in range(prob.npairs)]
+    he = getattr(prob, "g_edge", None)
+    if he is None:
+        hv = [0] * int(prob.succ_ptr[-1])
+    elif prob.dtype == "i32":
+        hv = [int(v) for v in he]
+    else:
+        hv = [float(v) for v in he]
+    rows = [[(int(prob.succ_idx[e]), hv[e]) for e in range(int(prob.succ_ptr[p]), int(prob.succ_ptr[p + 1]))]
+            for p in range(prob.npairs)]
     avoid = [bool(a) for a in prob.avoid]
     return G, g, rows, avoid
 
@@ -58,7 +71,7 @@ def apply_P(prob, W, _cache=None):
         best = G[x]
         for u in range(K):
             p = x * K + u
-            d = g[p] + max(W[y] for y in rows[p])
+            d = max(g[p] + h + W[y] for y, h in rows[p])
             if d < best:
                 best = d
         out.append(best)
@@ -95,7 +108,7 @@ def evaluate(prob, choice):
                 N.append(G[x])
             else:
                 p = x * K + c
-                N.append(min(G[x], g[p] + max(W[y] for y in rows[p])))
+                N.append(min(G[x], max(g[p] + h + W[y] for y, h in rows[p])))
         if N == W:
             return W
         W = N
@@ -120,7 +133,7 @@ def enumerate_V(prob):
 def cost_J(prob, u_sig, v_sig, x_sig, cost_of=None):
     """J(u,v,x) = G(x(T)) + sum_{t<T} g(x(t), x(t+1), u(t)), T = first t with
     v(t) = 1; INF if v never switches.  `cost_of(x, y, u)` defaults to the
-    per-pair cost g(x,u)."""
+    problem's running cost g(x,u) + h(x,y,u)."""
     G, g, rows, avoid = _vals(prob)
     K = prob.K
     if 1 not in v_sig:
@@ -128,8 +141,10 @@ def cost_J(prob, u_sig, v_sig, x_sig, cost_of=None):
     T = v_sig.index(1)
     tot = G[x_sig[T]]
     for t in range(T):
-        assert x_sig[t + 1] in rows[x_sig[t] * K + u_sig[t]], "not a behavior of the system"
-        tot += cost_of(x_sig[t], x_sig[t + 1], u_sig[t]) if cost_of else g[x_sig[t] * K + u_sig[t]]
+        p = x_sig[t] * K + u_sig[t]
+        hy = dict(rows[p])
+        assert x_sig[t + 1] in hy, "not a behavior of the system"
+        tot += cost_of(x_sig[t], x_sig[t + 1], u_sig[t]) if cost_of else g[p] + hy[x_sig[t + 1]]
     return tot
 
 
@@ -148,11 +163,14 @@ def kleene_np(prob, dtype=np.float64, max_iter=100000):
     else:
         G = prob.G.astype(dtype)
         g = prob.g.astype(dtype)
+    he = getattr(prob, "g_edge", None)
+    h = None if he is None else np.asarray(he, dtype=np.float64 if prob.dtype == "i32" else np.float32).astype(dtype)
     av = prob.avoid.astype(bool)
     W = np.where(av, np.inf, G).astype(dtype)
     starts = ptr[:-1]
     for it in range(max_iter):
-        mx = np.maximum.reduceat(W[idx], starts)
+        Wy = W[idx] if h is None else (h + W[idx]).astype(dtype)
+        mx = np.maximum.reduceat(Wy, starts)
         d = (g + mx).astype(dtype)
         best = d.reshape(n, K).min(axis=1)
         N = np.minimum(G, best).astype(dtype)

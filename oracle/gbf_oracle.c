@@ -9,9 +9,12 @@
  * What it computes (Weber, Kreuzer, Knoll, "A generalized Bellman-Ford
  * Algorithm for Application in Symbolic Optimal Control"):
  *   - Sect. III-C, dynamic programming operator
- *       P(W)(x) = min{ G(x), min_u max_{y in F(x,u)} g(x,u) + W(y) }
- *     with per-pair running costs g(x,u); the value function V is its
- *     maximal fixed point (Theorem on dynamic programming, Sect. III-C).
+ *       P(W)(x) = min{ G(x), min_u max_{y in F(x,u)} g(x,y,u) + W(y) }
+ *     with the running cost of a transition given as g(x,y,u) =
+ *     g(x,u) + h(x,y,u): a per-pair part g and, optionally, a per-edge part
+ *     h (one value per successor-list entry; absent = 0); the value
+ *     function V is its maximal fixed point (Theorem on dynamic
+ *     programming, Sect. III-C).
  *   - Sect. IV-A, Algorithm 1 (generalized Bellman-Ford-Yen): two state
  *     frontiers, the active one processed as F1 x U, in-place updates of W
  *     on strict improvement, predecessors of an improved state pushed into
@@ -25,6 +28,11 @@
  *   - int32 costs: sums are formed in int64; a sum >= INT32_MAX means INF
  *     (no improvement); a sum below -INT32_MAX saturates to -INT32_MAX and
  *     is counted in `saturations`.
+ *   - Per-edge costs h must be finite.  A pair's backup is
+ *     g(x,u) + max_y (h(x,y,u) + W(y)): exact in int64 for int32; for
+ *     single precision each h + W(y) is one IEEE addition and the pair cost
+ *     one more (adding g after the max equals adding it per edge, since
+ *     rounding is monotone).
  *   - Floating point: the definition is evaluated in double precision
  *     (oracle_solve_f64).  oracle_solve_f32 evaluates the same algorithm
  *     with one IEEE single-precision round-to-nearest-even addition per
@@ -150,10 +158,10 @@ typedef struct {
 /* ------------------------------------------------------------------ */
 /* Algorithm 1, one instantiation per value type.                      */
 /* ------------------------------------------------------------------ */
-#define OR_DEFINE_SOLVER(NAME, VT, GT, IS_INF, INFV, BACKUP)                                       \
-    int NAME(int64_t n, int64_t K, const int64_t* sp, const int32_t* si, const GT* g, const GT* G, \
-             const uint8_t* avoid, int64_t max_rounds, VT* W, int32_t* mu, oracle_counters* c,    \
-             int32_t* front_out, int64_t* front_len) {                                             \
+#define OR_DEFINE_SOLVER(NAME, VT, GT, IS_INF, INFV, BACKUP, WT, EDGE, WINF, BACKUPW)                \
+    int NAME(int64_t n, int64_t K, const int64_t* sp, const int32_t* si, const GT* g, const GT* h, \
+             const GT* G, const uint8_t* avoid, int64_t max_rounds, VT* W, int32_t* mu,           \
+             oracle_counters* c, int32_t* front_out, int64_t* front_len) {                         \
         oracle_counters cc;                                                                        \
         memset(&cc, 0, sizeof(cc));                                                                \
         int rc = check_graph(n, K, sp, si);                                                        \
@@ -200,12 +208,22 @@ typedef struct {
                     if (IS_INF(g[p])) continue;                                                    \
                     cc.pair_evals++;                                                               \
                     cc.edge_relax += sp[p + 1] - sp[p];                                            \
-                    VT mx = W[si[sp[p]]];                                                          \
-                    for (int64_t e = sp[p] + 1; e < sp[p + 1]; ++e)                                \
-                        if (W[si[e]] > mx) mx = W[si[e]];                                          \
-                    if (mx == INFV) continue;                                                      \
                     VT d;                                                                          \
-                    if (!BACKUP(g[p], mx, &d, &cc)) continue;                                      \
+                    if (h) {                                                                       \
+                        WT mw = EDGE(h[sp[p]], W[si[sp[p]]]);                                      \
+                        for (int64_t e = sp[p] + 1; e < sp[p + 1]; ++e) {                          \
+                            WT v = EDGE(h[e], W[si[e]]);                                           \
+                            if (v > mw) mw = v;                                                    \
+                        }                                                                          \
+                        if (mw == WINF) continue;                                                  \
+                        if (!BACKUPW(g[p], mw, &d, &cc)) continue;                                 \
+                    } else {                                                                       \
+                        VT mx = W[si[sp[p]]];                                                      \
+                        for (int64_t e = sp[p] + 1; e < sp[p + 1]; ++e)                            \
+                            if (W[si[e]] > mx) mx = W[si[e]];                                      \
+                        if (mx == INFV) continue;                                                  \
+                        if (!BACKUP(g[p], mx, &d, &cc)) continue;                                  \
+                    }                                                                              \
                     if (d < W[x]) {                                                                \
                         W[x] = d;                                                                  \
                         mu[x] = (int32_t)u;                                                        \
@@ -269,20 +287,45 @@ static inline int backup_f32(float g, float m, float* d, oracle_counters* c) {
     return 1;
 }
 
+/* per-edge term h + W(y); INF stays INF (a sentinel far above any finite
+ * int32 sum, so that the max over a row is INF if any W(y) is) */
+#define OR_EDGE_INF_I64 ((int64_t)1 << 62)
+static inline int64_t edge_i32(int32_t h, int32_t w) {
+    return (int64_t)w >= OR_INF_I32 ? OR_EDGE_INF_I64 : (int64_t)h + (int64_t)w;
+}
+static inline double edge_f64(float h, double w) { return (double)h + w; }
+static inline float edge_f32(float h, float w) {
+    volatile float s = h + w; /* one IEEE single addition */
+    return s;
+}
+static inline int backupw_i32(int32_t g, int64_t m, int32_t* d, oracle_counters* c) {
+    int64_t s = (int64_t)g + m;
+    if (s >= OR_INF_I32) return 0;
+    if (s < OR_LOW_I32) {
+        s = OR_LOW_I32;
+        c->saturations++;
+    }
+    *d = (int32_t)s;
+    return 1;
+}
+
 #define IS_INF_I32(v) ((int64_t)(v) >= OR_INF_I32)
 #define IS_INF_F(v) (isinf(v) && (v) > 0)
 
-OR_DEFINE_SOLVER(oracle_solve_i32, int32_t, int32_t, IS_INF_I32, (int32_t)INT32_MAX, backup_i32)
-OR_DEFINE_SOLVER(oracle_solve_f64, double, float, IS_INF_F, (double)INFINITY, backup_f64)
-OR_DEFINE_SOLVER(oracle_solve_f32, float, float, IS_INF_F, (float)INFINITY, backup_f32)
+OR_DEFINE_SOLVER(oracle_solve_i32, int32_t, int32_t, IS_INF_I32, (int32_t)INT32_MAX, backup_i32, int64_t,
+                 edge_i32, OR_EDGE_INF_I64, backupw_i32)
+OR_DEFINE_SOLVER(oracle_solve_f64, double, float, IS_INF_F, (double)INFINITY, backup_f64, double, edge_f64,
+                 (double)INFINITY, backup_f64)
+OR_DEFINE_SOLVER(oracle_solve_f32, float, float, IS_INF_F, (float)INFINITY, backup_f32, float, edge_f32,
+                 (float)INFINITY, backup_f32)
 
 /* ------------------------------------------------------------------ */
 /* Canonical policy + residual: one application of P to W.             */
 /* Returns the number of non-avoid states with P(W)(x) != W(x).        */
 /* ------------------------------------------------------------------ */
-#define OR_DEFINE_POLICY(NAME, VT, GT, IS_INF, INFV, BACKUP)                                        \
+#define OR_DEFINE_POLICY(NAME, VT, GT, IS_INF, INFV, BACKUP, WT, EDGE, WINF, BACKUPW)                 \
     int64_t NAME(int64_t n, int64_t K, const int64_t* sp, const int32_t* si, const GT* g,           \
-                 const GT* G, const uint8_t* avoid, const VT* W, int32_t* pol) {                    \
+                 const GT* h, const GT* G, const uint8_t* avoid, const VT* W, int32_t* pol) {       \
         oracle_counters dummy;                                                                      \
         int64_t bad = 0;                                                                            \
         for (int64_t x = 0; x < n; ++x) {                                                           \
@@ -296,12 +339,22 @@ OR_DEFINE_SOLVER(oracle_solve_f32, float, float, IS_INF_F, (float)INFINITY, back
             for (int64_t u = 0; u < K; ++u) {                                                       \
                 int64_t p = x * K + u;                                                              \
                 if (IS_INF(g[p])) continue;                                                         \
-                VT mx = W[si[sp[p]]];                                                               \
-                for (int64_t e = sp[p] + 1; e < sp[p + 1]; ++e)                                     \
-                    if (W[si[e]] > mx) mx = W[si[e]];                                               \
-                if (mx == INFV) continue;                                                           \
                 VT d;                                                                               \
-                if (!BACKUP(g[p], mx, &d, &dummy)) continue;                                        \
+                if (h) {                                                                            \
+                    WT mw = EDGE(h[sp[p]], W[si[sp[p]]]);                                           \
+                    for (int64_t e = sp[p] + 1; e < sp[p + 1]; ++e) {                               \
+                        WT v = EDGE(h[e], W[si[e]]);                                                \
+                        if (v > mw) mw = v;                                                         \
+                    }                                                                               \
+                    if (mw == WINF) continue;                                                       \
+                    if (!BACKUPW(g[p], mw, &d, &dummy)) continue;                                   \
+                } else {                                                                            \
+                    VT mx = W[si[sp[p]]];                                                           \
+                    for (int64_t e = sp[p] + 1; e < sp[p + 1]; ++e)                                 \
+                        if (W[si[e]] > mx) mx = W[si[e]];                                           \
+                    if (mx == INFV) continue;                                                       \
+                    if (!BACKUP(g[p], mx, &d, &dummy)) continue;                                    \
+                }                                                                                   \
                 if (d < best) {                                                                     \
                     best = d;                                                                       \
                     pu = (int32_t)u;                                                                \
@@ -314,9 +367,12 @@ OR_DEFINE_SOLVER(oracle_solve_f32, float, float, IS_INF_F, (float)INFINITY, back
         return bad;                                                                                 \
     }
 
-OR_DEFINE_POLICY(oracle_policy_i32, int32_t, int32_t, IS_INF_I32, (int32_t)INT32_MAX, backup_i32)
-OR_DEFINE_POLICY(oracle_policy_f64, double, float, IS_INF_F, (double)INFINITY, backup_f64)
-OR_DEFINE_POLICY(oracle_policy_f32, float, float, IS_INF_F, (float)INFINITY, backup_f32)
+OR_DEFINE_POLICY(oracle_policy_i32, int32_t, int32_t, IS_INF_I32, (int32_t)INT32_MAX, backup_i32, int64_t,
+                 edge_i32, OR_EDGE_INF_I64, backupw_i32)
+OR_DEFINE_POLICY(oracle_policy_f64, double, float, IS_INF_F, (double)INFINITY, backup_f64, double, edge_f64,
+                 (double)INFINITY, backup_f64)
+OR_DEFINE_POLICY(oracle_policy_f32, float, float, IS_INF_F, (float)INFINITY, backup_f32, float, edge_f32,
+                 (float)INFINITY, backup_f32)
 
 /* ------------------------------------------------------------------ */
 /* Box decoding (the oracle's own): packed 8-byte box per pair, low    */
@@ -362,8 +418,9 @@ int64_t oracle_box_to_csr(const int32_t* dims, int64_t npairs, const uint64_t* b
 /* Independent solver for non-negative running costs: a min-max        */
 /* Dijkstra (Knuth's generalisation to superior functions, 1977).      */
 /* States are settled in order of value; a pair becomes a candidate    */
-/* when its last successor settles, whose value is then the max.       */
-/* int32 costs only; returns OR_EINVAL if some finite g < 0.           */
+/* when its last successor settles (without per-edge costs that one    */
+/* holds the max).  int32 costs only; returns OR_EINVAL if some finite */
+/* g < 0 or some per-edge cost is negative.                            */
 /* ------------------------------------------------------------------ */
 typedef struct {
     int64_t key;
@@ -402,12 +459,15 @@ static or_heap_item heap_pop(or_heap_item* h, int64_t* len) {
 }
 
 int oracle_dijkstra_i32(int64_t n, int64_t K, const int64_t* sp, const int32_t* si, const int32_t* g,
-                        const int32_t* G, const uint8_t* avoid, int32_t* W) {
+                        const int32_t* h, const int32_t* G, const uint8_t* avoid, int32_t* W) {
     int rc = check_graph(n, K, sp, si);
     if (rc) return rc;
     int64_t np = n * K;
     for (int64_t p = 0; p < np; ++p)
         if (!IS_INF_I32(g[p]) && g[p] < 0) return OR_EINVAL;
+    if (h)
+        for (int64_t e = 0; e < sp[np]; ++e)
+            if (h[e] < 0 || IS_INF_I32(h[e])) return OR_EINVAL;
     /* reverse lists at pair level (with multiplicity) */
     int64_t m = sp[np];
     int64_t* rp = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
@@ -444,7 +504,17 @@ int oracle_dijkstra_i32(int64_t n, int64_t K, const int64_t* sp, const int32_t* 
             if (--cnt[p] != 0) continue;
             int64_t xp = p / K;
             if ((avoid && avoid[xp]) || done[xp] || IS_INF_I32(g[p])) continue;
-            int64_t d = (int64_t)g[p] + it.key;
+            /* all successors are settled: without h the last one has the
+             * largest value; with h the max is taken over the row */
+            int64_t mx = it.key;
+            if (h) {
+                mx = 0;
+                for (int64_t e2 = sp[p]; e2 < sp[p + 1]; ++e2) {
+                    int64_t v = (int64_t)h[e2] + tent[si[e2]];
+                    if (e2 == sp[p] || v > mx) mx = v;
+                }
+            }
+            int64_t d = (int64_t)g[p] + mx;
             if (d < tent[xp]) {
                 tent[xp] = d;
                 heap_push(heap, &hl, d, (int32_t)xp);

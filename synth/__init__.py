@@ -123,6 +123,8 @@ class Problem:
     cost_c: Optional[np.ndarray] = None   # [n*K] positive part of g
     c_min: float = 0.0
     name: str = ""
+    g_edge: Optional[np.ndarray] = None   # [m] per-edge part h of the running cost
+                                          # g(x,y,u) = g(x,u) + h(x,y,u), CSR order
 
     @property
     def n(self) -> int:
@@ -605,6 +607,67 @@ def potential_small(seed: int, n: int, K: int, max_succ: int = 3, dtype: str = "
         G = np.array(G)
         G[0] = 0
     return explicit_problem(n, K, rows, g, G, dtype=dtype, name=f"potential_small_{seed}")
+
+
+def with_edge_costs(prob: Problem, seed: int, extra=(0, 4), keep_pair=True) -> Problem:
+    """The same system with per-edge running costs in potential form:
+    h(x,y,u) = c'(x,y,u) + phi(x) - phi(y), c' drawn from `extra` (int32:
+    U{lo..hi-1}; fp32: U[lo,hi)), and the per-pair part g(x,u) = c(x,u) (the
+    positive part of the original cost; 0 if keep_pair is False).  Along any
+    path the potential terms telescope, so every cycle costs at least its
+    length times min c + min c' and no negative cycle exists (with c' >= 0
+    and c >= c_min, or c' >= 1 when keep_pair is False).  Needs CSR rows
+    and the potential phi."""
+    import copy
+    prob.ensure_csr()
+    q = copy.copy(prob)
+    r = Stream(seed, 21)
+    ptr = np.asarray(prob.succ_ptr, dtype=np.int64)
+    idx = np.asarray(prob.succ_idx, dtype=np.int64)
+    m = int(ptr[-1])
+    src = np.repeat(np.arange(prob.npairs, dtype=np.int64) // prob.K, np.diff(ptr))
+    phi = np.asarray(prob.phi, dtype=np.float64)
+    if prob.dtype == "i32":
+        ce = r.integers(extra[0], extra[1], m)
+        h = ce + phi[src].astype(np.int64) - phi[idx].astype(np.int64)
+        q.g_edge = h.astype(np.int32)
+        base = np.asarray(prob.cost_c, dtype=np.int64) if keep_pair else np.zeros(prob.npairs, np.int64)
+        q.g = np.where(np.asarray(prob.g) >= INF_I32, INF_I32, base).astype(np.int32)
+    else:
+        ce = extra[0] + (extra[1] - extra[0]) * r.uniform(m)
+        q.g_edge = (ce + phi[src] - phi[idx]).astype(np.float32)
+        base = np.asarray(prob.cost_c, dtype=np.float64) if keep_pair else np.zeros(prob.npairs)
+        q.g = np.where(np.isinf(np.asarray(prob.g)), np.inf, base).astype(np.float32)
+    q.name = prob.name + "_edgecost"
+    return q
+
+
+def potential_small_edges(seed: int, n: int, K: int, max_succ: int = 3, dtype: str = "i32",
+                          p_target: float = 0.3, zero_phi: bool = False) -> Problem:
+    """Tiny random problem with per-edge costs in potential form (no
+    negative cycles; all costs >= 0 with zero_phi)."""
+    prob = potential_small(seed, n, K, max_succ, dtype, p_target, zero_phi)
+    r = Stream(seed, 22)
+    phi = np.zeros(n) if zero_phi else (r.integers(0, 20, n) if dtype == "i32" else 20.0 * r.uniform(n))
+    c = r.integers(1, 6, n * K) if dtype == "i32" else 0.5 + 3.0 * r.uniform(n * K)
+    prob.phi = phi
+    prob.cost_c = c
+    return with_edge_costs(prob, seed, extra=(0, 4) if dtype == "i32" else (0.0, 2.0))
+
+
+def random_small_edges(seed: int, n: int, K: int, max_succ: int = 3, lo: int = -5, hi: int = 5,
+                       dtype: str = "i32") -> Problem:
+    """random_small with arbitrary-sign per-edge costs h in [lo, hi) added
+    to the per-pair costs.  May contain negative cycles."""
+    prob = random_small(seed, n, K, max_succ, dtype=dtype)
+    r = Stream(seed, 23)
+    m = int(prob.succ_ptr[-1])
+    if dtype == "i32":
+        prob.g_edge = r.integers(lo, hi, m).astype(np.int32)
+    else:
+        prob.g_edge = (lo + (hi - lo) * r.uniform(m)).astype(np.float32)
+    prob.name += "_edgecost"
+    return prob
 
 
 def chain_graph(seed: int, n: int, K: int, dtype: str = "i32") -> Problem:
