@@ -349,6 +349,8 @@ def run(args, pool=None):
         extras["grid4d_384k_f32_csr"] = config_line(pf, "csr")
         extras["grid4d_384k_f32_box+rev"] = config_line(pf, "box+rev")
         extras["grid4d_384k_f32_box"] = config_line(pf, "box")
+        # the same graph with the running cost on the edges, g(x,u) + h(x,y,u)
+        extras["grid4d_384k_i32_csr_edge_costs"] = config_line(synth.with_edge_costs(prob, 34), "csr")
         print("[bench] configs done", file=sys.stderr, flush=True)
         out["configs"] = extras
         out["batch64"] = batch_compare(jobs["batch"].get())

@@ -118,7 +118,22 @@ typedef struct gbf_problem {
      *   2 = successors decoded from the boxes, predecessors from a reverse
      *       CSR built at load time (~4 bytes per successor). */
     int32_t expand_box;
-    int32_t reserved[3];
+    int32_t reserved0;
+    /* Optional per-edge part of the running cost (Sect. III-B defines the
+     * running cost on transitions, g(x,y,u); the operator of Sect. III-C
+     * and the sup of Algorithm 1 take g(x,y,u) + W(y) per successor).  The
+     * cost of the transition from x under u to the successor listed at
+     * succ_idx[e] is g[x*K+u] + g_edge[e], so the backup of a pair is
+     *   g(x,u) + max over its row of (g_edge[e] + W(succ_idx[e])).
+     * [m] values of the problem's dtype, in succ_idx order; NULL = all 0.
+     * GBF_CSR only (GBF_EINVAL with GBF_BOX).  Every value must be finite
+     * (int32: not INT32_MAX; fp32: not NaN or +-inf), else GBF_EINVAL.
+     * int32 sums are exact in int64 with the rules of g; fp32 adds
+     * g_edge[e] + W(y) with one round-to-nearest-even addition and the
+     * pair cost with one more.  Same memspace as the other arrays; copied
+     * at load. */
+    const void* g_edge;
+    int32_t reserved[2];
 } gbf_problem;
 
 /* ---- solve options --------------------------------------------------- */

@@ -47,7 +47,8 @@ class _Problem(ctypes.Structure):
                 ("encoding", ctypes.c_int32), ("memspace", ctypes.c_int32), ("G", ctypes.c_void_p),
                 ("g", ctypes.c_void_p), ("avoid", ctypes.c_void_p), ("succ_ptr", ctypes.c_void_p),
                 ("succ_idx", ctypes.c_void_p), ("dims", ctypes.c_int32 * 4), ("box", ctypes.c_void_p),
-                ("expand_box", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("expand_box", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("g_edge", ctypes.c_void_p),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class _Opts(ctypes.Structure):
@@ -224,9 +225,10 @@ class Graph:
 
 
 def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=None, succ_idx=None,
-               dims=None, box=None, expand_box=False, stream=None) -> Graph:
+               dims=None, box=None, expand_box=False, g_edge=None, stream=None) -> Graph:
     """gbf_load_graph.  Arrays are numpy (host) or torch tensors on the GPU
-    (all of one kind).  G/g are int32 or float32 bit patterns."""
+    (all of one kind).  G/g (and the optional per-edge costs g_edge, CSR
+    only) are int32 or float32 bit patterns."""
     L = lib()
     p = _Problem()
     p.n_states = int(n)
@@ -253,7 +255,10 @@ def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=
     if p.encoding == CSR:
         put("succ_ptr", succ_ptr, np.int64)
         put("succ_idx", succ_idx, np.int32)
+        put("g_edge", g_edge, vt)
     else:
+        if g_edge is not None:
+            raise ValueError("per-edge costs need the csr encoding")
         put("box", box, np.uint64)
         d = list(dims) + [1] * (4 - len(dims))
         for a in range(4):
@@ -271,10 +276,18 @@ def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=
 
 def load_problem(prob, encoding="csr", stream=None) -> Graph:
     """Loads an object with the fields of an optimal control problem
-    (n, K, dtype, G, g, avoid, succ_ptr/succ_idx or dims/box_packed()).
+    (n, K, dtype, G, g, avoid, succ_ptr/succ_idx or dims/box_packed(), and
+    optionally per-edge costs g_edge in succ_idx order).
     encoding: "csr" (explicit lists; expanded from the boxes on the device
     when the object carries no lists), "box" (implicit), "box->csr" or
-    "box+rev" (box successors, reverse CSR for the predecessors)."""
+    "box+rev" (box successors, reverse CSR for the predecessors).  Per-edge
+    costs need "csr" with explicit lists."""
+    g_edge = getattr(prob, "g_edge", None)
+    if g_edge is not None:
+        if encoding != "csr" or getattr(prob, "succ_ptr", None) is None:
+            raise ValueError("per-edge costs need the csr encoding with explicit successor lists")
+        return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="csr", avoid=prob.avoid,
+                          succ_ptr=prob.succ_ptr, succ_idx=prob.succ_idx, g_edge=g_edge, stream=stream)
     if encoding == "box+rev":
         return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="box", avoid=prob.avoid,
                           dims=prob.dims, box=prob.box_packed(), expand_box=2, stream=stream)

@@ -19,8 +19,10 @@ ENCODINGS = ("csr", "box+rev")
 
 
 def signature(probs) -> str:
-    """Shape of a problem set: dims, inputs and value type per instance."""
-    parts = [f"{tuple(int(d) for d in p.dims)}:{int(p.K)}:{p.dtype}" for p in probs]
+    """Shape of a problem set: dims, inputs, value type and whether costs are
+    per edge, per instance."""
+    parts = [f"{tuple(int(d) for d in p.dims)}:{int(p.K)}:{p.dtype}"
+             + (":edge" if getattr(p, "g_edge", None) is not None else "") for p in probs]
     return hashlib.sha1(";".join(parts).encode()).hexdigest()[:20]
 
 
@@ -51,6 +53,8 @@ def autotune(probs, encodings=ENCODINGS, reps=3, cache=None, log=None):
     for enc in encodings:
         if enc != "csr" and any(getattr(p, "box_lo", None) is None for p in probs):
             continue  # no boxes: only explicit successor lists
+        if enc != "csr" and any(getattr(p, "g_edge", None) is not None for p in probs):
+            continue  # per-edge costs are attached to explicit successor lists
         opts, ms = _measure(probs, enc, reps)
         if log:
             log(f"tune {enc}: {opts} {ms:.3f} ms")

@@ -180,6 +180,7 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
         return fail(GBF_EINVAL, "expand_box must be 0, 1 or 2");
     if (p->memspace != GBF_HOST && p->memspace != GBF_DEVICE) return fail(GBF_EINVAL, "bad memspace");
     if (!p->G || !p->g) return fail(GBF_EINVAL, "G and g are required");
+    if (p->g_edge && p->encoding != GBF_CSR) return fail(GBF_EINVAL, "per-edge costs need GBF_CSR");
     const int64_t n = p->n_states, K = p->n_inputs, np = n * K;
     if (np >= (int64_t)1 << 31) return fail(GBF_EINVAL, "n_states * n_inputs must be < 2^31");
     const hipMemcpyKind kind = p->memspace == GBF_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
@@ -261,6 +262,12 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
         HIPC(hipMemcpyAsync(sidx, p->succ_idx, m * 4, kind, s));
         I.sidx = sidx;
         I.sptr = sptr;
+        if (p->g_edge) {
+            int32_t* ge;
+            if ((rc = M.alloc((void**)&ge, m * 4))) return rc;
+            HIPC(hipMemcpyAsync(ge, p->g_edge, m * 4, kind, s));
+            I.ge = ge;
+        }
     } else {
         uint64_t* box;
         if ((rc = M.alloc((void**)&box, np * 8))) return rc;
@@ -278,6 +285,7 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
         if (herr & 4) msg += " NaN or -inf cost;";
         if (herr & 8) msg += " finite G on an avoid cell;";
         if (herr & 16) msg += " box outside the grid;";
+        if (herr & 32) msg += " non-finite per-edge cost;";
         return fail(GBF_EINVAL, msg);
     }
 
@@ -412,7 +420,7 @@ static int plan_solve(Scratch& S, const std::vector<Inst>& insts, int dtype, con
         total_pairs = std::max<int64_t>(total_pairs, I.pair_base + I.n * I.K);
         P.max_rounds = std::max<int64_t>(P.max_rounds, I.max_rounds);
         P.max_states = std::max<int64_t>(P.max_states, I.n);
-        P.enc_mask |= I.enc == 0 ? 1 : I.enc == 1 ? 2 : 4;
+        P.enc_mask |= I.enc == 0 ? (I.ge ? 8 : 1) : I.enc == 1 ? 2 : 4;
     }
     const int nevents = o.profile ? 2 * (int)std::min<int64_t>(P.max_rounds + 2, 4096) + 2 : 4;
     int rc = ensure_scratch(S, total_pairs, P.max_rounds, P.ninst, nevents);

@@ -54,6 +54,26 @@ struct TI32 {
         return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __device__ static __forceinline__ int32_t out_word(int32_t k) { return k; }
+    // per-edge costs: h + W(y) exactly in int64; INF stays far above every
+    // finite sum so that a row max is INF if any W(y) is
+    using wide_t = int64_t;
+    static constexpr int64_t WINF = (int64_t)1 << 62;
+    static constexpr int64_t WLOWEST = -((int64_t)1 << 62);
+    __device__ static __forceinline__ int64_t edge(int32_t h, int32_t v) {
+        return v == INF ? WINF : (int64_t)h + (int64_t)v;
+    }
+    __device__ static __forceinline__ int64_t wmax2(int64_t a, int64_t b) { return a > b ? a : b; }
+    __device__ static __forceinline__ bool backupw(int32_t g, int64_t m, int32_t& d, int& sat) {
+        if (g == INF || m >= WINF) return false;
+        int64_t s = (int64_t)g + m;
+        if (s >= (int64_t)INF) return false;
+        if (s < -(int64_t)INF) {
+            s = -(int64_t)INF;
+            sat = 1;
+        }
+        d = (int32_t)s;
+        return true;
+    }
 };
 
 struct TF32 {
@@ -85,6 +105,18 @@ struct TF32 {
         return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __device__ static __forceinline__ int32_t out_word(uint32_t k) { return __float_as_int(unkey(k)); }
+    // per-edge costs: one round-to-nearest-even addition h + W(y), kept as
+    // a key (+inf, from W(y) = INF or an overflow, is INF)
+    using wide_t = uint32_t;
+    static constexpr uint32_t WINF = INF;
+    static constexpr uint32_t WLOWEST = LOWEST;
+    __device__ static __forceinline__ uint32_t edge(int32_t hraw, uint32_t v) {
+        return key(__fadd_rn(__int_as_float(hraw), unkey(v)));
+    }
+    __device__ static __forceinline__ uint32_t wmax2(uint32_t a, uint32_t b) { return a > b ? a : b; }
+    __device__ static __forceinline__ bool backupw(int32_t graw, uint32_t m, uint32_t& d, int& sat) {
+        return backup(graw, m, d, sat);
+    }
 };
 
 // ---------------------------------------------------------------- wave helpers

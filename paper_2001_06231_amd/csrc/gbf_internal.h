@@ -18,6 +18,7 @@ struct Inst {
     const uint64_t* box;    // BOX encoding [nK]
     const int32_t* G;       // terminal cost bits [n]
     const int32_t* g;       // running cost bits [nK] (pruned pairs = INF)
+    const int32_t* ge;      // CSR only: per-edge cost bits [m] (succ_idx order), or NULL
     const uint8_t* avoid;   // [n]
     void* V;                // value words [n] (int32 or fp32 key)
     const int32_t* win;     // BOX: per input 8 ints: min (lo-x) per axis, max (hi-x) per axis

@@ -180,6 +180,11 @@ __global__ void k_validate(Inst I, const int64_t* sptr64, int64_t m, int dtype, 
                 for (int64_t j = a; j < b; ++j) {
                     int32_t y = I.sidx[j];
                     if (y < 0 || y >= I.n) e |= 2;
+                    if (I.ge) {
+                        const int32_t hr = I.ge[j];
+                        // per-edge costs must be finite
+                        if (dtype == 1 ? (hr & 0x7f800000) == 0x7f800000 : hr == 0x7fffffff) e |= 32;
+                    }
                 }
             }
         } else {
@@ -525,16 +530,23 @@ __device__ __forceinline__ void mark_pair(const Inst& I, uint8_t* __restrict__ d
 }
 
 // Encodings.  Template ENC: 1 = CSR, 2 = BOX, 4 = box successors with a
-// reverse CSR for the predecessors (HYB), 3 = decided per instance from
-// Inst.enc (0 CSR, 1 BOX, 2 HYB).
+// reverse CSR for the predecessors (HYB), 5 = CSR with per-edge costs,
+// 3 = decided per instance from Inst.enc (0 CSR, 1 BOX, 2 HYB) and Inst.ge.
 template <int ENC>
 __device__ __forceinline__ bool fwd_csr(const Inst& I) {
-    return ENC == 1 || (ENC == 3 && I.enc == 0);
+    return ENC == 1 || ENC == 5 || (ENC == 3 && I.enc == 0);
 }
 template <int ENC>
 __device__ __forceinline__ bool rev_csr(const Inst& I) {
-    return ENC == 1 || ENC == 4 || (ENC == 3 && I.enc != 1);
+    return ENC == 1 || ENC == 4 || ENC == 5 || (ENC == 3 && I.enc != 1);
 }
+template <int ENC>
+__device__ __forceinline__ bool has_edge(const Inst& I) {
+    return ENC == 5 || (ENC == 3 && I.enc == 0 && I.ge != nullptr);
+}
+// Kernels that may meet per-edge costs.
+template <int ENC>
+constexpr bool kMayEdge = ENC == 5 || ENC == 3;
 
 // Whole-wave expansion of one state y (wave-uniform arguments): every live
 // pair (x',u') with y in F(x',u') is marked.  CSR: the (sorted) reverse row
@@ -988,6 +1000,13 @@ __device__ __forceinline__ typename T::key_t group_max(typename T::key_t v) {
     return v;
 }
 
+template <class T, int G>
+__device__ __forceinline__ typename T::wide_t group_wmax(typename T::wide_t v) {
+#pragma unroll
+    for (int d = G / 2; d > 0; d >>= 1) v = T::wmax2(v, __shfl_xor(v, d, kWave));
+    return v;
+}
+
 // Per-lane view of the listed pair that a lane group works on.
 struct PairCtx {
     uint32_t s0, len;  // CSR row of the pair (BOX: unused)
@@ -1028,6 +1047,7 @@ __device__ __forceinline__ PairCtx load_pair(const Inst* __restrict__ It, const 
 template <class T>
 struct PairVal {
     typename T::key_t mx, cur;
+    typename T::wide_t mw;  // per-edge costs: this lane's max of h + W(y)
     int32_t graw;
     uint32_t len;
 };
@@ -1048,9 +1068,26 @@ __device__ __forceinline__ PairVal<T> pair_gather(const Inst* __restrict__ It, c
         graw = ldx<GBF_NT_MISC>(gp(I.g) + c.p);
     }
     K mx = (K)T::LOWEST;
+    typename T::wide_t mw = T::WLOWEST;
     uint32_t len = c.len;
     if (c.valid) {
-        if (fwd_csr<ENC>(I)) {
+        if (has_edge<ENC>(I)) {
+            // per-edge costs: the row's h values stream beside its indices
+            const GBF_GLOBAL int32_t* row = gp(I.sidx) + c.s0;
+            const GBF_GLOBAL int32_t* hrow = gp(I.ge) + c.s0;
+            for (uint32_t t = (uint32_t)sub; t < len; t += kRowBatch * G) {
+                int32_t y[kRowBatch], hv[kRowBatch];
+#pragma unroll
+                for (int k = 0; k < kRowBatch; ++k) {
+                    const uint32_t tk = t + (uint32_t)(k * G);
+                    y[k] = tk < len ? ldx<GBF_NT_ROWS>(row + tk) : -1;
+                    hv[k] = tk < len ? ldx<GBF_NT_ROWS>(hrow + tk) : 0;
+                }
+#pragma unroll
+                for (int k = 0; k < kRowBatch; ++k)
+                    if (y[k] >= 0) mw = T::wmax2(mw, T::edge(hv[k], V[y[k]]));
+            }
+        } else if (fwd_csr<ENC>(I)) {
             // kRowBatch successor indices per lane in flight, then their values
             const GBF_GLOBAL int32_t* row = gp(I.sidx) + c.s0;
             for (uint32_t t = (uint32_t)sub; t < len; t += kRowBatch * G) {
@@ -1087,7 +1124,7 @@ __device__ __forceinline__ PairVal<T> pair_gather(const Inst* __restrict__ It, c
             }
         }
     }
-    return PairVal<T>{mx, cur, graw, len};
+    return PairVal<T>{mx, cur, mw, graw, len};
 }
 
 // Commit phase: max over the group, backup, one candidate per state, strict
@@ -1107,12 +1144,15 @@ __device__ __forceinline__ void pair_commit(const Inst* __restrict__ It, const P
     const int32_t graw = pv.graw;
     const uint32_t len = pv.len;
     const K mx = group_max<T, G>(pv.mx);
+    typename T::wide_t mw = T::WLOWEST;
+    if constexpr (kMayEdge<ENC>) mw = group_wmax<T, G>(pv.mw);
     // candidate value of this pair (INF if it cannot improve V(x))
     K d = (K)T::INF;
     if (c.valid) {
         int sat = 0;
         K dd;
-        if (T::backup(graw, mx, dd, sat) && T::less(dd, cur)) d = dd;
+        const bool ok = has_edge<ENC>(I) ? T::backupw(graw, mw, dd, sat) : T::backup(graw, mx, dd, sat);
+        if (ok && T::less(dd, cur)) d = dd;
         if (sub == 0) {
             acc.pairs += 1;
             acc.edges += len;
@@ -1359,17 +1399,20 @@ static void pick(int G, RelaxFn* rf, PersistFn* pf) {
     }
 }
 
-// enc_mask: bit 0 = some instance uses CSR, bit 1 = BOX, bit 2 = HYB.
+// enc_mask: bit 0 = some instance uses CSR, bit 1 = BOX, bit 2 = HYB,
+// bit 3 = CSR with per-edge costs.
 template <class T>
 static void pick_t(bool multi, int enc_mask, int G, RelaxFn* rf, PersistFn* pf) {
     if (multi) {
         if (enc_mask == 1) pick<T, true, 1>(G, rf, pf);
         else if (enc_mask == 2) pick<T, true, 2>(G, rf, pf);
         else if (enc_mask == 4) pick<T, true, 4>(G, rf, pf);
+        else if (enc_mask == 8) pick<T, true, 5>(G, rf, pf);
         else pick<T, true, 3>(G, rf, pf);
     } else {
         if (enc_mask == 2) pick<T, false, 2>(G, rf, pf);
         else if (enc_mask == 4) pick<T, false, 4>(G, rf, pf);
+        else if (enc_mask == 8) pick<T, false, 5>(G, rf, pf);
         else pick<T, false, 1>(G, rf, pf);
     }
 }
@@ -1383,6 +1426,8 @@ hipError_t launch_seed(const Inst* dI, int ninst, const Run& R, int64_t max_stat
                        hipStream_t s) {
     const int grid = grid_for((max_states + kWave - 1) / kWave, kWavesPerBlock, 4096);
     SeedFn f;
+    // the seed reads only the successor structure: per-edge costs do not matter
+    if (enc_mask == 8) enc_mask = 1;
     if (dtype == 1)
         f = enc_mask == 1 ? k_seed<TF32, 1> : enc_mask == 2 ? k_seed<TF32, 2> : enc_mask == 4 ? k_seed<TF32, 4>
                                                                                          : k_seed<TF32, 3>;
@@ -1411,6 +1456,7 @@ template <class T>
 static SingleFn pick_single_t(int enc_mask, int G) {
     if (enc_mask == 2) return pick_single<T, 2>(G);
     if (enc_mask == 4) return pick_single<T, 4>(G);
+    if (enc_mask == 8) return pick_single<T, 5>(G);
     return pick_single<T, 1>(G);
 }
 
@@ -1504,7 +1550,15 @@ __global__ __launch_bounds__(kBlock) void k_policy(Inst I, int32_t* pol, unsigne
         if (valid) {
             const int64_t p = x * K_ + u;
             K m = (K)T::LOWEST;
-            if (ENC == 1) {
+            typename T::wide_t mw = T::WLOWEST;
+            if (ENC == 5) {
+                const GBF_GLOBAL uint32_t* sptr = gp(I.sptr);
+                const GBF_GLOBAL int32_t* sidx = gp(I.sidx);
+                const GBF_GLOBAL int32_t* h = gp(I.ge);
+                const uint32_t e1 = ldx<GBF_NT_MISC>(sptr + p + 1);
+                for (uint32_t j = ldx<GBF_NT_MISC>(sptr + p); j < e1; ++j)
+                    mw = T::wmax2(mw, T::edge(ldx<GBF_NT_ROWS>(h + j), V[ldx<GBF_NT_ROWS>(sidx + j)]));
+            } else if (ENC == 1) {
                 const GBF_GLOBAL uint32_t* sptr = gp(I.sptr);
                 const GBF_GLOBAL int32_t* sidx = gp(I.sidx);
                 const uint32_t e1 = ldx<GBF_NT_MISC>(sptr + p + 1);
@@ -1528,7 +1582,7 @@ __global__ __launch_bounds__(kBlock) void k_policy(Inst I, int32_t* pol, unsigne
             }
             K dd;
             int sat = 0;
-            if (T::backup(gp(I.g)[p], m, dd, sat)) d = dd;
+            if (ENC == 5 ? T::backupw(gp(I.g)[p], mw, dd, sat) : T::backup(gp(I.g)[p], m, dd, sat)) d = dd;
         }
         sd[lane] = d;
         wave_sync();
@@ -1576,7 +1630,10 @@ __global__ void k_policy_wide(Inst I, int32_t* pol, unsigned long long* bad) {
         for (int u = 0; u < I.K; ++u) {
             const int64_t p = x * I.K + u;
             K m = (K)T::LOWEST;
-            if (I.enc == 0) {
+            typename T::wide_t mw = T::WLOWEST;
+            if (I.enc == 0 && I.ge) {
+                for (uint32_t j = I.sptr[p]; j < I.sptr[p + 1]; ++j) mw = T::wmax2(mw, T::edge(I.ge[j], V[I.sidx[j]]));
+            } else if (I.enc == 0) {
                 for (uint32_t j = I.sptr[p]; j < I.sptr[p + 1]; ++j) m = T::max2(m, V[I.sidx[j]]);
             } else {
                 const BoxDec d = decode_box(I.box[p]);
@@ -1589,7 +1646,8 @@ __global__ void k_policy_wide(Inst I, int32_t* pol, unsigned long long* bad) {
             }
             K d;
             int sat = 0;
-            if (T::backup(I.g[p], m, d, sat) && T::less(d, best)) {
+            const bool ok = (I.enc == 0 && I.ge) ? T::backupw(I.g[p], mw, d, sat) : T::backup(I.g[p], m, d, sat);
+            if (ok && T::less(d, best)) {
                 best = d;
                 pu = u;
             }
@@ -1611,10 +1669,12 @@ hipError_t launch_policy(const Inst& I, int dtype, int32_t* pol, unsigned long l
     const int64_t steps = (I.n + (kWave / I.K) - 1) / (kWave / I.K);
     const int grid = grid_for(steps, kWavesPerBlock, 8192);
     if (dtype == 1) {
-        if (I.enc == 0) k_policy<TF32, 1><<<grid, kBlock, 0, s>>>(I, pol, bad);
+        if (I.enc == 0 && I.ge) k_policy<TF32, 5><<<grid, kBlock, 0, s>>>(I, pol, bad);
+        else if (I.enc == 0) k_policy<TF32, 1><<<grid, kBlock, 0, s>>>(I, pol, bad);
         else k_policy<TF32, 2><<<grid, kBlock, 0, s>>>(I, pol, bad);
     } else {
-        if (I.enc == 0) k_policy<TI32, 1><<<grid, kBlock, 0, s>>>(I, pol, bad);
+        if (I.enc == 0 && I.ge) k_policy<TI32, 5><<<grid, kBlock, 0, s>>>(I, pol, bad);
+        else if (I.enc == 0) k_policy<TI32, 1><<<grid, kBlock, 0, s>>>(I, pol, bad);
         else k_policy<TI32, 2><<<grid, kBlock, 0, s>>>(I, pol, bad);
     }
     return hipGetLastError();

@@ -25,11 +25,29 @@ def test_library_exports_every_declared_symbol():
         assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
 
 
-def test_struct_layouts_match_header():
-    # sizes of the ABI structs as laid out by the C compiler
-    assert ctypes.sizeof(gbf._Problem) == 8 + 4 * 4 + 8 * 5 + 16 + 8 + 16
-    assert ctypes.sizeof(gbf._Opts) == 4 * 2 + 8 + 8 + 4 * 4 + 16
-    assert ctypes.sizeof(gbf._Stats) % 8 == 0
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the binding's structs equal those the C
+    compiler gives the declarations in include/gbf.h."""
+    import os
+    import subprocess
+    structs = {"gbf_problem": gbf._Problem, "gbf_opts": gbf._Opts, "gbf_stats": gbf._Stats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gbf.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-std=c99", "-I", inc, "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
 def test_error_paths_without_gpu_work():
@@ -60,6 +78,12 @@ def test_error_paths_without_gpu_work():
     p.g = ctypes.cast(g, ctypes.c_void_p)
     assert L.gbf_load_graph(ctypes.byref(p), None, ctypes.byref(h)) == gbf.EINVAL
     assert b"expand_box" in L.gbf_last_error()
+    # per-edge costs with the box encoding are rejected before any device work
+    p.expand_box = 0
+    ge = (ctypes.c_int32 * 8)()
+    p.g_edge = ctypes.cast(ge, ctypes.c_void_p)
+    assert L.gbf_load_graph(ctypes.byref(p), None, ctypes.byref(h)) == gbf.EINVAL
+    assert b"per-edge" in L.gbf_last_error()
 
 
 def test_mlp_error_paths_without_gpu_work():
