@@ -116,7 +116,13 @@ typedef struct gbf_problem {
      *   1 = expand the boxes into explicit successor lists and a reverse
      *       CSR on the device at load time (~8 bytes per successor);
      *   2 = successors decoded from the boxes, predecessors from a reverse
-     *       CSR built at load time (~4 bytes per successor). */
+     *       CSR built at load time (~4 bytes per successor);
+     *   3 = memory-budgeted images (Sect. VI-A: the paper's implementation
+     *       keeps computed images of F and pred in memory up to a user
+     *       threshold of its RAM, 68%, and recomputes beyond it): the
+     *       predecessor images of 2 are built if the handle's peak memory
+     *       at load stays within mem_budget, else the problem stays
+     *       implicit as in 0.  gbf_stats.enc_used reports the choice. */
     int32_t expand_box;
     int32_t reserved0;
     /* Optional per-edge part of the running cost (Sect. III-B defines the
@@ -133,7 +139,9 @@ typedef struct gbf_problem {
      * pair cost with one more.  Same memspace as the other arrays; copied
      * at load. */
     const void* g_edge;
-    int32_t reserved[2];
+    /* expand_box 3: device memory budget in bytes for the handle at load;
+     * 0 = 68% of the device memory free at load.  Must be >= 0. */
+    int64_t mem_budget;
 } gbf_problem;
 
 /* ---- solve options --------------------------------------------------- */
@@ -179,6 +187,10 @@ typedef struct gbf_stats {
     int32_t lanes_used;
     int32_t graph_used;     /* 1 = batched solve replayed from a HIP graph */
     int32_t sweeps;         /* bucket order: ascending passes over the buckets */
+    int32_t enc_used;       /* representation the handle holds: 0 CSR, 1 implicit
+                               boxes, 2 boxes + reverse CSR (expand_box 2, or
+                               3 when the predecessor images fit the budget) */
+    int32_t reserved_s;
 } gbf_stats;
 
 typedef struct gbf_graph gbf_graph;

@@ -48,7 +48,7 @@ class _Problem(ctypes.Structure):
                 ("g", ctypes.c_void_p), ("avoid", ctypes.c_void_p), ("succ_ptr", ctypes.c_void_p),
                 ("succ_idx", ctypes.c_void_p), ("dims", ctypes.c_int32 * 4), ("box", ctypes.c_void_p),
                 ("expand_box", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("g_edge", ctypes.c_void_p),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("mem_budget", ctypes.c_int64)]
 
 
 class _Opts(ctypes.Structure):
@@ -66,10 +66,11 @@ class _Stats(ctypes.Structure):
                 ("solve_ms", ctypes.c_double), ("relax_ms", ctypes.c_double),
                 ("relax_launches", ctypes.c_int64), ("barrier_ms", ctypes.c_double), ("device_bytes", ctypes.c_int64),
                 ("mode_used", ctypes.c_int32), ("grid_used", ctypes.c_int32), ("block_used", ctypes.c_int32),
-                ("lanes_used", ctypes.c_int32), ("graph_used", ctypes.c_int32), ("sweeps", ctypes.c_int32)]
+                ("lanes_used", ctypes.c_int32), ("graph_used", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("enc_used", ctypes.c_int32), ("reserved_s", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: (getattr(self, k) if k != "reserved" else None) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
 
 
 EXPORTS = ("gbf_load_graph", "gbf_solve", "gbf_extract_policy", "gbf_solve_batch", "gbf_tune", "gbf_free_graph",
@@ -225,7 +226,7 @@ class Graph:
 
 
 def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=None, succ_idx=None,
-               dims=None, box=None, expand_box=False, g_edge=None, stream=None) -> Graph:
+               dims=None, box=None, expand_box=False, g_edge=None, mem_budget=0, stream=None) -> Graph:
     """gbf_load_graph.  Arrays are numpy (host) or torch tensors on the GPU
     (all of one kind).  G/g (and the optional per-edge costs g_edge, CSR
     only) are int32 or float32 bit patterns."""
@@ -264,6 +265,7 @@ def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=
         for a in range(4):
             p.dims[a] = int(d[a])
         p.expand_box = int(expand_box)
+        p.mem_budget = int(mem_budget)
     if len(spaces) > 1:
         raise ValueError("problem arrays must all be host arrays or all device tensors")
     p.memspace = spaces.pop() if spaces else HOST
@@ -274,20 +276,26 @@ def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=
     return Graph(h, int(n), int(K), p.dtype, None)
 
 
-def load_problem(prob, encoding="csr", stream=None) -> Graph:
+def load_problem(prob, encoding="csr", stream=None, mem_budget=0) -> Graph:
     """Loads an object with the fields of an optimal control problem
     (n, K, dtype, G, g, avoid, succ_ptr/succ_idx or dims/box_packed(), and
     optionally per-edge costs g_edge in succ_idx order).
     encoding: "csr" (explicit lists; expanded from the boxes on the device
     when the object carries no lists), "box" (implicit), "box->csr" or
-    "box+rev" (box successors, reverse CSR for the predecessors).  Per-edge
-    costs need "csr" with explicit lists."""
+    "box+rev" (box successors, reverse CSR for the predecessors), or
+    "box:budget" ("box+rev" if the predecessor images fit `mem_budget`
+    bytes, 0 = 68% of the free device memory, else "box").  Per-edge costs
+    need "csr" with explicit lists."""
     g_edge = getattr(prob, "g_edge", None)
     if g_edge is not None:
         if encoding != "csr" or getattr(prob, "succ_ptr", None) is None:
             raise ValueError("per-edge costs need the csr encoding with explicit successor lists")
         return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="csr", avoid=prob.avoid,
                           succ_ptr=prob.succ_ptr, succ_idx=prob.succ_idx, g_edge=g_edge, stream=stream)
+    if encoding == "box:budget":
+        return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="box", avoid=prob.avoid,
+                          dims=prob.dims, box=prob.box_packed(), expand_box=3, mem_budget=mem_budget,
+                          stream=stream)
     if encoding == "box+rev":
         return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="box", avoid=prob.avoid,
                           dims=prob.dims, box=prob.box_packed(), expand_box=2, stream=stream)

@@ -102,7 +102,14 @@ struct Scratch {
     }
 };
 
+// Default memory budget of expand_box 3: this fraction of the device
+// memory free at load (plus what the handle already holds), the threshold
+// the paper's implementation used for its cache of images.
+constexpr double kDefaultBudgetFraction = 0.68;
+
 struct gbf_graph {
+    int64_t budget_bytes = 0;  // expand_box 3: the budget applied
+    int64_t budget_need = 0;   // expand_box 3: load bytes the predecessor images would have needed
     int64_t n = 0;
     int32_t K = 0;
     int32_t dtype = 0;
@@ -176,8 +183,9 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
     if (p->n_states <= 0 || p->n_inputs <= 0) return fail(GBF_EINVAL, "n_states and n_inputs must be positive");
     if (p->dtype != GBF_I32 && p->dtype != GBF_F32) return fail(GBF_EINVAL, "dtype must be GBF_I32 or GBF_F32");
     if (p->encoding != GBF_CSR && p->encoding != GBF_BOX) return fail(GBF_EINVAL, "bad encoding");
-    if (p->encoding == GBF_BOX && (p->expand_box < 0 || p->expand_box > 2))
-        return fail(GBF_EINVAL, "expand_box must be 0, 1 or 2");
+    if (p->encoding == GBF_BOX && (p->expand_box < 0 || p->expand_box > 3))
+        return fail(GBF_EINVAL, "expand_box must be 0, 1, 2 or 3");
+    if (p->mem_budget < 0) return fail(GBF_EINVAL, "mem_budget must be >= 0");
     if (p->memspace != GBF_HOST && p->memspace != GBF_DEVICE) return fail(GBF_EINVAL, "bad memspace");
     if (!p->G || !p->g) return fail(GBF_EINVAL, "G and g are required");
     if (p->g_edge && p->encoding != GBF_CSR) return fail(GBF_EINVAL, "per-edge costs need GBF_CSR");
@@ -289,10 +297,38 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
         return fail(GBF_EINVAL, msg);
     }
 
+    // expand_box 3: keep the predecessor images (HYB) if their peak at load
+    // fits the memory budget, else stay implicit (BOX)
+    int eb = p->encoding == GBF_BOX ? p->expand_box : 0;
+    if (eb == 3) {
+        uint32_t* sizes;
+        unsigned long long* tot64;
+        if ((rc = M.alloc((void**)&sizes, (np + 1) * 4)) || (rc = M.alloc((void**)&tot64, 8))) return rc;
+        HIPC(hipMemsetAsync(tot64, 0, 8, s));
+        HIPC(launch_box_sizes(I, sizes, tot64, s));
+        unsigned long long total64 = 0;
+        HIPC(hipMemcpyAsync(&total64, tot64, 8, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        M.release(sizes, (np + 1) * 4);
+        M.release(tot64, 8);
+        int64_t budget = p->mem_budget;
+        if (budget == 0) {
+            size_t fr = 0, tot = 0;
+            HIPC(hipMemGetInfo(&fr, &tot));
+            budget = (int64_t)(kDefaultBudgetFraction * (double)(fr + M.bytes));
+        }
+        // peak of the HYB build: temporary successor lists and row pointers,
+        // box sizes, reverse lists, reverse row pointers and counts, scans
+        const int64_t msucc = (int64_t)total64;
+        const int64_t need = msucc * 4 * 2 + (np + 1) * 4 * 3 + (n + 1) * 4 * 2 + ((np + 1023) / 1024 + 2) * 8;
+        eb = (msucc < ((int64_t)1 << 31) && (int64_t)M.bytes + need <= budget) ? 2 : 0;
+        gr->budget_bytes = budget;
+        gr->budget_need = (int64_t)M.bytes + need;
+    }
     // expand_box 2 (HYB): successors stay boxes, predecessors become a
     // reverse CSR built from a temporary expansion
-    const bool hyb = p->encoding == GBF_BOX && p->expand_box == 2;
-    if (p->encoding == GBF_BOX && p->expand_box) {
+    const bool hyb = p->encoding == GBF_BOX && eb == 2;
+    if (p->encoding == GBF_BOX && eb) {
         // materialise F as successor lists on the device (then as CSR below)
         uint32_t *sizes, *sptr, *tmp;
         unsigned long long* tot64;
@@ -660,7 +696,7 @@ static gbf_opts default_opts() {
     return o;
 }
 
-static void fill_stats(gbf_stats* st, int status, const SolveOut& so, int64_t rounds_cap, size_t bytes) {
+static void fill_stats(gbf_stats* st, int status, const SolveOut& so, int64_t rounds_cap, size_t bytes, int enc) {
     if (!st) return;
     std::memset(st, 0, sizeof(*st));
     st->status = status;
@@ -682,6 +718,7 @@ static void fill_stats(gbf_stats* st, int status, const SolveOut& so, int64_t ro
     st->lanes_used = so.lanes;
     st->graph_used = so.graph;
     st->sweeps = so.sweeps;
+    st->enc_used = enc;
 }
 
 static int write_values(gbf_graph* g, void* V_out, int memspace, hipStream_t s) {
@@ -742,7 +779,7 @@ extern "C" int gbf_solve(gbf_graph* g, const gbf_opts* opts, void* V_out, gbf_st
     HIPC(hipEventElapsedTime(&ms, g->scratch.events[0], g->scratch.events[1]));
     so.solve_ms = ms;
     const int status = so.inst_status[0] ? GBF_ENEGCYCLE : GBF_OK;
-    fill_stats(st, status, so, I.max_rounds, g->mem.bytes + g->scratch.mem.bytes);
+    fill_stats(st, status, so, I.max_rounds, g->mem.bytes + g->scratch.mem.bytes, g->enc);
     if (st) st->fallback = fallback;
     g->solved = true;
     if (status != GBF_OK) fail(status, "round cap reached with a non-empty frontier");
@@ -946,7 +983,7 @@ extern "C" int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gb
         const int status = so.inst_status[i] ? GBF_ENEGCYCLE : GBF_OK;
         if (status != GBF_OK) worst = status;
         graphs[i]->solved = true;
-        if (st) fill_stats(st + i, status, so, insts[i].max_rounds, graphs[i]->mem.bytes);
+        if (st) fill_stats(st + i, status, so, insts[i].max_rounds, graphs[i]->mem.bytes, graphs[i]->enc);
     }
     if (worst != GBF_OK) fail(worst, "round cap reached in some instance");
     return worst;

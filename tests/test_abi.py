@@ -71,13 +71,19 @@ def test_error_paths_without_gpu_work():
     p.dtype = gbf.I32
     p.encoding = gbf.BOX
     p.memspace = gbf.HOST
-    p.expand_box = 3
+    p.expand_box = 4
     G = (ctypes.c_int32 * 4)(0, 1, 1, 1)
     g = (ctypes.c_int32 * 4)(1, 1, 1, 1)
     p.G = ctypes.cast(G, ctypes.c_void_p)
     p.g = ctypes.cast(g, ctypes.c_void_p)
     assert L.gbf_load_graph(ctypes.byref(p), None, ctypes.byref(h)) == gbf.EINVAL
     assert b"expand_box" in L.gbf_last_error()
+    # a negative memory budget too
+    p.expand_box = 3
+    p.mem_budget = -1
+    assert L.gbf_load_graph(ctypes.byref(p), None, ctypes.byref(h)) == gbf.EINVAL
+    assert b"mem_budget" in L.gbf_last_error()
+    p.mem_budget = 0
     # per-edge costs with the box encoding are rejected before any device work
     p.expand_box = 0
     ge = (ctypes.c_int32 * 8)()
