@@ -89,7 +89,7 @@ def lib():
         if _lib is None:
             if not os.path.exists(LIB_PATH):
                 raise ImportError(f"{LIB_PATH} is missing: build it with "
-                                  "`python -c 'import __graft_entry__ as e; e.build()'`")
+                                  "`python paper_2001_06231_amd/build.py`")
             L = ctypes.CDLL(LIB_PATH)
             P = ctypes.c_void_p
             L.gbf_load_graph.argtypes = [ctypes.POINTER(_Problem), P, ctypes.POINTER(P)]
