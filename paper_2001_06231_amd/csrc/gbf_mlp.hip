@@ -747,7 +747,7 @@ extern "C" int gbf_mlp_bucket_keys(gbf_mlp* m, const int32_t dims[4], float tcx,
         vh = m->scratch_v;
     }
     // blocks of the key kernel: 4 waves x 32 cells per step, at most
-    // GBF_VHAT_BLOCKS (each block loads the weights into LDS once)
+    // GBF_VHAT_BLOCKS (each wave loads its weight operands once and loops)
     const int64_t nb = std::min<int64_t>((n + 127) / 128, GBF_VHAT_BLOCKS);
     if (m->bmin_blocks < nb + 1) {
         if (m->bmin) dfree(m, m->bmin);
