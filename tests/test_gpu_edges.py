@@ -221,3 +221,29 @@ def test_chained_solves():
     _exact(r2, _solve(p2), "chain-2")
     # chaining can only lower values: V2 <= G2 = V1
     assert (r2["V"].astype(np.int64) <= r1["V"].astype(np.int64)).all()
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_tiny_edges_arbitrary_sign(seed):
+    """Per-edge costs of both signs, negative cycles possible: a diverging
+    Kleene iteration must end at the round cap on the GPU; otherwise the
+    GPU's values are the Kleene limit."""
+    import math
+    from oracle import brute
+    n, K = 3 + seed % 5, 1 + seed % 3
+    prob = synth.random_small_edges(7100 + seed, n, K)
+    _case(f"tiny edges arbitrary seed={seed}")
+    mode = MODES[seed % 3]
+    gr = gbf.load_problem(prob)
+    status, stats, V = gr.solve(mode=mode)
+    try:
+        kl, _ = brute.kleene(prob)
+    except brute.Diverged:
+        assert status == gbf.ENEGCYCLE
+        gr.free()
+        return
+    if status == gbf.ENEGCYCLE:
+        status, stats, V = gr.solve(mode=mode, max_rounds=100 * n)
+    assert status == gbf.OK
+    assert [math.inf if v == 2**31 - 1 else int(v) for v in V] == kl
+    gr.free()
