@@ -42,3 +42,20 @@ def test_lists_only_problem_skips_box(monkeypatch):
                                                                             "grid": 0}, 1.0)))
     assert T.autotune([prob])["encoding"] == "csr"
     assert seen == ["csr"]
+
+
+def test_edge_costs_tune_only_lists(monkeypatch):
+    """Problems with per-edge costs are tuned on explicit successor lists
+    only, under a signature of their own."""
+    base = synth.grid2d_small()
+    prob = synth.with_edge_costs(base, 3)
+    assert T.signature([prob]) != T.signature([base])
+    seen = []
+
+    def fake(probs, enc, reps):
+        seen.append(enc)
+        return {"mode": "hostloop", "lanes": 4, "grid": 1024}, 1.0
+
+    monkeypatch.setattr(T, "_measure", fake)
+    best = T.autotune([prob])
+    assert seen == ["csr"] and best["encoding"] == "csr"
