@@ -148,3 +148,32 @@ def test_successor_limit_rejected():
     L = gbf.lib()
     assert L.gbf_load_graph(ctypes.byref(p), None, ctypes.byref(h)) == gbf.EINVAL
     assert b"2^31" in L.gbf_last_error()
+
+
+def _check_f32(prob, mode):
+    ref = oracle.solve(prob, precision="f32")
+    gr = gbf.load_problem(prob)
+    status, st, V = gr.solve(mode=mode)
+    assert status == gbf.OK and ref["status"] == oracle.OK
+    pol, res = gr.policy()
+    assert res == 0
+    same = (V == ref["V"]) | (np.isnan(V) & np.isnan(ref["V"]))
+    assert same.all() and np.array_equal(pol, ref["policy"])
+    gr.free()
+    return ref
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_fp32_overflow_and_signed_zero(mode):
+    """fp32 sums that overflow to +inf count as INF (no candidate), and
+    -0.0 costs and terminal values compare equal to +0.0."""
+    _case(f"fp32 overflow / -0 {mode}")
+    big = np.float32(3.0e38)
+    rows = [[1], [2], [2], [2], [3], [0, 4]]
+    g = [big, big, 0.0, -0.0, 1.5, 2.0]     # 0 -> 1 -> 2 costs big + big: overflow
+    G = [np.inf, np.inf, -0.0, np.inf, np.inf, np.inf]
+    prob = synth.explicit_problem(6, 1, rows, g, G, dtype="f32")
+    ref = _check_f32(prob, mode)
+    assert ref["V"][1] == big and np.isinf(ref["V"][0])   # big + big overflows
+    assert ref["V"][2] == 0.0 and ref["V"][3] == 0.0 and ref["V"][4] == 1.5
+    assert np.isinf(ref["V"][5])                          # max over {INF, 1.5}
