@@ -198,14 +198,16 @@ typedef struct gbf_graph gbf_graph;
 /* Validates a problem, copies it to device memory owned by the handle and
  * builds what the solver needs: the reverse adjacency pred (Sect. IV-A,
  * pred(x,u) = { y : x in F(y,u) }) as a pair-level reverse CSR for
- * GBF_CSR (and GBF_BOX with expand_box 1 or 2), or per-input predecessor
- * windows for GBF_BOX with expand_box 0; pairs that can
+ * GBF_CSR (and GBF_BOX with expand_box 1 or 2, or 3 within the memory
+ * budget), or per-input predecessor windows for GBF_BOX with expand_box 0
+ * (or 3 over the budget); pairs that can
  * never improve a value (g = INF, avoid source, or a successor in the avoid
  * set) are pruned.  `hip_stream` is a hipStream_t (NULL = default stream)
  * on which all later work of this handle is ordered.
  * Errors: GBF_EINVAL (n or K <= 0, empty F(x,u), index or box outside the
- * grid, NaN or -inf cost, finite G on an avoid cell, m >= 2^31),
- * GBF_ENOMEM, GBF_EHIP.  On error *out is NULL. */
+ * grid, NaN or -inf cost, finite G on an avoid cell, m >= 2^31, per-edge
+ * costs that are not finite or come with GBF_BOX, expand_box outside 0..3,
+ * mem_budget < 0), GBF_ENOMEM, GBF_EHIP.  On error *out is NULL. */
 int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph** out);
 
 /* Runs Algorithm 1 (Sect. IV-A) until the frontier is empty or the round
