@@ -8,6 +8,19 @@ if the library is missing, importing a function raises.
 Names follow the paper (Weber, Kreuzer, Knoll, Sect. III-C and IV-A):
 a problem is (X, U, F, G, g), the solver returns the value function V and a
 controller (policy) that realizes it.
+
+Use (arrays on the host or torch tensors on the GPU)::
+
+    import paper_2001_06231_amd as gbf
+    g = gbf.load_graph(n, K, G, g_pair, succ_ptr=ptr, succ_idx=idx, avoid=av)
+    status, stats, V = g.solve()          # V: numpy, or pass V_out=<tensor>
+    policy, residual = g.policy()         # -1 hand over, -2 no controller
+    g.free()
+
+``load_problem`` takes an object with those fields (see ``synth``) and an
+encoding ("csr", "box", "box+rev", "box->csr", "box:budget");
+``solve_batch`` solves many handles in one frontier; ``MLP`` is the
+frontier-ordering network (keys for ``solve(order="buckets", ...)``).
 """
 from __future__ import annotations
 
