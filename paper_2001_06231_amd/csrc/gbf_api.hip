@@ -645,7 +645,7 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
     if ((rc = enqueue_init(S, P, insts, s))) return rc;
     if (P.mode == GBF_MODE_SINGLE_BLOCK) {
         if (o.profile) HIPC(hipEventRecord(S.events[2], s));
-        HIPC(launch_single(S.dinst, P.R, P.lanes, dtype, P.enc_mask, s));
+        HIPC(launch_single(S.dinst, P.R, P.lanes, dtype, P.enc_mask, P.max_states, s));
         if (o.profile) HIPC(hipEventRecord(S.events[3], s));
         if ((rc = enqueue_readback(S, P, s))) return rc;
         HIPC(hipStreamSynchronize(s));

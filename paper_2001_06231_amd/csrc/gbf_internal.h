@@ -95,7 +95,8 @@ hipError_t launch_persistent(const Inst* dI, const Run& R, int grid, int lanes, 
                              bool attr_launch, hipStream_t s);
 int persistent_blocks_per_cu(const Run& R, int lanes, int dtype, int enc_mask);
 // all rounds of one instance in a single 1024-thread workgroup
-hipError_t launch_single(const Inst* dI, const Run& R, int lanes, int dtype, int enc_mask, hipStream_t s);
+hipError_t launch_single(const Inst* dI, const Run& R, int lanes, int dtype, int enc_mask, int64_t n_states,
+                         hipStream_t s);
 hipError_t launch_sum_slots(const unsigned long long* slots, int nslots, unsigned long long* ctr, hipStream_t s);
 hipError_t launch_sort_rows(const uint32_t* rptr, uint32_t* rev, int64_t n, hipStream_t s);
 hipError_t launch_decode(const Inst& I, int dtype, void* out, hipStream_t s);

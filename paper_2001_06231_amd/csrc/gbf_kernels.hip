@@ -44,6 +44,9 @@
 #ifndef GBF_ROW_BATCH
 #define GBF_ROW_BATCH 4  // successor indices loaded together per lane (CSR relax)
 #endif
+#ifndef GBF_SMALL_LDS
+#define GBF_SMALL_LDS 1  // single-block mode on small CSR instances keeps V, frontiers and list in LDS
+#endif
 #ifndef GBF_ILP
 #define GBF_ILP 1  // wave steps whose gathers a host-loop relax wave keeps in flight together (2+ measured slower)
 #endif
@@ -1380,6 +1383,157 @@ __global__ __launch_bounds__(kPBlock) void k_single(const Inst* __restrict__ It,
     flush_acc(acc, s_acc, R.slots);
 }
 
+// Small instances (CSR, one instance, at most kSmallPairs pairs and
+// kSmallStates states): the single-block solver with V, both frontiers (as
+// bitmaps) and the frontier list in LDS.  Only the read-only successor and
+// reverse rows, costs and row bounds come from global memory; a round's
+// dependent accesses to V, the marks and the list stay on the CU.  V is
+// loaded from (and at the end written back to) global memory; the seeded
+// byte map is converted once.
+constexpr int kSmallPairs = 16384;
+constexpr int kSmallStates = 6144;
+constexpr int kSmallWords = kSmallPairs / 32;
+
+template <class T, int G>
+__global__ __launch_bounds__(kPBlock) void k_small(const Inst* __restrict__ It, Run R) {
+    using K = typename T::key_t;
+    constexpr int NW = kPBlock / kWave;
+    constexpr int W = kWave / G;  // pairs per wave step
+    __shared__ K s_V[kSmallStates];
+    __shared__ uint16_t s_list[kSmallPairs];
+    __shared__ uint32_t s_bits[2][kSmallWords];
+    __shared__ int s_w[NW];
+    __shared__ AccLds s_acc;
+    acc_init(s_acc);
+    Acc acc;
+    const Inst& I = It[0];
+    const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+    const int sub = lane & (G - 1), grp = lane / G;
+    const int n = (int)I.n, KK = I.K, np = n * KK;
+    const int nwords = (np + 31) / 32;  // <= kSmallWords <= kPBlock
+    GBF_GLOBAL K* Vg = gp(static_cast<K*>(I.V));
+    const GBF_GLOBAL uint32_t* sptr = gp(I.sptr);
+    const GBF_GLOBAL int32_t* sidx = gp(I.sidx);
+    const GBF_GLOBAL int32_t* gc = gp(I.g);
+    const GBF_GLOBAL uint32_t* rptr = gp(I.rptr);
+    const GBF_GLOBAL uint32_t* rev = gp(I.rev);
+    for (int i = t; i < n; i += kPBlock) s_V[i] = Vg[i];
+    {
+        const GBF_GLOBAL uint8_t* d0 = gp(R.dirty[0]);
+        if (t < nwords) {
+            uint32_t bits = 0;
+            for (int b = 0; b < 32; ++b) {
+                const int q = t * 32 + b;
+                if (q < np && d0[q]) bits |= 1u << b;
+            }
+            s_bits[0][t] = bits;
+            s_bits[1][t] = 0u;
+        }
+    }
+    __syncthreads();
+    for (int round = 0;; ++round) {
+        uint32_t* cur = s_bits[round & 1];
+        uint32_t* nxt = s_bits[(round + 1) & 1];
+        // frontier list, ascending, from the bits (one word per thread)
+        uint32_t word = t < nwords ? cur[t] : 0u;
+        const int c = __popc(word);
+        const int incl = wave_incl_scan(c);
+        if (lane == kWave - 1) s_w[w] = incl;
+        __syncthreads();
+        int wofs = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int v = s_w[k];
+            wofs += k < w ? v : 0;
+            tot += v;
+        }
+        uint32_t pos = (uint32_t)(wofs + incl - c);
+        while (word) {
+            const int b = __ffs(word) - 1;
+            s_list[pos++] = (uint16_t)(t * 32 + b);
+            word &= word - 1u;
+        }
+        if (t < nwords) cur[t] = 0u;
+        const uint32_t count = (uint32_t)tot;
+        if (t == 0) R.counts[round] = count;
+        __syncthreads();  // list complete; s_w read by every thread
+        if (count == 0) {
+            if (t == 0) R.result[0] = round;
+            break;
+        }
+        if (round >= I.max_rounds) {
+            // the round cap (second condition of Algorithm 1's while loop)
+            // with work left: drop the frontier, flag the instance
+            if (t == 0) R.inst_status[0] = 1;
+            continue;
+        }
+        for (uint32_t first = (uint32_t)(w * W); first < count; first += (uint32_t)(NW * W)) {
+            const uint32_t i = first + (uint32_t)grp;
+            const bool valid = i < count;
+            const uint32_t q = valid ? (uint32_t)s_list[i] : 0u;
+            const uint32_t x = q / (uint32_t)KK;
+            K mx = (K)T::LOWEST, cv = (K)T::INF;
+            uint32_t len = 0;
+            int32_t graw = 0;
+            if (valid) {
+                const uint32_t s0 = sptr[q];
+                len = sptr[q + 1] - s0;
+                graw = gc[q];
+                cv = s_V[x];
+                for (uint32_t e = (uint32_t)sub; e < len; e += G) mx = T::max2(mx, s_V[sidx[s0 + e]]);
+            }
+            mx = group_max<T, G>(mx);
+            K d = (K)T::INF;
+            if (valid) {
+                int sat = 0;
+                K dd;
+                if (T::backup(graw, mx, dd, sat) && T::less(dd, cv)) d = dd;
+                if (sub == 0) {
+                    acc.pairs += 1;
+                    acc.edges += len;
+                    acc.sat += (unsigned)sat;
+                }
+            }
+            // one candidate per state and wave step (its pairs are adjacent)
+            const uint32_t key = valid ? x : 0xffffffffu;
+#pragma unroll
+            for (int st = 1; st < W; st <<= 1) {
+                const K od = __shfl_down(d, st * G, kWave);
+                const uint32_t ok = __shfl_down(key, st * G, kWave);
+                if (grp + st < W && ok == key) d = T::less(od, d) ? od : d;
+            }
+            const uint32_t pkey = __shfl_up(key, G, kWave);
+            const bool head = valid && sub == 0 && (grp == 0 || pkey != key);
+            bool expand = false;
+            if (head && T::less(d, cv)) {
+                atomicMin(&s_V[x], d);
+                acc.impr += 1;
+                expand = true;
+            }
+            unsigned long long bal = __ballot(expand);
+            while (bal) {
+                const int l = __ffsll(bal) - 1;
+                bal &= bal - 1;
+                const uint32_t xl = __shfl(x, l, kWave);
+                const uint32_t r0 = rptr[xl], rl = rptr[xl + 1] - r0;
+                if (lane == 0) {
+                    acc.expanded += 1;
+                    acc.marks += rl;
+                }
+                for (uint32_t e = (uint32_t)lane; e < rl; e += kWave) {
+                    const uint32_t qp = rev[r0 + e];
+                    atomicOr(&nxt[qp >> 5], 1u << (qp & 31u));
+                }
+            }
+        }
+        fold_acc(acc, s_acc);
+        __syncthreads();  // every mark of the round is in nxt
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += kPBlock) Vg[i] = s_V[i];
+    flush_acc(acc, s_acc, R.slots);
+}
+
 // ------------------------------------------------------------------ dispatch
 // Kernel variants: value type (int32 / fp32 key), single or batched
 // instance table, encoding (1 CSR, 2 BOX, 3 mixed batch) and lanes per pair.
@@ -1460,8 +1614,25 @@ static SingleFn pick_single_t(int enc_mask, int G) {
     return pick_single<T, 1>(G);
 }
 
-hipError_t launch_single(const Inst* dI, const Run& R, int lanes, int dtype, int enc_mask, hipStream_t s) {
-    const SingleFn f = dtype == 1 ? pick_single_t<TF32>(enc_mask, lanes) : pick_single_t<TI32>(enc_mask, lanes);
+template <class T>
+static SingleFn pick_small(int G) {
+    switch (G) {
+        case 1: return k_small<T, 1>;
+        case 2: return k_small<T, 2>;
+        case 8: return k_small<T, 8>;
+        case 16: return k_small<T, 16>;
+        case 32: return k_small<T, 32>;
+        default: return k_small<T, 4>;
+    }
+}
+
+hipError_t launch_single(const Inst* dI, const Run& R, int lanes, int dtype, int enc_mask, int64_t n_states,
+                         hipStream_t s) {
+    SingleFn f;
+    if (GBF_SMALL_LDS && enc_mask == 1 && R.ninst == 1 && R.total_pairs <= kSmallPairs && n_states <= kSmallStates)
+        f = dtype == 1 ? pick_small<TF32>(lanes) : pick_small<TI32>(lanes);
+    else
+        f = dtype == 1 ? pick_single_t<TF32>(enc_mask, lanes) : pick_single_t<TI32>(enc_mask, lanes);
     f<<<1, kPBlock, 0, s>>>(dI, R);
     return hipGetLastError();
 }
