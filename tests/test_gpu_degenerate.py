@@ -112,7 +112,7 @@ def test_chain(mode):
     assert list(ref["V"]) == list(range(n))
 
 
-@pytest.mark.parametrize("mode", ["hostloop", "persistent"])
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("K", [63, 64, 65, 130])
 def test_many_inputs(mode, K):
     """K around and above the wave width (the policy kernel switches to its
