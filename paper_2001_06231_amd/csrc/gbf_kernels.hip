@@ -1383,7 +1383,7 @@ __global__ __launch_bounds__(kPBlock) void k_single(const Inst* __restrict__ It,
     flush_acc(acc, s_acc, R.slots);
 }
 
-// Small instances (CSR, one instance, at most kSmallPairs pairs and
+// Small instances (CSR, with or without per-edge costs, one instance, at most kSmallPairs pairs and
 // kSmallStates states): the single-block solver with V, both frontiers (as
 // bitmaps) and the frontier list in LDS.  Only the read-only successor and
 // reverse rows, costs and row bounds come from global memory; a round's
@@ -1394,7 +1394,7 @@ constexpr int kSmallPairs = 16384;
 constexpr int kSmallStates = 6144;
 constexpr int kSmallWords = kSmallPairs / 32;
 
-template <class T, int G>
+template <class T, int G, bool EDGE>
 __global__ __launch_bounds__(kPBlock) void k_small(const Inst* __restrict__ It, Run R) {
     using K = typename T::key_t;
     constexpr int NW = kPBlock / kWave;
@@ -1417,6 +1417,7 @@ __global__ __launch_bounds__(kPBlock) void k_small(const Inst* __restrict__ It, 
     const GBF_GLOBAL int32_t* gc = gp(I.g);
     const GBF_GLOBAL uint32_t* rptr = gp(I.rptr);
     const GBF_GLOBAL uint32_t* rev = gp(I.rev);
+    const GBF_GLOBAL int32_t* hc = gp(I.ge);  // EDGE: per-edge costs
     for (int i = t; i < n; i += kPBlock) s_V[i] = Vg[i];
     {
         const GBF_GLOBAL uint8_t* d0 = gp(R.dirty[0]);
@@ -1473,6 +1474,7 @@ __global__ __launch_bounds__(kPBlock) void k_small(const Inst* __restrict__ It, 
             const uint32_t q = valid ? (uint32_t)s_list[i] : 0u;
             const uint32_t x = q / (uint32_t)KK;
             K mx = (K)T::LOWEST, cv = (K)T::INF;
+            typename T::wide_t mw = T::WLOWEST;
             uint32_t len = 0;
             int32_t graw = 0;
             if (valid) {
@@ -1480,14 +1482,21 @@ __global__ __launch_bounds__(kPBlock) void k_small(const Inst* __restrict__ It, 
                 len = sptr[q + 1] - s0;
                 graw = gc[q];
                 cv = s_V[x];
-                for (uint32_t e = (uint32_t)sub; e < len; e += G) mx = T::max2(mx, s_V[sidx[s0 + e]]);
+                if (EDGE) {
+                    for (uint32_t e = (uint32_t)sub; e < len; e += G)
+                        mw = T::wmax2(mw, T::edge(hc[s0 + e], s_V[sidx[s0 + e]]));
+                } else {
+                    for (uint32_t e = (uint32_t)sub; e < len; e += G) mx = T::max2(mx, s_V[sidx[s0 + e]]);
+                }
             }
-            mx = group_max<T, G>(mx);
+            if (EDGE) mw = group_wmax<T, G>(mw);
+            else mx = group_max<T, G>(mx);
             K d = (K)T::INF;
             if (valid) {
                 int sat = 0;
                 K dd;
-                if (T::backup(graw, mx, dd, sat) && T::less(dd, cv)) d = dd;
+                const bool ok = EDGE ? T::backupw(graw, mw, dd, sat) : T::backup(graw, mx, dd, sat);
+                if (ok && T::less(dd, cv)) d = dd;
                 if (sub == 0) {
                     acc.pairs += 1;
                     acc.edges += len;
@@ -1614,24 +1623,26 @@ static SingleFn pick_single_t(int enc_mask, int G) {
     return pick_single<T, 1>(G);
 }
 
-template <class T>
+template <class T, bool EDGE>
 static SingleFn pick_small(int G) {
     switch (G) {
-        case 1: return k_small<T, 1>;
-        case 2: return k_small<T, 2>;
-        case 8: return k_small<T, 8>;
-        case 16: return k_small<T, 16>;
-        case 32: return k_small<T, 32>;
-        default: return k_small<T, 4>;
+        case 1: return k_small<T, 1, EDGE>;
+        case 2: return k_small<T, 2, EDGE>;
+        case 8: return k_small<T, 8, EDGE>;
+        case 16: return k_small<T, 16, EDGE>;
+        case 32: return k_small<T, 32, EDGE>;
+        default: return k_small<T, 4, EDGE>;
     }
 }
 
 hipError_t launch_single(const Inst* dI, const Run& R, int lanes, int dtype, int enc_mask, int64_t n_states,
                          hipStream_t s) {
     SingleFn f;
-    if (GBF_SMALL_LDS && enc_mask == 1 && R.ninst == 1 && R.total_pairs <= kSmallPairs && n_states <= kSmallStates)
-        f = dtype == 1 ? pick_small<TF32>(lanes) : pick_small<TI32>(lanes);
-    else
+    if (GBF_SMALL_LDS && (enc_mask == 1 || enc_mask == 8) && R.ninst == 1 && R.total_pairs <= kSmallPairs &&
+        n_states <= kSmallStates) {
+        if (enc_mask == 8) f = dtype == 1 ? pick_small<TF32, true>(lanes) : pick_small<TI32, true>(lanes);
+        else f = dtype == 1 ? pick_small<TF32, false>(lanes) : pick_small<TI32, false>(lanes);
+    } else
         f = dtype == 1 ? pick_single_t<TF32>(enc_mask, lanes) : pick_single_t<TI32>(enc_mask, lanes);
     f<<<1, kPBlock, 0, s>>>(dI, R);
     return hipGetLastError();
