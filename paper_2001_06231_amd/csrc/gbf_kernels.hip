@@ -1383,7 +1383,7 @@ __global__ __launch_bounds__(kPBlock) void k_single(const Inst* __restrict__ It,
     flush_acc(acc, s_acc, R.slots);
 }
 
-// Small instances (CSR, with or without per-edge costs, one instance, at most kSmallPairs pairs and
+// Small instances (CSR with or without per-edge costs, or HYB; one instance, at most kSmallPairs pairs and
 // kSmallStates states): the single-block solver with V, both frontiers (as
 // bitmaps) and the frontier list in LDS.  Only the read-only successor and
 // reverse rows, costs and row bounds come from global memory; a round's
@@ -1394,7 +1394,7 @@ constexpr int kSmallPairs = 16384;
 constexpr int kSmallStates = 6144;
 constexpr int kSmallWords = kSmallPairs / 32;
 
-template <class T, int G, bool EDGE>
+template <class T, int G, bool EDGE, bool HYB>
 __global__ __launch_bounds__(kPBlock) void k_small(const Inst* __restrict__ It, Run R) {
     using K = typename T::key_t;
     constexpr int NW = kPBlock / kWave;
@@ -1477,7 +1477,21 @@ __global__ __launch_bounds__(kPBlock) void k_small(const Inst* __restrict__ It, 
             typename T::wide_t mw = T::WLOWEST;
             uint32_t len = 0;
             int32_t graw = 0;
-            if (valid) {
+            if (valid && HYB) {
+                // the box is w1*w2*w3 rows of w0 consecutive cells along axis 0
+                graw = gc[q];
+                cv = s_V[x];
+                const BoxDec bd = decode_box(gp(I.box)[q]);
+                const uint32_t w0 = bd.e[0] + 1, w1 = bd.e[1] + 1, w2 = bd.e[2] + 1;
+                const uint32_t nrows = w1 * w2 * (uint32_t)(bd.e[3] + 1);
+                len = w0 * nrows;
+                for (uint32_t r = (uint32_t)sub; r < nrows; r += G) {
+                    const uint32_t r2 = r / w1, j1 = r - r2 * w1, j3 = r2 / w2, j2 = r2 - j3 * w2;
+                    const uint32_t b0 = (uint32_t)bd.lo + j1 * (uint32_t)I.strides[1] + j2 * (uint32_t)I.strides[2] +
+                                        j3 * (uint32_t)I.strides[3];
+                    for (uint32_t j0 = 0; j0 < w0; ++j0) mx = T::max2(mx, s_V[b0 + j0]);
+                }
+            } else if (valid) {
                 const uint32_t s0 = sptr[q];
                 len = sptr[q + 1] - s0;
                 graw = gc[q];
@@ -1623,25 +1637,26 @@ static SingleFn pick_single_t(int enc_mask, int G) {
     return pick_single<T, 1>(G);
 }
 
-template <class T, bool EDGE>
+template <class T, bool EDGE, bool HYB>
 static SingleFn pick_small(int G) {
     switch (G) {
-        case 1: return k_small<T, 1, EDGE>;
-        case 2: return k_small<T, 2, EDGE>;
-        case 8: return k_small<T, 8, EDGE>;
-        case 16: return k_small<T, 16, EDGE>;
-        case 32: return k_small<T, 32, EDGE>;
-        default: return k_small<T, 4, EDGE>;
+        case 1: return k_small<T, 1, EDGE, HYB>;
+        case 2: return k_small<T, 2, EDGE, HYB>;
+        case 8: return k_small<T, 8, EDGE, HYB>;
+        case 16: return k_small<T, 16, EDGE, HYB>;
+        case 32: return k_small<T, 32, EDGE, HYB>;
+        default: return k_small<T, 4, EDGE, HYB>;
     }
 }
 
 hipError_t launch_single(const Inst* dI, const Run& R, int lanes, int dtype, int enc_mask, int64_t n_states,
                          hipStream_t s) {
     SingleFn f;
-    if (GBF_SMALL_LDS && (enc_mask == 1 || enc_mask == 8) && R.ninst == 1 && R.total_pairs <= kSmallPairs &&
-        n_states <= kSmallStates) {
-        if (enc_mask == 8) f = dtype == 1 ? pick_small<TF32, true>(lanes) : pick_small<TI32, true>(lanes);
-        else f = dtype == 1 ? pick_small<TF32, false>(lanes) : pick_small<TI32, false>(lanes);
+    if (GBF_SMALL_LDS && (enc_mask == 1 || enc_mask == 4 || enc_mask == 8) && R.ninst == 1 &&
+        R.total_pairs <= kSmallPairs && n_states <= kSmallStates) {
+        if (enc_mask == 8) f = dtype == 1 ? pick_small<TF32, true, false>(lanes) : pick_small<TI32, true, false>(lanes);
+        else if (enc_mask == 4) f = dtype == 1 ? pick_small<TF32, false, true>(lanes) : pick_small<TI32, false, true>(lanes);
+        else f = dtype == 1 ? pick_small<TF32, false, false>(lanes) : pick_small<TI32, false, false>(lanes);
     } else
         f = dtype == 1 ? pick_single_t<TF32>(enc_mask, lanes) : pick_single_t<TI32>(enc_mask, lanes);
     f<<<1, kPBlock, 0, s>>>(dI, R);
