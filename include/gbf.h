@@ -253,6 +253,16 @@ int gbf_tune(gbf_graph* const* graphs, int32_t count, const gbf_opts* base, int3
 /* Releases a handle (NULL is allowed). */
 void gbf_free_graph(gbf_graph* g);
 
+/* Releases the state the library keeps across calls: the batch contexts of
+ * gbf_solve_batch (their scratch, private streams and captured HIP graphs).
+ * Handles stay valid; a later batch call rebuilds its context.  The library
+ * never releases this state from a static destructor (those run at process
+ * exit, possibly after the HIP runtime has shut down), so a program that
+ * wants it freed calls this while the runtime is up, e.g. from an exit
+ * handler after freeing its handles.  It waits for a batch call running in
+ * another thread to finish. */
+void gbf_shutdown(void);
+
 /* ---- frontier-ordering network -----------------------------------------
  * A multilayer perceptron 4 -> 64 -> 64 -> 1 with ReLU, trained on value
  * functions the solver produced, that predicts V from the coordinates of a

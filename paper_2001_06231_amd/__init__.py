@@ -24,9 +24,11 @@ frontier-ordering network (keys for ``solve(order="buckets", ...)``).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import threading
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -87,12 +89,32 @@ class _Stats(ctypes.Structure):
 
 
 EXPORTS = ("gbf_load_graph", "gbf_solve", "gbf_extract_policy", "gbf_solve_batch", "gbf_tune", "gbf_free_graph",
-           "gbf_last_error", "gbf_mlp_create", "gbf_mlp_set_params", "gbf_mlp_get_params", "gbf_mlp_samples",
+           "gbf_last_error", "gbf_shutdown", "gbf_mlp_create", "gbf_mlp_set_params", "gbf_mlp_get_params", "gbf_mlp_samples",
            "gbf_mlp_forward", "gbf_mlp_grad", "gbf_mlp_train_step", "gbf_mlp_bucket_keys", "gbf_mlp_free")
 MLP_NPARAMS = 4545
 
 _lock = threading.Lock()
 _lib = None
+# live handles (graphs, networks): released by the exit handler below while
+# the HIP runtime is still up; afterwards every release is a no-op
+_live = weakref.WeakSet()
+_closed = False
+
+
+def _shutdown():
+    """Exit handler: frees every live handle and the library's batch state
+    (captured graphs, streams) before the HIP runtime shuts down."""
+    global _closed
+    if _closed or _lib is None:
+        _closed = True
+        return
+    for obj in list(_live):
+        try:
+            obj.free()
+        except Exception:
+            pass
+    _lib.gbf_shutdown()
+    _closed = True
 
 
 def lib():
@@ -121,6 +143,8 @@ def lib():
             L.gbf_free_graph.restype = None
             L.gbf_last_error.argtypes = []
             L.gbf_last_error.restype = ctypes.c_char_p
+            L.gbf_shutdown.argtypes = []
+            L.gbf_shutdown.restype = None
             I64, F, I = ctypes.c_int64, ctypes.c_float, ctypes.c_int32
             D4 = ctypes.POINTER(ctypes.c_int32)
             for name, args in (
@@ -139,6 +163,8 @@ def lib():
             L.gbf_mlp_free.argtypes = [P]
             L.gbf_mlp_free.restype = None
             _lib = L
+            # registered after torch's own handlers, so it runs before them
+            atexit.register(_shutdown)
     return _lib
 
 
@@ -179,6 +205,7 @@ class Graph:
         self._h = handle
         self.n, self.K, self.dtype = n, K, dtype
         self._keep = keep
+        _live.add(self)
 
     def __del__(self):
         self.free()
@@ -186,7 +213,7 @@ class Graph:
     def free(self):
         if getattr(self, "_h", None):
             L = _lib
-            if L is not None:
+            if L is not None and not _closed:
                 L.gbf_free_graph(self._h)
             self._h = None
 
@@ -406,13 +433,14 @@ class MLP:
         if rc != OK:
             raise _err(L, rc)
         self._h = h
+        _live.add(self)
 
     def __del__(self):
         self.free()
 
     def free(self):
         if getattr(self, "_h", None):
-            if _lib is not None:
+            if _lib is not None and not _closed:
                 _lib.gbf_mlp_free(self._h)
             self._h = None
 

@@ -435,7 +435,7 @@ struct SolveOut {
     double solve_ms = 0, relax_ms = 0, barrier_ms = 0;
     int64_t relax_launches = 0;
     int mode = 0, grid = 0, block = 0, lanes = 0, graph = 0, sweeps = 0;
-    std::vector<int32_t> inst_status;
+    int32_t inst_status[kMaxBatch] = {};  // per instance: 1 = round cap reached with work left
 };
 
 // Everything needed to enqueue one solve over a table of instances.
@@ -447,12 +447,13 @@ struct Plan {
     bool bucket = false;
 };
 
-static int plan_solve(Scratch& S, const std::vector<Inst>& insts, int dtype, const gbf_opts& o, int cus,
+static int plan_solve(Scratch& S, const Inst* insts, int ninst, int dtype, const gbf_opts& o, int cus,
                       int clock_khz, Plan& P) {
-    P.ninst = (int)insts.size();
+    P.ninst = ninst;
     P.dtype = dtype;
     int64_t total_pairs = 0;
-    for (const Inst& I : insts) {
+    for (int i = 0; i < ninst; ++i) {
+        const Inst& I = insts[i];
         total_pairs = std::max<int64_t>(total_pairs, I.pair_base + I.n * I.K);
         P.max_rounds = std::max<int64_t>(P.max_rounds, I.max_rounds);
         P.max_states = std::max<int64_t>(P.max_states, I.n);
@@ -533,7 +534,7 @@ static int plan_solve(Scratch& S, const std::vector<Inst>& insts, int dtype, con
 }
 
 // Fills, W <- G, seed.  Kernels only (no memset), so it can be captured.
-static int enqueue_init(Scratch& S, const Plan& P, const std::vector<Inst>& insts, hipStream_t s) {
+static int enqueue_init(Scratch& S, const Plan& P, const Inst* insts, hipStream_t s) {
     const Run& R = P.R;
     HIPC(launch_fill_u32((uint32_t*)R.dirty[0], 0, R.nchunks * 4, s));
     HIPC(launch_fill_u32((uint32_t*)R.dirty[1], 0, R.nchunks * 4, s));
@@ -545,7 +546,7 @@ static int enqueue_init(Scratch& S, const Plan& P, const std::vector<Inst>& inst
     HIPC(launch_fill_u32((uint32_t*)R.error, 0, 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.result, 0, 16, s));
     if (P.bucket) HIPC(launch_fill_u32((uint32_t*)R.occ, 0, 65536 / 4, s));
-    for (const Inst& I : insts) HIPC(launch_init(S.dinst, I, P.dtype, s));
+    for (int i = 0; i < P.ninst; ++i) HIPC(launch_init(S.dinst, insts[i], P.dtype, s));
     HIPC(launch_seed(S.dinst, P.ninst, R, P.max_states, P.dtype, P.enc_mask, s));
     return GBF_OK;
 }
@@ -574,7 +575,6 @@ static void read_host(const Scratch& S, const Plan& P, SolveOut& out, bool round
         out.barrier_ms = (double)ticks / (double)clock_khz;
     }
     std::memcpy(out.ctr, host + 16, 6 * sizeof(unsigned long long));
-    out.inst_status.assign(P.ninst, 0);
     for (int i = 0; i < P.ninst; ++i) out.inst_status[i] = host[64 + i];
     out.sweeps = P.bucket ? host[8] : 0;
     out.mode = P.mode;
@@ -635,13 +635,13 @@ static int enqueue_hostloop(Scratch& S, const Plan& P, const gbf_opts& o, hipStr
 }
 
 // Runs one solve over `insts`, not captured.
-static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, const gbf_opts& o, hipStream_t s,
+static int run_rounds(Scratch& S, const Inst* insts, int ninst, int dtype, const gbf_opts& o, hipStream_t s,
                       int cus, int clock_khz, SolveOut& out) {
     Plan P;
-    int rc = plan_solve(S, insts, dtype, o, cus, clock_khz, P);
+    int rc = plan_solve(S, insts, ninst, dtype, o, cus, clock_khz, P);
     if (rc) return rc;
-    HIPC(hipEventRecord(S.events[0], s));
-    HIPC(hipMemcpyAsync(S.dinst, insts.data(), sizeof(Inst) * P.ninst, hipMemcpyHostToDevice, s));
+    if (!S.events.empty()) HIPC(hipEventRecord(S.events[0], s));
+    HIPC(hipMemcpyAsync(S.dinst, insts, sizeof(Inst) * P.ninst, hipMemcpyHostToDevice, s));
     if ((rc = enqueue_init(S, P, insts, s))) return rc;
     if (P.mode == GBF_MODE_SINGLE_BLOCK) {
         if (o.profile) HIPC(hipEventRecord(S.events[2], s));
@@ -670,7 +670,7 @@ static int run_rounds(Scratch& S, const std::vector<Inst>& insts, int dtype, con
                 gbf_opts o2 = o;
                 o2.mode = GBF_MODE_HOSTLOOP;
                 out = SolveOut();
-                return run_rounds(S, insts, dtype, o2, s, cus, clock_khz, out);
+                return run_rounds(S, insts, ninst, dtype, o2, s, cus, clock_khz, out);
             }
             return fail(GBF_ETIMEOUT, "grid barrier timed out (blocks not co-resident?)");
         }
@@ -755,9 +755,9 @@ extern "C" int gbf_solve(gbf_graph* g, const gbf_opts* opts, void* V_out, gbf_st
         I.occ = g->scratch.occ;
         I.max_rounds += 65536;
     }
-    std::vector<Inst> insts{I};
+    const Inst insts[1] = {I};
     SolveOut so;
-    int rc = run_rounds(g->scratch, insts, g->dtype, o, s, g->cus, g->clock_khz, so);
+    int rc = run_rounds(g->scratch, insts, 1, g->dtype, o, s, g->cus, g->clock_khz, so);
     if (rc) return rc;
     int fallback = 0;
     if (bucket && so.inst_status[0]) {
@@ -827,8 +827,25 @@ struct BatchCtx {
 // Batch contexts by the ordered set of handles.  One lock guards the map;
 // a batch call holds it for its whole duration (a context's scratch and
 // graph are not shared between concurrent calls).
-static std::map<std::vector<gbf_graph*>, std::unique_ptr<BatchCtx>> g_batches;
+// The map is created on first use and never destroyed by a static
+// destructor: destructors of library-scope objects run at process exit,
+// possibly after the HIP runtime (or a profiler attached to it) has shut
+// down, and a HIP call from there faults.  gbf_shutdown releases the
+// contexts explicitly while the runtime is still up.
+using BatchMap = std::map<std::vector<gbf_graph*>, std::unique_ptr<BatchCtx>>;
+static BatchMap& g_batches_map() {
+    static BatchMap* m = new BatchMap();
+    return *m;
+}
+#define g_batches (g_batches_map())
 static std::mutex g_batches_lock;
+
+extern "C" void gbf_shutdown(void) {
+    std::lock_guard<std::mutex> lk(g_batches_lock);
+    for (auto& kv : g_batches)
+        if (kv.second->priv) (void)hipStreamSynchronize(kv.second->priv);
+    g_batches.clear();
+}
 
 static void forget_batches_of(gbf_graph* g) {
     std::lock_guard<std::mutex> lk(g_batches_lock);
@@ -847,7 +864,7 @@ static bool same_opts(const gbf_opts& a, const gbf_opts& b) {
            a.v_memspace == b.v_memspace;
 }
 
-static int capture_batch(BatchCtx& ctx, const Plan& P, const std::vector<Inst>& insts, void* const* V_outs,
+static int capture_batch(BatchCtx& ctx, const Plan& P, const Inst* insts, void* const* V_outs,
                          hipStream_t s) {
     Scratch& S = ctx.scratch;
     hipGraph_t graph = nullptr;
@@ -857,7 +874,7 @@ static int capture_batch(BatchCtx& ctx, const Plan& P, const std::vector<Inst>& 
     if (!rc) e = launch_persistent(S.dinst, P.R, P.grid, P.lanes, P.dtype, P.enc_mask, true, s);
     if (!rc && e == hipSuccess) rc = enqueue_readback(S, P, s);
     if (!rc && e == hipSuccess)
-        for (size_t i = 0; i < insts.size(); ++i)
+        for (int i = 0; i < P.ninst; ++i)
             if (V_outs && V_outs[i]) {
                 e = launch_decode(insts[i], P.dtype, V_outs[i], s);
                 if (e != hipSuccess) break;
@@ -915,7 +932,7 @@ extern "C" int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gb
     Scratch& S = ctx->scratch;
     SolveOut so;
     Plan P;
-    int rc = plan_solve(S, insts, dtype, o, graphs[0]->cus, graphs[0]->clock_khz, P);
+    int rc = plan_solve(S, insts.data(), count, dtype, o, graphs[0]->cus, graphs[0]->clock_khz, P);
     if (rc) return rc;
     const bool graphable = P.mode == GBF_MODE_PERSISTENT && o.v_memspace == GBF_DEVICE && !o.profile;
     bool replayed = false;
@@ -936,7 +953,7 @@ extern "C" int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gb
         if (fresh) {
             HIPC(hipMemcpyAsync(S.dinst, insts.data(), sizeof(Inst) * count, hipMemcpyHostToDevice, gs));
             HIPC(hipStreamSynchronize(gs));
-            if (capture_batch(*ctx, P, insts, V_outs, gs) != GBF_OK) {
+            if (capture_batch(*ctx, P, insts.data(), V_outs, gs) != GBF_OK) {
                 ctx->graph_failed = true;  // fall back to direct launches
                 (void)hipGetLastError();
             } else {
@@ -961,7 +978,7 @@ extern "C" int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gb
     if (!replayed) {
         gbf_opts o2 = o;
         if (graphable && o.mode == GBF_MODE_AUTO && ((int32_t*)S.host)[1] != 0) o2.mode = GBF_MODE_HOSTLOOP;
-        rc = run_rounds(S, insts, dtype, o2, s, graphs[0]->cus, graphs[0]->clock_khz, so);
+        rc = run_rounds(S, insts.data(), count, dtype, o2, s, graphs[0]->cus, graphs[0]->clock_khz, so);
         if (rc) return rc;
         for (int i = 0; i < count; ++i) {
             if (!V_outs || !V_outs[i]) continue;
