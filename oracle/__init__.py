@@ -57,29 +57,69 @@ def build() -> str:
     return LIB_PATH
 
 
+def _bind(L):
+    """Declares the argument types of the oracle's entry points on L."""
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    for nm in ("oracle_solve_i32", "oracle_solve_f64", "oracle_solve_f32"):
+        f = getattr(L, nm)
+        f.argtypes = [i64, i64, P, P, P, P, P, P, i64, P, P, ctypes.POINTER(Counters), P, P]
+        f.restype = ctypes.c_int
+    for nm in ("oracle_policy_i32", "oracle_policy_f64", "oracle_policy_f32"):
+        f = getattr(L, nm)
+        f.argtypes = [i64, i64, P, P, P, P, P, P, P, P]
+        f.restype = i64
+    L.oracle_box_to_csr.argtypes = [P, i64, P, P, P]
+    L.oracle_box_to_csr.restype = i64
+    L.oracle_dijkstra_i32.argtypes = [i64, i64, P, P, P, P, P, P, P]
+    L.oracle_dijkstra_i32.restype = ctypes.c_int
+    return L
+
+
 def lib():
     global _lib
     with _lock:
         if _lib is None:
             if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC):
                 build()
-            L = ctypes.CDLL(LIB_PATH)
-            P = ctypes.c_void_p
-            i64 = ctypes.c_int64
-            for nm in ("oracle_solve_i32", "oracle_solve_f64", "oracle_solve_f32"):
-                f = getattr(L, nm)
-                f.argtypes = [i64, i64, P, P, P, P, P, P, i64, P, P, ctypes.POINTER(Counters), P, P]
-                f.restype = ctypes.c_int
-            for nm in ("oracle_policy_i32", "oracle_policy_f64", "oracle_policy_f32"):
-                f = getattr(L, nm)
-                f.argtypes = [i64, i64, P, P, P, P, P, P, P, P]
-                f.restype = i64
-            L.oracle_box_to_csr.argtypes = [P, i64, P, P, P]
-            L.oracle_box_to_csr.restype = i64
-            L.oracle_dijkstra_i32.argtypes = [i64, i64, P, P, P, P, P, P, P]
-            L.oracle_dijkstra_i32.restype = ctypes.c_int
-            _lib = L
+            _lib = _bind(ctypes.CDLL(LIB_PATH))
     return _lib
+
+
+def build_variant(src_text: str, path: str) -> str:
+    """Compiles a modified copy of the oracle's source (tests that plant a
+    mistake in the oracle use this to show that a pin catches it)."""
+    src = path + ".c"
+    with open(src, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                           "-shared", "-o", path, src, "-lm"])
+    return path
+
+
+class use_variant:
+    """Context manager: the oracle's functions run on the library at `path`
+    (built by build_variant) inside the block."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        lib()
+        self._saved = _lib
+        _lib = _bind(ctypes.CDLL(self.path))
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self._saved
+        return False
+
+
+def source() -> str:
+    with open(_SRC) as f:
+        return f.read()
 
 
 def _p(a):
