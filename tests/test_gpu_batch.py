@@ -113,26 +113,78 @@ def test_batch_with_capped_instance():
 
 @pytest.fixture(scope="module")
 def batch64():
-    return synth.batch_mix(64, with_csr=False)
+    """The 64-instance mix and the oracle's solution of every instance (the
+    oracle's C calls release the interpreter lock, so threads run them in
+    parallel)."""
+    from concurrent.futures import ThreadPoolExecutor
+    probs = synth.batch_mix(64, with_csr=False)
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        refs = list(ex.map(oracle.solve, probs))
+    return probs, refs
 
 
-def test_batch64_vs_single_solves(batch64):
+def _check64(probs, refs, graphs, outs, label):
+    for i, (p, ref, gr, V) in enumerate(zip(probs, refs, graphs, outs)):
+        Vh = V.cpu().numpy()
+        bad = np.nonzero(Vh != ref["V"])[0]
+        assert bad.size == 0, (label, i, p.name, bad[:8], Vh[bad[:8]], ref["V"][bad[:8]])
+        pol, res = gr.policy()
+        assert res == 0 and np.array_equal(pol, ref["policy"]), (label, i, p.name)
+
+
+def test_batch64_vs_oracle(batch64):
     """The 64-instance mix (2-D 128x128, 3-D 48x48x24, 4-D up to
-    40x40x24x10): the batched solve equals 64 single solves, and a sample is
-    checked against the oracle."""
+    40x40x24x10) with the library defaults: every instance bit-exact with
+    the oracle (values and canonical policy), and equal to its single
+    solve."""
     import torch
-    _case("batch64")
-    graphs = [gbf.load_problem(p, encoding="csr") for p in batch64]
-    outs = [torch.empty(p.n, dtype=torch.int32, device="cuda") for p in batch64]
+    probs, refs = batch64
+    _case("batch64 defaults vs oracle")
+    graphs = [gbf.load_problem(p, encoding="csr") for p in probs]
+    outs = [torch.empty(p.n, dtype=torch.int32, device="cuda") for p in probs]
     status, stats, _ = gbf.solve_batch(graphs, outs)
     assert status == gbf.OK
-    for p, gr, V in zip(batch64, graphs, outs):
-        st, s, Vs = gr.solve()
+    _check64(probs, refs, graphs, outs, "defaults")
+    for i in range(0, 64, 7):
+        st, s, Vs = graphs[i].solve()
         assert st == gbf.OK
-        assert np.array_equal(V.cpu().numpy(), Vs), p.name
-    for i in (0, 16, 32):
-        ref = oracle.solve(batch64[i])
-        assert np.array_equal(outs[i].cpu().numpy(), ref["V"]), batch64[i].name
+        assert np.array_equal(Vs, refs[i]["V"]), probs[i].name
+    for gr in graphs:
+        gr.free()
+
+
+def test_batch64_tuned_configuration_vs_oracle(batch64):
+    """The configuration the autotuner picks for this mix on MI355X (box
+    successors with a reverse CSR, host loop, 2 lanes per pair, 2048
+    blocks): every instance bit-exact with the oracle."""
+    import torch
+    probs, refs = batch64
+    _case("batch64 box+rev hostloop lanes=2 grid=2048 vs oracle")
+    graphs = [gbf.load_problem(p, encoding="box+rev") for p in probs]
+    outs = [torch.empty(p.n, dtype=torch.int32, device="cuda") for p in probs]
+    status, stats, _ = gbf.solve_batch(graphs, outs, mode="hostloop", lanes=2, grid=2048)
+    assert status == gbf.OK
+    _check64(probs, refs, graphs, outs, "tuned")
+    for gr in graphs:
+        gr.free()
+
+
+@pytest.mark.parametrize("encoding", ["csr", "box+rev"])
+def test_batch64_graph_replays_vs_oracle(batch64, encoding):
+    """The persistent form captured in a HIP graph and replayed: every
+    replay bit-exact with the oracle on all 64 instances."""
+    import torch
+    probs, refs = batch64
+    _case(f"batch64 persistent graph replays {encoding}")
+    graphs = [gbf.load_problem(p, encoding=encoding) for p in probs]
+    outs = [torch.empty(p.n, dtype=torch.int32, device="cuda") for p in probs]
+    for rep in range(3):
+        for V in outs:
+            V.fill_(-7)
+        status, stats, _ = gbf.solve_batch(graphs, outs, mode="persistent")
+        assert status == gbf.OK
+        assert stats[0]["graph_used"] == 1
+        _check64(probs, refs, graphs, outs, f"graph-{encoding}-{rep}")
     for gr in graphs:
         gr.free()
 
