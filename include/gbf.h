@@ -218,6 +218,27 @@ int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph** out);
  * GBF_EINVAL (BUCKETS without a key), GBF_ETIMEOUT, GBF_EHIP. */
 int gbf_solve(gbf_graph* g, const gbf_opts* opts, void* V_out, gbf_stats* st);
 
+/* Allocation-free form of gbf_solve, for callers that cannot allocate
+ * device memory at solve time (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same semantics and results as
+ * gbf_solve with the plain order; it calls no hipMalloc, hipFree,
+ * hipHostMalloc or hipEventCreate.  All solver scratch (frontier byte
+ * maps, frontier list, per-round counts, statistics, barrier and status
+ * words) lives in one static device array of the library, ~57 MiB, which
+ * every device the library runs on holds until the process ends.  Limits:
+ * n_states * n_inputs <= GBF_NOALLOC_MAX_PAIRS and a round cap (max_rounds,
+ * or n_states when it is 0) <= GBF_NOALLOC_MAX_ROUNDS; larger problems get
+ * GBF_EINVAL before any device work.  GBF_ORDER_BUCKETS gets GBF_EINVAL;
+ * opts->profile is ignored (no per-launch timing) and st->solve_ms is
+ * host wall time.  V_out as for gbf_solve (host or device, per
+ * opts->v_memspace).  Every call on one device shares that device's array
+ * and overwrites it (each solve clears what must start at zero), so calls
+ * that overlap in time on one device race: serialise them.  gbf_extract_policy
+ * works after it as after gbf_solve. */
+#define GBF_NOALLOC_MAX_PAIRS (1 << 23)
+#define GBF_NOALLOC_MAX_ROUNDS (1 << 21)
+int gbf_solve_noalloc(gbf_graph* g, const gbf_opts* opts, void* V_out, gbf_stats* st);
+
 /* Canonical controller from the last solve (Algorithm 1's mu, made
  * independent of processing order): policy[x] = the smallest input u with
  * g(x,u) + max_{y in F(x,u)} V(y) = V(x) < G(x); GBF_HANDOVER if

@@ -45,6 +45,7 @@ ORDER_PLAIN, ORDER_BUCKETS = 0, 1
 MODE_AUTO, MODE_HOSTLOOP, MODE_PERSISTENT, MODE_SINGLE_BLOCK = 0, 1, 2, 3
 HANDOVER, NONE = -1, -2
 INF_I32 = 2**31 - 1
+NOALLOC_MAX_PAIRS, NOALLOC_MAX_ROUNDS = 1 << 23, 1 << 21
 
 _MODES = {"auto": MODE_AUTO, "hostloop": MODE_HOSTLOOP, "persistent": MODE_PERSISTENT,
           "single_block": MODE_SINGLE_BLOCK}
@@ -89,7 +90,7 @@ class _Stats(ctypes.Structure):
 
 
 EXPORTS = ("gbf_load_graph", "gbf_solve", "gbf_extract_policy", "gbf_solve_batch", "gbf_tune", "gbf_free_graph",
-           "gbf_last_error", "gbf_shutdown", "gbf_mlp_create", "gbf_mlp_set_params", "gbf_mlp_get_params", "gbf_mlp_samples",
+           "gbf_last_error", "gbf_shutdown", "gbf_solve_noalloc", "gbf_mlp_create", "gbf_mlp_set_params", "gbf_mlp_get_params", "gbf_mlp_samples",
            "gbf_mlp_forward", "gbf_mlp_grad", "gbf_mlp_train_step", "gbf_mlp_bucket_keys", "gbf_mlp_free")
 MLP_NPARAMS = 4545
 
@@ -131,6 +132,8 @@ def lib():
             L.gbf_load_graph.restype = ctypes.c_int
             L.gbf_solve.argtypes = [P, ctypes.POINTER(_Opts), P, ctypes.POINTER(_Stats)]
             L.gbf_solve.restype = ctypes.c_int
+            L.gbf_solve_noalloc.argtypes = [P, ctypes.POINTER(_Opts), P, ctypes.POINTER(_Stats)]
+            L.gbf_solve_noalloc.restype = ctypes.c_int
             L.gbf_extract_policy.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
             L.gbf_extract_policy.restype = ctypes.c_int
             L.gbf_solve_batch.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(_Opts),
@@ -247,6 +250,21 @@ class Graph:
         o = self._opts(order, mode, max_rounds, grid, profile, bucket_key, vs, lanes, bucket_span)
         st = _Stats()
         rc = L.gbf_solve(self._h, ctypes.byref(o), vp, ctypes.byref(st))
+        if rc < 0 or (check and rc not in (OK, ENEGCYCLE)):
+            raise _err(L, rc)
+        return rc, st.as_dict(), V_out
+
+    def solve_noalloc(self, V_out=None, *, mode="auto", max_rounds=0, grid=0, lanes=0, check=True):
+        """gbf_solve_noalloc: the plain-order solve with all scratch in the
+        library's static device array (no allocation in the call).  Returns
+        (status, stats dict, V_out) as solve()."""
+        L = lib()
+        if V_out is None:
+            V_out = np.empty(self.n, dtype=np.int32 if self.dtype == I32 else np.float32)
+        vp, vs = _ptr(V_out)
+        o = self._opts("plain", mode, max_rounds, grid, False, None, vs, lanes, 0)
+        st = _Stats()
+        rc = L.gbf_solve_noalloc(self._h, ctypes.byref(o), vp, ctypes.byref(st))
         if rc < 0 or (check and rc not in (OK, ENEGCYCLE)):
             raise _err(L, rc)
         return rc, st.as_dict(), V_out

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -96,7 +97,12 @@ struct Scratch {
     size_t host_bytes = 0;
     std::vector<hipEvent_t> events;
     DevMem mem;
+    // A view of the library's static device scratch (gbf_solve_noalloc): its
+    // buffers are carved from that array, nothing is allocated or released,
+    // and no events exist.
+    bool fixed = false;
     ~Scratch() {
+        if (fixed) return;
         if (host) (void)hipHostFree(host);
         for (auto e : events) (void)hipEventDestroy(e);
     }
@@ -127,6 +133,11 @@ struct gbf_graph {
 };
 
 static int ensure_scratch(Scratch& S, int64_t total_pairs, int64_t max_rounds, int ninst, int nevents) {
+    if (S.fixed) {
+        if (total_pairs > S.total_pairs || max_rounds + 2 > S.counts_cap || ninst > S.ninst_cap)
+            return fail(GBF_EINVAL, "problem exceeds the static scratch of the no-allocation solve");
+        return GBF_OK;
+    }
     const int64_t nchunks = (total_pairs + 15) / 16;
     if (S.total_pairs < total_pairs) {
         if (S.dirty[0]) S.mem.release(S.dirty[0], 0), S.mem.release(S.dirty[1], 0), S.mem.release(S.list, 0);
@@ -781,6 +792,124 @@ extern "C" int gbf_solve(gbf_graph* g, const gbf_opts* opts, void* V_out, gbf_st
     const int status = so.inst_status[0] ? GBF_ENEGCYCLE : GBF_OK;
     fill_stats(st, status, so, I.max_rounds, g->mem.bytes + g->scratch.mem.bytes, g->enc);
     if (st) st->fallback = fallback;
+    g->solved = true;
+    if (status != GBF_OK) fail(status, "round cap reached with a non-empty frontier");
+    return status;
+}
+
+// ------------------------------------------------------------------ no-allocation solve
+// One static device array holds every scratch buffer of a solve (frontier
+// byte maps, list, per-round counts, statistics, barrier and status words,
+// the instance table).  Each device the library runs on holds its own copy
+// for the life of the process.  Host code never passes the array's name to
+// a kernel (in host code it names a host-side stand-in): the device address
+// of each device's copy is taken once with hipGetSymbolAddress and kept.
+constexpr int64_t kNaPairs = GBF_NOALLOC_MAX_PAIRS;
+constexpr int64_t kNaRounds = (int64_t)GBF_NOALLOC_MAX_ROUNDS + 2;  // round-count slots (round cap + 2)
+constexpr int kNaMaxDevices = 64;
+constexpr size_t kNaAlign = 256;
+constexpr size_t na_up(size_t v) { return (v + kNaAlign - 1) / kNaAlign * kNaAlign; }
+constexpr size_t kNaOffDirty0 = 0;
+constexpr size_t kNaOffDirty1 = kNaOffDirty0 + na_up((size_t)kNaPairs);
+constexpr size_t kNaOffList = kNaOffDirty1 + na_up((size_t)kNaPairs);
+constexpr size_t kNaOffCounts = kNaOffList + na_up((size_t)kNaPairs * 4);
+constexpr size_t kNaOffCtr = kNaOffCounts + na_up((size_t)kNaRounds * 4);
+constexpr size_t kNaOffSlots = kNaOffCtr + na_up(8 * sizeof(unsigned long long));
+constexpr size_t kNaOffBarrier = kNaOffSlots + na_up((size_t)kMaxGrid * 8 * sizeof(unsigned long long));
+constexpr size_t kNaOffError = kNaOffBarrier + na_up(4096);
+constexpr size_t kNaOffResult = kNaOffError + na_up(64);
+constexpr size_t kNaOffOcc = kNaOffResult + na_up(64);
+constexpr size_t kNaOffThr = kNaOffOcc + na_up(65536);
+constexpr size_t kNaOffInst = kNaOffThr + na_up(64);
+constexpr size_t kNaOffStatus = kNaOffInst + na_up(sizeof(Inst));
+constexpr size_t kNaBytes = kNaOffStatus + na_up(64);
+
+static __device__ __align__(256) uint8_t scratch[kNaBytes];
+
+static std::mutex g_na_lock;
+static void* g_na_ptr[kNaMaxDevices];
+// host readback words (pageable: the copies into it complete before use)
+static int32_t g_na_host[kNaMaxDevices][2048];
+
+// Device address of `scratch` on `device` (looked up once per device, with
+// that device current).
+static int na_scratch(int device, void** out) {
+    if (device < 0 || device >= kNaMaxDevices) return fail(GBF_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_na_lock);
+    if (!g_na_ptr[device]) {
+        int cur = -1;
+        HIPC(hipGetDevice(&cur));
+        if (cur != device) HIPC(hipSetDevice(device));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr)
+            return fail(GBF_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_na_ptr[device] = ptr;
+    }
+    *out = g_na_ptr[device];
+    return GBF_OK;
+}
+
+extern "C" int gbf_solve_noalloc(gbf_graph* g, const gbf_opts* opts, void* V_out, gbf_stats* st) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!g) return fail(GBF_EINVAL, "graph is NULL");
+    gbf_opts o = opts ? *opts : default_opts();
+    if (o.order != GBF_ORDER_PLAIN) return fail(GBF_EINVAL, "the no-allocation solve uses the plain order");
+    if (o.v_memspace != GBF_HOST && o.v_memspace != GBF_DEVICE) return fail(GBF_EINVAL, "bad v_memspace");
+    o.profile = 0;  // per-launch timing needs events, which are allocated
+    const int64_t npairs = g->n * g->K;
+    const int64_t max_rounds = o.max_rounds > 0 ? o.max_rounds : g->n;
+    if (npairs > kNaPairs)
+        return fail(GBF_EINVAL, "the no-allocation solve takes at most " + std::to_string(kNaPairs) + " pairs");
+    if (max_rounds > kNaRounds - 2)
+        return fail(GBF_EINVAL, "the no-allocation solve takes a round cap of at most " +
+                                    std::to_string(kNaRounds - 2) + " (pass a smaller max_rounds)");
+    void* base = nullptr;
+    int rc = na_scratch(g->device, &base);
+    if (rc) return rc;
+    uint8_t* b = static_cast<uint8_t*>(base);
+    hipStream_t s = g->stream;
+    Scratch S;
+    S.fixed = true;
+    S.total_pairs = kNaPairs;
+    S.counts_cap = kNaRounds;
+    S.ninst_cap = 1;
+    S.dirty[0] = b + kNaOffDirty0;
+    S.dirty[1] = b + kNaOffDirty1;
+    S.list = reinterpret_cast<uint32_t*>(b + kNaOffList);
+    S.counts = reinterpret_cast<uint32_t*>(b + kNaOffCounts);
+    S.ctr = reinterpret_cast<unsigned long long*>(b + kNaOffCtr);
+    S.slots = reinterpret_cast<unsigned long long*>(b + kNaOffSlots);
+    S.barrier = reinterpret_cast<uint32_t*>(b + kNaOffBarrier);
+    S.error = reinterpret_cast<int32_t*>(b + kNaOffError);
+    S.result = reinterpret_cast<int32_t*>(b + kNaOffResult);
+    S.occ = b + kNaOffOcc;
+    S.thr = reinterpret_cast<uint32_t*>(b + kNaOffThr);
+    S.dinst = reinterpret_cast<Inst*>(b + kNaOffInst);
+    S.inst_status = reinterpret_cast<int32_t*>(b + kNaOffStatus);
+    S.host = g_na_host[g->device];
+    S.host_bytes = sizeof(g_na_host[0]);
+    g->solved = false;
+    Inst I = g->inst;
+    I.pair_base = 0;
+    I.max_rounds = max_rounds;
+    const Inst insts[1] = {I};
+    SolveOut so;
+    rc = run_rounds(S, insts, 1, g->dtype, o, s, g->cus, g->clock_khz, so);
+    if (rc) return rc;
+    if (V_out) {
+        if (o.v_memspace == GBF_DEVICE) {
+            HIPC(launch_decode(g->inst, g->dtype, V_out, s));
+        } else {
+            HIPC(launch_decode(g->inst, g->dtype, S.list, s));
+            HIPC(hipMemcpyAsync(V_out, S.list, g->n * 4, hipMemcpyDeviceToHost, s));
+        }
+    }
+    HIPC(hipStreamSynchronize(s));
+    so.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    const int status = so.inst_status[0] ? GBF_ENEGCYCLE : GBF_OK;
+    fill_stats(st, status, so, I.max_rounds, g->mem.bytes, g->enc);
     g->solved = true;
     if (status != GBF_OK) fail(status, "round cap reached with a non-empty frontier");
     return status;
