@@ -3,19 +3,32 @@
 One step = one full pass of the hot path on device-resident inputs: solve
 (initialise W <- G, seed the frontier, every frontier round until it drains:
 compact, relax, expand) plus extraction of the canonical controller with its
-fixed-point residual.  Workload: the 4-D UAV-style grid 40x40x24x10
+fixed-point residual.  Main workload: the 4-D UAV-style grid 40x40x24x10
 (384,000 cells), 12 inputs, int32 potential-form costs, explicit successor
 lists (CSR).
 
 Prints ONE JSON line.  `value` = edge relaxations (sum of |F(x,u)| over the
-pairs the GPU evaluated) per second of step time.  `roofline` is for the
-dominant kernel (the relax kernel in host-loop mode, the round kernel in
-persistent mode): its algorithmic bytes per launch divided by its average
-launch duration, both measured inside the timed steps with HIP events on the
-solver's stream.  `traffic` is the measured HBM bytes per launch of that
-kernel from the committed rocprofv3 counter summary, if the kernel source is
-unchanged since it was taken.  `cpu_baseline` is the single-threaded CPU
-oracle on the same instance.
+pairs the GPU evaluated) per second of step time.  Every workload (the main
+line, each entry of `configs`, `batch64`, `learned`) carries:
+  - `roofline` of its dominant kernel (the relax kernel in host-loop mode,
+    the round kernel in persistent or single-workgroup mode): algorithmic
+    bytes per launch (the counters of the solves times the per-unit bytes
+    below) over the kernel's average launch duration, measured with HIP
+    events on the solver's stream around every launch;
+  - `cpu_baseline`: the single-threaded CPU oracle, pinned to one host core
+    (its own worker process), on the same workload or a stated sample.
+Algorithmic bytes per unit (what the method must move, not cache behaviour):
+  relax: 20 B per evaluated pair (list id 4, row bounds 8, cost 4, W(x) 4)
+         + per successor 8 B (CSR: index 4 + W(y) 4), 4 B (box successors:
+         W(y)), 12 B (CSR with per-edge costs: index, h, W(y));
+  expand: 8 B per improved state (reverse-row bounds) + 8 B per predecessor
+         pair or box candidate visited (reverse entry 4 + frontier word 4);
+  compact (inside the persistent and single-workgroup kernels only): the
+         frontier read and cleared once per round, nK/4 B, + 4 B per listed
+         pair.
+`traffic` is the measured HBM bytes per launch of the main line's kernel
+from the committed rocprofv3 counter summary, if the kernel source is
+unchanged since it was taken.
 """
 import argparse
 import hashlib
@@ -32,6 +45,8 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "edge relaxations/sec + solve time, 4D 384k-cell graph; learned/batched vs plain"
 KERNEL_SRC = os.path.join(ROOT, "paper_2001_06231_amd", "csrc", "gbf_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "relax_traffic_grid4d_384k.txt")
+PER_EDGE_BYTES = {"csr": 8, "box->csr": 8, "box": 4, "box+rev": 4, "box:budget": 4, "csr_edge": 12}
+KERNEL_OF_MODE = {"persistent": "k_persistent", "single_block": "k_single", "hostloop": "k_relax"}
 
 
 def kernel_source_hash():
@@ -39,18 +54,35 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def algorithmic_bytes(st, npairs, mode, rounds):
-    """Bytes the method must move per solve (not cache behaviour):
-    relax (CSR): 20 B per evaluated pair (list id 4, row bounds 8, cost 4,
-    W(x) 4) + 8 B per edge (successor index 4, W(y) 4);
-    expand: 8 B per expanded state (reverse-row bounds) + 5 B per marked
-    predecessor pair (reverse entry 4, dirty byte 1);
-    compact (part of the persistent and single-block kernels only): the dirty byte map
-    is read once per round (npairs B) + 4 B per listed pair."""
-    b = 20 * st["pair_evals"] + 8 * st["edge_relax"] + 8 * st["expansions"] + 5 * st["marks"]
+def algorithmic_bytes(st, npairs, per_edge, mode):
+    """Bytes the method must move in one solve, from its counters (see the
+    module docstring)."""
+    b = 20 * st["pair_evals"] + per_edge * st["edge_relax"] + 8 * st["expansions"] + 8 * st["marks"]
     if mode in ("persistent", "single_block"):
-        b += (rounds + 1) * npairs + 4 * st["pair_evals"]
+        b += (st["rounds"] + 1) * npairs / 4 + 4 * st["pair_evals"]
     return b
+
+
+def mode_name(st):
+    import paper_2001_06231_amd as gbf
+    return {gbf.MODE_PERSISTENT: "persistent", gbf.MODE_SINGLE_BLOCK: "single_block"}.get(st["mode_used"],
+                                                                                         "hostloop")
+
+
+def roofline(stats, npairs, per_edge, small_lds=False):
+    """Roofline object of the dominant kernel over solves run with
+    profile=True (HIP events around every launch of that kernel)."""
+    mode = mode_name(stats[0])
+    kernel = KERNEL_OF_MODE[mode]
+    if mode == "single_block" and small_lds:
+        kernel = "k_small"  # the single-workgroup solver with V and the frontiers in LDS
+    launches = sum(s["relax_launches"] for s in stats)
+    kern_ms = sum(s["relax_ms"] for s in stats) / max(1, launches)
+    nbytes = sum(algorithmic_bytes(s, npairs, per_edge, mode) for s in stats) / max(1, launches)
+    achieved = nbytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
+    return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel_avg_ms": kern_ms,
+            "launches_per_solve": launches / len(stats), "algorithmic_bytes_per_launch": nbytes}
 
 
 def read_traffic(kernel):
@@ -71,25 +103,27 @@ def read_traffic(kernel):
         return None
 
 
-def _gen_learned(index):
-    import synth
-    return synth.learned_instance(index, with_csr=False)
-
-
-def _gen_batch(i):
-    import synth
-    return synth.batch_instance(i, 64, with_csr=False)
-
-
-def _gen_small(kind):
+# ---------------------------------------------------------------- inputs
+def make_problem(kind):
+    """The synthetic inputs of every workload, by name."""
     import synth
     if kind == "grid2d":
         return synth.grid2d_small()
-    return synth.grid4d(dtype="f32")
+    if kind == "grid4d_i32":
+        return synth.grid4d()
+    if kind == "grid4d_f32":
+        return synth.grid4d(dtype="f32")
+    if kind == "grid4d_i32_edge":
+        return synth.with_edge_costs(synth.grid4d(), 34)
+    if kind.startswith("batch:"):
+        return synth.batch_instance(int(kind[6:]), 64, with_csr=False)
+    if kind.startswith("learned:"):
+        return synth.learned_instance(int(kind[8:]), with_csr=False)
+    raise ValueError(kind)
 
 
 class _Done:
-    """A finished job (generation without worker processes)."""
+    """A finished job (when no worker processes are used)."""
 
     def __init__(self, value):
         self.value = value
@@ -101,20 +135,123 @@ class _Done:
         return self.value
 
 
-def _median_solve(graph, reps, **kw):
-    """Median-time solve over `reps` runs (after one warm-up): stats dict."""
+def host_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cores": len(os.sched_getaffinity(0))}
+
+
+# ---------------------------------------------------------------- CPU oracle
+def cpu_job(spec):
+    """Runs in a worker process pinned to one host core: times the oracle's
+    whole solve call (its own predecessor lists, Algorithm 1 and the policy
+    pass); generating the input is outside the clock."""
+    label, kinds, reps, precision, core = spec
+    if core is not None:
+        os.sched_setaffinity(0, {core})
     import numpy as np
-    graph.solve(**kw)
-    runs = [graph.solve(**kw)[1] for _ in range(reps)]
+
+    import oracle
+    oracle.lib()
+    probs = [make_problem(k) for k in kinds]
+    times, edges, pairs = [], [], []
+    for _ in range(reps):
+        t_sum, e_sum, p_sum = 0.0, 0, 0
+        for p in probs:
+            t0 = time.perf_counter()
+            r = oracle.solve(p, precision=precision)
+            t_sum += time.perf_counter() - t0
+            e_sum += r["counters"]["edge_relax"]
+            p_sum += r["counters"]["pair_evals"]
+        times.append(t_sum)
+        edges.append(e_sum)
+        pairs.append(p_sum)
+    t = float(np.median(times))
+    e = float(np.median(edges))
+    return label, {"value": e / t, "unit": "edge_relaxations/s", "cores": 1, "kind": "oracle",
+                   "solve_s": t, "edge_relax": e, "pair_evals": float(np.median(pairs)),
+                   "pinned_core": core, "reps": reps}
+
+
+CPU_SAMPLES = {
+    # label: (problem kinds, repetitions, precision, description)
+    "main": (["grid4d_i32"], 3, None, "the full 4-D 40x40x24x10 int32 instance, median of 3 solves"),
+    "grid2d_64x64_i32_csr": (["grid2d"], 5, None, "the full 2-D 64x64 instance, median of 5 solves"),
+    "grid4d_384k_f32": (["grid4d_f32"], 1, "f32", "the full 4-D 40x40x24x10 fp32 instance, one solve with the "
+                                                  "single-precision operator (encoding-independent)"),
+    "grid4d_384k_i32_csr_edge_costs": (["grid4d_i32_edge"], 1, None,
+                                       "the full 4-D 40x40x24x10 int32 instance with per-edge costs, one solve"),
+    "batch64": ([f"batch:{i}" for i in range(0, 64, 4)], 1, None,
+                "16 of the 64 batch instances (every 4th: 4 2-D, 4 3-D, 8 4-D), one solve each; the rate is "
+                "their summed relaxations over their summed solve time"),
+    "learned": (["learned:1000"], 1, None, "held-out instance 1000 (60x60x30x12, K=16), one solve"),
+}
+
+
+def start_cpu_jobs(pool, labels):
+    cores = sorted(os.sched_getaffinity(0))
+    # leave the lowest core to the process that drives the GPU
+    usable = cores[1:] if len(cores) > len(labels) else cores
+    specs = []
+    for i, lab in enumerate(labels):
+        kinds, reps, prec, _ = CPU_SAMPLES[lab]
+        specs.append((lab, kinds, reps, prec, usable[(len(usable) - 1 - i) % len(usable)]))
+    if pool is None:
+        return _Done([cpu_job(s) for s in specs])
+    return pool.map_async(cpu_job, specs)
+
+
+def attach_cpu(res, cpu_results, label, info):
+    if label in cpu_results:
+        c = dict(cpu_results[label])
+        c["sample"] = CPU_SAMPLES[label][3] + ("; the oracle counts its own relaxations (state frontier x all "
+                                               "inputs), so the rate is throughput, not a comparison of counts")
+        c.update(info)
+        res["cpu_baseline"] = c
+
+
+# ---------------------------------------------------------------- GPU legs
+def measure(graph, prob, encoding, reps=5, V=None, **kw):
+    """Median solve time over `reps` solves after one warm-up, edge
+    relaxations/s, and the roofline of the dominant kernel (the same solves
+    run with per-launch events)."""
+    import numpy as np
+    import torch
+    if V is None:
+        V = torch.empty(prob.n, dtype=torch.int32 if prob.dtype == "i32" else torch.float32, device="cuda")
+    graph.solve(V, **kw)
+    runs = [graph.solve(V, **kw)[1] for _ in range(reps)]
     med = float(np.median([r["solve_ms"] for r in runs]))
     best = min(runs, key=lambda r: abs(r["solve_ms"] - med))
-    return dict(best, solve_ms=med)
+    prof = [graph.solve(V, profile=True, **kw)[1] for _ in range(reps)]
+    per_edge = PER_EDGE_BYTES["csr_edge" if getattr(prob, "g_edge", None) is not None else encoding]
+    return {"solve_ms": med, "edge_relax_per_s": best["edge_relax"] / (med * 1e-3), "rounds": best["rounds"],
+            "pair_evals": best["pair_evals"], "edge_relax": best["edge_relax"],
+            "device_bytes": best["device_bytes"], "encoding": encoding, "mode": mode_name(best),
+            "roofline": roofline(prof, prob.npairs, per_edge,
+                                 small_lds=encoding in ("csr", "box+rev") and prob.npairs <= 16384 and prob.n <= 6144)}
+
+
+def config_line(prob, encoding, reps=5):
+    import paper_2001_06231_amd as gbf
+    g = gbf.load_problem(prob, encoding=encoding)
+    try:
+        return measure(g, prob, encoding, reps)
+    finally:
+        g.free()
 
 
 def learned_compare(prob, params, untrained, reps=3):
     """Plain vs network-bucketed order on one instance: solve times, MLP
-    inference time, relaxation counts, rounds; values compared bit for bit.
-    `untrained` is the control network (initial weights)."""
+    inference time, relaxation counts, rounds; values compared bit for bit
+    (GPU plain order against GPU bucket order; both are checked against the
+    oracle in the tests)."""
     import torch
 
     import paper_2001_06231_amd as gbf
@@ -122,11 +259,11 @@ def learned_compare(prob, params, untrained, reps=3):
     g = gbf.load_problem(prob, encoding="csr")
     Vp = torch.empty(prob.n, dtype=torch.int32, device="cuda")
     Vb = torch.empty_like(Vp)
-    plain = _median_solve(g, reps, V_out=Vp)
+    plain = measure(g, prob, "csr", reps, V=Vp)
+    g.solve(Vp)
     pol_p, _ = g.policy()
     tc = learn.target_centre(prob)
-    out = {"instance": prob.name, "n_states": prob.n, "pairs": prob.npairs,
-           "plain": {k: plain[k] for k in ("solve_ms", "rounds", "pair_evals", "edge_relax")}}
+    out = {"instance": prob.name, "n_states": prob.n, "pairs": prob.npairs, "plain": plain}
     for label, par in (("learned", params), ("untrained", untrained)):
         net = gbf.MLP(par)
         keys = torch.empty(prob.n, dtype=torch.int16, device="cuda")
@@ -139,25 +276,29 @@ def learned_compare(prob, params, untrained, reps=3):
             e1.record()
             e1.synchronize()
             mlp_ms.append(e0.elapsed_time(e1))
-        st = _median_solve(g, reps, V_out=Vb, order="buckets", bucket_key=keys)
+        st = measure(g, prob, "csr", reps, V=Vb, order="buckets", bucket_key=keys)
+        g.solve(Vb, order="buckets", bucket_key=keys)
         pol_b, res = g.policy()
         exact = bool(torch.equal(Vp, Vb)) and bool((pol_b == pol_p).all()) and res == 0
-        out[label] = {"solve_ms": st["solve_ms"], "mlp_ms": sorted(mlp_ms)[len(mlp_ms) // 2],
-                      "rounds": st["rounds"], "sweeps": st["sweeps"], "pair_evals": st["pair_evals"],
-                      "edge_relax": st["edge_relax"], "fallback": st["fallback"], "bit_exact": exact}
+        last = g.solve(Vb, order="buckets", bucket_key=keys)[1]
+        st.update({"mlp_ms": sorted(mlp_ms)[len(mlp_ms) // 2], "sweeps": last["sweeps"],
+                   "fallback": last["fallback"], "bit_exact_vs_plain_gpu": exact})
+        out[label] = st
         net.free()
     g.free()
     L, P = out["learned"], out["plain"]
     out["wall_speedup_incl_mlp"] = P["solve_ms"] / (L["solve_ms"] + L["mlp_ms"])
     out["relaxation_reduction"] = P["edge_relax"] / max(1, L["edge_relax"])
+    out["roofline"] = L["roofline"]
     return out
 
 
 def batch_compare(probs, reps=3):
-    """One batched solve of all instances, with the encoding and launch
-    configuration picked by the autotuner, vs one plain solve per instance
-    with the library defaults (wall time around the calls, device outputs);
-    and the persistent form replayed from its HIP graph."""
+    """One batched solve of the 64 instances in the encoding and launch
+    configuration the autotuner picks, against 64 sequential plain solves
+    (library defaults) in the same encoding and in CSR; the persistent form
+    replayed from its HIP graph; wall time around the calls (device
+    outputs)."""
     import numpy as np
     import torch
 
@@ -166,9 +307,6 @@ def batch_compare(probs, reps=3):
     t0 = time.time()
     tuned = autotune.autotune(probs, reps=2)
     tune_s = time.time() - t0
-    graphs = [gbf.load_problem(p, encoding="csr") for p in probs]
-    outs = [torch.empty(p.n, dtype=torch.int32, device="cuda") for p in probs]
-    seq = [torch.empty_like(o) for o in outs]
 
     def wall(fn):
         fn()
@@ -181,45 +319,38 @@ def batch_compare(probs, reps=3):
             ts.append(1e3 * (time.perf_counter() - t0))
         return float(np.median(ts)), r
 
-    def sequential():
-        return [gr.solve(v)[1] for gr, v in zip(graphs, seq)]
-
-    seq_ms, seq_stats = wall(sequential)
-    per_ms, (_, per_stats, _) = wall(lambda: gbf.solve_batch(graphs, outs, mode="persistent"))
-    exact = all(bool(torch.equal(a, b)) for a, b in zip(outs, seq))
-    if tuned["encoding"] != "csr":
-        for gr in graphs:
-            gr.free()
-        graphs = [gbf.load_problem(p, encoding=tuned["encoding"]) for p in probs]
-    bat_ms, (_, bat_stats, _) = wall(lambda: gbf.solve_batch(graphs, outs, mode=tuned["mode"], lanes=tuned["lanes"],
-                                                             grid=tuned["grid"]))
-    exact = exact and all(bool(torch.equal(a, b)) for a, b in zip(outs, seq))
+    outs = [torch.empty(p.n, dtype=torch.int32, device="cuda") for p in probs]
+    seq = [torch.empty_like(o) for o in outs]
     res = {"instances": len(probs), "n_states": int(sum(p.n for p in probs)),
            "pairs": int(sum(p.npairs for p in probs)),
-           "sequential_ms": seq_ms, "batched_ms": bat_ms,
-           "tuned": {k: tuned[k] for k in ("encoding", "mode", "lanes", "grid")}, "tune_s": tune_s,
-           "persistent_graph_ms": per_ms, "graph_used": int(per_stats[0]["graph_used"]),
-           "speedup": seq_ms / bat_ms,
-           "edge_relax_batched": int(bat_stats[0]["edge_relax"]),
-           "edge_relax_sequential": int(sum(s["edge_relax"] for s in seq_stats)),
-           "rounds_batched": int(bat_stats[0]["rounds"]), "bit_exact": exact}
-    for gr in graphs:
-        gr.free()
+           "tuned": {k: tuned[k] for k in ("encoding", "mode", "lanes", "grid")}, "tune_s": tune_s}
+    exact = True
+    for enc in dict.fromkeys(["csr", tuned["encoding"]]):
+        graphs = [gbf.load_problem(p, encoding=enc) for p in probs]
+        seq_ms, seq_stats = wall(lambda: [gr.solve(v)[1] for gr, v in zip(graphs, seq)])
+        res[f"sequential_{enc}_ms"] = seq_ms
+        res[f"edge_relax_sequential_{enc}"] = int(sum(s["edge_relax"] for s in seq_stats))
+        per_ms, (_, per_stats, _) = wall(lambda: gbf.solve_batch(graphs, outs, mode="persistent"))
+        exact = exact and all(bool(torch.equal(a, b)) for a, b in zip(outs, seq))
+        res[f"persistent_graph_{enc}_ms"] = per_ms
+        res[f"graph_used_{enc}"] = int(per_stats[0]["graph_used"])
+        if enc == tuned["encoding"]:
+            kw = dict(mode=tuned["mode"], lanes=tuned["lanes"], grid=tuned["grid"])
+            bat_ms, (_, bat_stats, _) = wall(lambda: gbf.solve_batch(graphs, outs, **kw))
+            exact = exact and all(bool(torch.equal(a, b)) for a, b in zip(outs, seq))
+            prof = [gbf.solve_batch(graphs, outs, profile=True, **kw)[1][0] for _ in range(reps)]
+            per_edge = PER_EDGE_BYTES[enc]
+            res["roofline"] = roofline(prof, res["pairs"], per_edge)
+            res["batched_ms"] = bat_ms
+            res["edge_relax_batched"] = int(bat_stats[0]["edge_relax"])
+            res["rounds_batched"] = int(bat_stats[0]["rounds"])
+            res["edge_relax_per_s_batched"] = bat_stats[0]["edge_relax"] / (bat_ms * 1e-3)
+        for gr in graphs:
+            gr.free()
+    res["speedup_same_encoding"] = res[f"sequential_{tuned['encoding']}_ms"] / res["batched_ms"]
+    res["speedup_vs_sequential_csr"] = res["sequential_csr_ms"] / res["batched_ms"]
+    res["bit_exact_vs_sequential_gpu"] = exact
     return res
-
-
-def config_line(prob, encoding, reps=5):
-    """Solve time, edge relaxations/s and device memory of one configuration."""
-    import torch
-
-    import paper_2001_06231_amd as gbf
-    g = gbf.load_problem(prob, encoding=encoding)
-    V = torch.empty(prob.n, dtype=torch.int32 if prob.dtype == "i32" else torch.float32, device="cuda")
-    st = _median_solve(g, reps, V_out=V)
-    g.free()
-    return {"solve_ms": st["solve_ms"], "edge_relax_per_s": st["edge_relax"] / (st["solve_ms"] * 1e-3),
-            "rounds": st["rounds"], "edge_relax": st["edge_relax"], "device_bytes": st["device_bytes"],
-            "encoding": encoding}
 
 
 def run(args, pool=None):
@@ -227,24 +358,24 @@ def run(args, pool=None):
     import torch
 
     import paper_2001_06231_amd as gbf
-    import synth
 
+    info = host_info()
     jobs = {}
+    cpu_labels = []
+    if not args.no_cpu:
+        cpu_labels = ["main"] + ([] if args.no_extras else
+                                 ["grid2d_64x64_i32_csr", "grid4d_384k_f32", "grid4d_384k_i32_csr_edge_costs",
+                                  "batch64", "learned"])
+        jobs["cpu"] = start_cpu_jobs(pool, cpu_labels)
     if not args.no_extras:
-        if pool is not None:
-            jobs["learned"] = pool.apply_async(_gen_learned, (1000,))
-            jobs["batch"] = pool.map_async(_gen_batch, range(64))
-            jobs["grid2d"] = pool.apply_async(_gen_small, ("grid2d",))
-            jobs["grid4d_f32"] = pool.apply_async(_gen_small, ("grid4d_f32",))
-        else:
-            jobs["learned"] = _Done(_gen_learned(1000))
-            jobs["batch"] = _Done([_gen_batch(i) for i in range(64)])
-            jobs["grid2d"] = _Done(_gen_small("grid2d"))
-            jobs["grid4d_f32"] = _Done(_gen_small("grid4d_f32"))
+        for kind in ("grid2d", "grid4d_f32", "grid4d_i32_edge", "learned:1000"):
+            jobs[kind] = pool.apply_async(make_problem, (kind,)) if pool is not None else _Done(make_problem(kind))
+        jobs["batch"] = (pool.map_async(make_problem, [f"batch:{i}" for i in range(64)]) if pool is not None
+                         else _Done([make_problem(f"batch:{i}") for i in range(64)]))
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
     t0 = time.time()
-    prob = synth.grid4d()
+    prob = make_problem("grid4d_i32")
     gen_s = time.time() - t0
     print(f"[bench] generated {prob.name}: n={prob.n} pairs={prob.npairs} m={prob.m} in {gen_s:.1f}s",
           file=sys.stderr, flush=True)
@@ -263,8 +394,9 @@ def run(args, pool=None):
     pol = torch.empty(prob.n, dtype=torch.int32, device="cuda")
     # the other workloads are generated in worker processes; let them finish
     # first so that they do not compete with the host side of the timed loop
-    for j in jobs.values():
-        j.wait()
+    for k, j in jobs.items():
+        if k != "cpu":
+            j.wait()
 
     def step():
         status, st, _ = graph.solve(V, mode=args.mode, lanes=args.lanes, grid=args.grid, profile=True)
@@ -286,15 +418,8 @@ def run(args, pool=None):
 
     ms_per_step = 1e3 * elapsed / args.steps
     edges = float(np.mean([s["edge_relax"] for s in stats]))
-    mode_used = {gbf.MODE_PERSISTENT: "persistent", gbf.MODE_SINGLE_BLOCK: "single_block"}.get(
-        stats[0]["mode_used"], "hostloop")
-    kernel = {"persistent": "k_persistent", "single_block": "k_single"}.get(mode_used, "k_relax")
-    launches = sum(s["relax_launches"] for s in stats)
-    kern_ms = sum(s["relax_ms"] for s in stats) / max(1, launches)
-    total_bytes = sum(algorithmic_bytes(s, prob.npairs, mode_used, s["rounds"]) for s in stats)
-    bytes_per_launch = total_bytes / max(1, launches)
-    achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
-    traffic = read_traffic(kernel)
+    rl = roofline(stats, prob.npairs, PER_EDGE_BYTES["csr"])
+    rl["traffic"] = read_traffic(rl["kernel"])
     out = {
         "metric": METRIC,
         "value": edges / (ms_per_step * 1e-3),
@@ -318,31 +443,21 @@ def run(args, pool=None):
         "rounds": int(np.median([s["rounds"] for s in stats])),
         "edge_relax_per_solve": edges,
         "pair_evals_per_solve": float(np.mean([s["pair_evals"] for s in stats])),
-        "mode": mode_used,
+        "mode": mode_name(stats[0]),
         "lanes": int(stats[0]["lanes_used"]),
         "grid": int(stats[0]["grid_used"]),
-        "roofline": {
-            "bound": "hbm",
-            "kernel": kernel,
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel_avg_ms": kern_ms,
-            "launches_per_step": launches / args.steps,
-            "algorithmic_bytes_per_launch": bytes_per_launch,
-        },
+        "roofline": rl,
         "load_s": load_s,
         "device_bytes": int(stats[0]["device_bytes"]),
         "kernel_source_sha256_16": kernel_source_hash(),
     }
     graph.free()
-    if jobs:
+    if not args.no_extras:
         from paper_2001_06231_amd import learn
         extras = {}
         p2 = jobs["grid2d"].get()
         pf = jobs["grid4d_f32"].get()
+        pe = jobs["grid4d_i32_edge"].get()
         extras["grid2d_64x64_i32_csr"] = config_line(p2, "csr")
         extras["grid4d_384k_i32_box+rev"] = config_line(prob, "box+rev")
         extras["grid4d_384k_i32_box"] = config_line(prob, "box")
@@ -350,19 +465,30 @@ def run(args, pool=None):
         extras["grid4d_384k_f32_box+rev"] = config_line(pf, "box+rev")
         extras["grid4d_384k_f32_box"] = config_line(pf, "box")
         # the same graph with the running cost on the edges, g(x,u) + h(x,y,u)
-        extras["grid4d_384k_i32_csr_edge_costs"] = config_line(synth.with_edge_costs(prob, 34), "csr")
+        extras["grid4d_384k_i32_csr_edge_costs"] = config_line(pe, "csr")
         print("[bench] configs done", file=sys.stderr, flush=True)
         out["configs"] = extras
         out["batch64"] = batch_compare(jobs["batch"].get())
         print("[bench] batch done", file=sys.stderr, flush=True)
         if os.path.exists(learn.WEIGHTS):
-            out["learned"] = learned_compare(jobs["learned"].get(), learn.load_params(),
-                                             learn.init_params(1))
+            out["learned"] = learned_compare(jobs["learned:1000"].get(), learn.load_params(), learn.init_params(1))
         else:
             out["learned"] = {"skipped": "no trained weights"}
         print("[bench] learned done", file=sys.stderr, flush=True)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_reps)
+    if "cpu" in jobs:
+        cpu = dict(jobs["cpu"].get())
+        print("[bench] cpu baselines done", file=sys.stderr, flush=True)
+        attach_cpu(out, cpu, "main", info)
+        if not args.no_extras:
+            attach_cpu(out["configs"]["grid2d_64x64_i32_csr"], cpu, "grid2d_64x64_i32_csr", info)
+            for k in ("grid4d_384k_f32_csr", "grid4d_384k_f32_box+rev", "grid4d_384k_f32_box"):
+                attach_cpu(out["configs"][k], cpu, "grid4d_384k_f32", info)
+            for k in ("grid4d_384k_i32_box+rev", "grid4d_384k_i32_box"):
+                attach_cpu(out["configs"][k], cpu, "main", info)
+            attach_cpu(out["configs"]["grid4d_384k_i32_csr_edge_costs"], cpu, "grid4d_384k_i32_csr_edge_costs", info)
+            attach_cpu(out["batch64"], cpu, "batch64", info)
+            if "plain" in out["learned"]:
+                attach_cpu(out["learned"], cpu, "learned", info)
     return out
 
 
@@ -377,15 +503,17 @@ def learned_eval(args, pool):
     params = learn.load_params()
     untrained = learn.init_params(1)
     recs = []
-    idx = list(range(1000, 1000 + args.learned_eval))
-    gen = pool.imap(_gen_learned, idx) if pool is not None else map(_gen_learned, idx)
+    idx = [f"learned:{i}" for i in range(1000, 1000 + args.learned_eval)]
+    gen = pool.imap(make_problem, idx) if pool is not None else map(make_problem, idx)
     for i, prob in zip(idx, gen):
         r = learned_compare(prob, params, untrained, reps=args.eval_reps)
         recs.append(r)
         print(f"[eval] {i}: plain {r['plain']['solve_ms']:.2f} ms / {r['plain']['edge_relax']:.3e} edges, "
               f"learned {r['learned']['solve_ms']:.2f} (+{r['learned']['mlp_ms']:.2f}) ms / "
-              f"{r['learned']['edge_relax']:.3e}, untrained {r['untrained']['solve_ms']:.2f} ms, "
-              f"exact {r['learned']['bit_exact'] and r['untrained']['bit_exact']}", file=sys.stderr, flush=True)
+              f"{r['learned']['edge_relax']:.3e}, untrained {r['untrained']['solve_ms']:.2f} ms "
+              f"(fallback {r['untrained']['fallback']}), "
+              f"exact {r['learned']['bit_exact_vs_plain_gpu'] and r['untrained']['bit_exact_vs_plain_gpu']}",
+              file=sys.stderr, flush=True)
 
     def mean(f):
         return float(np.mean([f(r) for r in recs]))
@@ -400,30 +528,16 @@ def learned_eval(args, pool):
         "untrained_edge_relax": mean(lambda r: r["untrained"]["edge_relax"]),
         "plain_rounds": mean(lambda r: r["plain"]["rounds"]),
         "learned_rounds": mean(lambda r: r["learned"]["rounds"]),
-        "all_bit_exact": all(r["learned"]["bit_exact"] and r["untrained"]["bit_exact"] for r in recs),
-        "fallbacks": int(sum(r["learned"]["fallback"] + r["untrained"]["fallback"] for r in recs)),
+        "all_bit_exact": all(r["learned"]["bit_exact_vs_plain_gpu"] and r["untrained"]["bit_exact_vs_plain_gpu"]
+                             for r in recs),
+        "fallbacks_learned": int(sum(r["learned"]["fallback"] for r in recs)),
+        "fallbacks_untrained": int(sum(r["untrained"]["fallback"] for r in recs)),
     }
     summary["wall_speedup_incl_mlp"] = summary["plain_solve_ms"] / (summary["learned_solve_ms"] +
                                                                      summary["learned_mlp_ms"])
     summary["relaxation_reduction"] = summary["plain_edge_relax"] / summary["learned_edge_relax"]
+    summary["untrained_over_plain"] = summary["untrained_solve_ms"] / summary["plain_solve_ms"]
     return {"summary": summary, "instances": recs}
-
-
-def cpu_baseline(prob, reps):
-    import numpy as np
-
-    import oracle
-    times, edges = [], []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        r = oracle.solve(prob)
-        times.append(time.perf_counter() - t0)
-        edges.append(r["counters"]["edge_relax"])
-    t = float(np.median(times))
-    return {"value": float(np.median(edges)) / t, "unit": "edge_relaxations/s", "cores": 1, "kind": "oracle",
-            "sample": f"the full 4-D 384k-cell instance, {reps} single-threaded solves (median); the oracle "
-                      "counts its own relaxations (state frontier x all inputs)",
-            "solve_s": t}
 
 
 def main():
@@ -435,7 +549,6 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true", help="run a 256 MiB device copy first (counter reference)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the main workload (no other configs, batch or learned comparison)")
@@ -443,15 +556,16 @@ def main():
                     help="instead: evaluate the trained network on this many held-out instances")
     ap.add_argument("--eval-reps", type=int, default=3)
     ap.add_argument("--workers", type=int, default=8,
-                    help="generator processes (1 = generate in this process, e.g. under a profiler)")
+                    help="worker processes for input generation and the CPU oracle (1 = none, e.g. under a "
+                         "profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver has no multi-GPU "
               "path", file=sys.stderr)
         sys.exit(2)
-    # the generator workers are forked before the first GPU call
+    # the worker processes are forked before the first GPU call
     pool = None
-    if args.workers > 1 and (args.learned_eval or not args.no_extras):
+    if args.workers > 1 and (args.learned_eval or not args.no_extras or not args.no_cpu):
         import multiprocessing as mp
         pool = mp.get_context("fork").Pool(args.workers)
     try:

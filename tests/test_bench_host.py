@@ -10,14 +10,43 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_algorithmic_bytes_model():
-    st = {"pair_evals": 10, "edge_relax": 180, "expansions": 3, "marks": 600}
-    # relax: 20 per pair + 8 per edge; expansion: 8 per state + 5 per mark
-    assert bench.algorithmic_bytes(st, 1000, "hostloop", 7) == 20 * 10 + 8 * 180 + 8 * 3 + 5 * 600
-    # the persistent and single-block kernels also read the map once per round
-    # (rounds + 1 scans) and write 4 bytes per listed pair
-    want = 20 * 10 + 8 * 180 + 8 * 3 + 5 * 600 + 8 * 1000 + 4 * 10
-    assert bench.algorithmic_bytes(st, 1000, "persistent", 7) == want
-    assert bench.algorithmic_bytes(st, 1000, "single_block", 7) == want
+    st = {"pair_evals": 10, "edge_relax": 180, "expansions": 3, "marks": 600, "rounds": 7}
+    # relax: 20 per pair + 8 per CSR successor; expansion: 8 per state + 8 per
+    # visited predecessor pair
+    base = 20 * 10 + 8 * 3 + 8 * 600
+    assert bench.algorithmic_bytes(st, 1000, 8, "hostloop") == base + 8 * 180
+    # box successors: 4 bytes per successor (no index stream)
+    assert bench.algorithmic_bytes(st, 1000, 4, "hostloop") == base + 4 * 180
+    # the persistent and single-block kernels also read and clear the
+    # frontier once per round (rounds + 1 scans of nK/4 bytes) and write 4
+    # bytes per listed pair
+    want = base + 8 * 180 + 8 * 1000 / 4 + 4 * 10
+    assert bench.algorithmic_bytes(st, 1000, 8, "persistent") == want
+    assert bench.algorithmic_bytes(st, 1000, 8, "single_block") == want
+
+
+def test_roofline_from_profiled_solves():
+    """achieved = algorithmic bytes per launch over the average launch time."""
+    import paper_2001_06231_amd as gbf
+    st = {"pair_evals": 1000, "edge_relax": 16000, "expansions": 100, "marks": 20000, "rounds": 5,
+          "relax_launches": 10, "relax_ms": 0.5, "mode_used": gbf.MODE_HOSTLOOP}
+    r = bench.roofline([st, st], 4096, 8)
+    per_launch = (20 * 1000 + 8 * 16000 + 8 * 100 + 8 * 20000) / 10
+    assert r["kernel"] == "k_relax" and r["unit"] == "GB/s" and r["bound"] == "hbm"
+    assert abs(r["algorithmic_bytes_per_launch"] - per_launch) < 1e-6
+    assert abs(r["achieved"] - per_launch / 0.05e-3 / 1e9) < 1e-6
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-12
+
+
+def test_cpu_job_pins_one_core():
+    """The CPU baseline runs the oracle in a process pinned to one core."""
+    import os as _os
+    core = sorted(_os.sched_getaffinity(0))[-1]
+    before = _os.sched_getaffinity(0)
+    label, r = bench.cpu_job(("t", ["grid2d"], 1, None, core))
+    assert _os.sched_getaffinity(0) == {core}
+    _os.sched_setaffinity(0, before)
+    assert r["cores"] == 1 and r["pinned_core"] == core and r["value"] > 0 and r["edge_relax"] > 0
 
 
 def test_traffic_read_only_for_the_same_kernel_source(tmp_path, monkeypatch):
