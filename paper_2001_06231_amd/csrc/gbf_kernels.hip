@@ -50,6 +50,9 @@
 #ifndef GBF_ILP
 #define GBF_ILP 1  // wave steps whose gathers a host-loop relax wave keeps in flight together (2+ measured slower)
 #endif
+#ifndef GBF_XCD_BARRIER
+#define GBF_XCD_BARRIER 1  // persistent kernel: one L2 write-back per XCD and barrier
+#endif
 #ifndef GBF_COMPACT_GRID
 #define GBF_COMPACT_GRID 512  // blocks of a host-loop compaction
 #endif
@@ -1245,25 +1248,54 @@ __global__ __launch_bounds__(kBlock) void k_relax(const Inst* __restrict__ It, R
 // barrier that does not complete within R.timeout_ticks of the constant-rate
 // device clock sets R.error, and every block leaves the loop (blocks that
 // start after an error leave at once).
-// Barrier words, each on its own 128-byte line (uint32 index * 32):
+// Barrier words, each counter on its own 128-byte line (uint32 index * 32):
 //   line 0: top-level arrival counter, line 1: generation,
-//   line 2 + g: arrival counter of group g (blocks b with b % kBarGroups == g).
+//   line 2 + g: arrival counter of group g (blocks b with b % kBarGroups == g),
+//   line 18: blocks per XCD (word k for XCD k) and, word 16, the number of
+//            XCDs with blocks,
+//   line 19: arrival counter of the XCD leaders,
+//   lines 20..27: arrival counter of XCD k at word 20*32 + 16*k.
 // Arrivals are device-scope atomics, which execute at the memory side and
 // serialise per address; spreading them over groups keeps each chain short.
 constexpr int kBarGroups = 16;
 constexpr int kBarLine = 32;
-static_assert((2 + kBarGroups) * kBarLine * 4 <= 4096, "barrier words exceed their 4 KiB allocation");
+constexpr int kMaxXcd = 16;
+constexpr int kBarXcdInfo = 18 * kBarLine;
+constexpr int kBarXcdTop = 19 * kBarLine;
+constexpr int kBarXcdCtr = 20 * kBarLine;
+static_assert(kBarXcdCtr + kMaxXcd * 16 <= 1024, "barrier words exceed their 4 KiB allocation");
 
+// The accelerator complex (XCD) this wave runs on.  Each XCD has its own L2.
+__device__ __forceinline__ uint32_t xcd_id() {
+    return (uint32_t)__builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11)) & (kMaxXcd - 1);
+}
+
+// Waits (thread 0 of the block) until the generation word moves past
+// `gen`, with relaxed loads: an acquire load would invalidate the XCD's L2
+// on every poll and evict the data the blocks still working there use.
+__device__ __forceinline__ int wait_generation(uint32_t* gen_w, uint32_t gen, int32_t* err, uint64_t timeout_ticks) {
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(gen_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(4);
+        if (wall_clock64() - t0 > timeout_ticks ||
+            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            atomicOr(err, 1);
+            return 0;
+        }
+    }
+    return 1;
+}
+
+// Grid barrier over all blocks, arrivals combined in groups of blocks.
 __device__ __forceinline__ bool grid_barrier(uint32_t* bar, int32_t* err, uint32_t nblocks, uint64_t timeout_ticks) {
     __shared__ int s_ok;
-    // the block barrier completes every wave's stores; one agent-scope
-    // release fence per block (not per wave) then publishes them
-    // device-wide, and one acquire fence after the wait makes the other
-    // blocks' stores visible
+    // the block barrier orders every wave's stores before thread 0's
+    // agent-scope release fence, which publishes them device-wide; one
+    // acquire fence after the wait makes the other blocks' stores visible
     __syncthreads();
     if (threadIdx.x == 0) {
-        // release: this block's stores (completed by the block barrier)
-        // are written back to memory before the arrival is seen
+        // release: this block's stores are written back to memory before
+        // the arrival is seen
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         int ok = 1;
         uint32_t* top = bar;
@@ -1284,22 +1316,64 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* bar, int32_t* err, uint32
                 released = true;
             }
         }
-        if (!released) {
-            const uint64_t t0 = wall_clock64();
-            while (__hip_atomic_load(gen_w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(4);
-                if (wall_clock64() - t0 > timeout_ticks ||
-                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                    atomicOr(err, 1);
-                    ok = 0;
-                    break;
-                }
-            }
-        }
+        if (!released) ok = wait_generation(gen_w, gen, err, timeout_ticks);
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
         s_ok = ok;
         // acquire: stale lines of other blocks' data are dropped before the
         // block reads again
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// Registers the block with the XCD it runs on (once, before the first
+// grid barrier; after that barrier the counts are final).
+__device__ __forceinline__ void xcd_register(uint32_t* bar) {
+    if (threadIdx.x == 0) {
+        const uint32_t x = xcd_id();
+        const uint32_t a = __hip_atomic_fetch_add(bar + kBarXcdInfo + x, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        if (a == 0) __hip_atomic_fetch_add(bar + kBarXcdInfo + kMaxXcd, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Grid barrier with one L2 write-back per XCD: every wave waits until its
+// own stores have completed (they are then in its XCD's L2), the blocks of
+// an XCD count their arrivals, and the last block of each XCD writes that
+// L2 back to memory (one agent-scope release) and arrives at the top
+// level.  The last XCD leader advances the generation; every block then
+// drops its stale cache lines (agent-scope acquire) before reading again.
+// xsize: blocks on this block's XCD; nx: XCDs holding blocks (both from
+// xcd_register).
+__device__ __forceinline__ bool xcd_barrier(uint32_t* bar, int32_t* err, uint32_t xsize, uint32_t nx,
+                                            uint64_t timeout_ticks) {
+    __shared__ int s_ok;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have completed
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        uint32_t* gen_w = bar + kBarLine;
+        uint32_t* xtop = bar + kBarXcdTop;
+        uint32_t* xctr = bar + kBarXcdCtr + 16 * xcd_id();
+        const uint32_t gen = __hip_atomic_load(gen_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t a = __hip_atomic_fetch_add(xctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bool released = false;
+        if (a == xsize - 1) {
+            __hip_atomic_store(xctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // every block of this XCD has arrived with its stores in this
+            // L2: write it back once for all of them
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const uint32_t t = __hip_atomic_fetch_add(xtop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == nx - 1) {
+                __hip_atomic_store(xtop, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(gen_w, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                released = true;
+            }
+        }
+        if (!released) ok = wait_generation(gen_w, gen, err, timeout_ticks);
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
+        s_ok = ok;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
@@ -1326,12 +1400,29 @@ void k_persistent(const Inst* __restrict__ It, Run R) {
     Acc acc;
     uint64_t t_bar = 0;  // block 0: device-clock ticks spent in barriers
     const int64_t ntiles = (R.nchunks + kPBlock * kPCompactC - 1) / (kPBlock * kPCompactC);
+#if GBF_XCD_BARRIER
+    __shared__ uint32_t s_xsize, s_nx;
+    xcd_register(R.barrier);
+    if (!grid_barrier(R.barrier, R.error, gridDim.x, R.timeout_ticks)) {
+        flush_acc(acc, s_acc, R.slots);
+        return;
+    }
+    if (threadIdx.x == 0) {
+        s_xsize = __hip_atomic_load(R.barrier + kBarXcdInfo + xcd_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_nx = __hip_atomic_load(R.barrier + kBarXcdInfo + kMaxXcd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const uint32_t xsize = s_xsize, nx = s_nx;
+#define GBF_PBARRIER() xcd_barrier(R.barrier, R.error, xsize, nx, R.timeout_ticks)
+#else
+#define GBF_PBARRIER() grid_barrier(R.barrier, R.error, gridDim.x, R.timeout_ticks)
+#endif
     for (int round = 0;; ++round) {
         uint8_t* cur = R.dirty[round & 1];
         for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
             compact_tile<kPBlock, kPCompactC>(cur, R.nchunks, tile, R.list, R.counts + round, s_w, &s_base);
         uint64_t t0 = wall_clock64();
-        const bool ok1 = grid_barrier(R.barrier, R.error, gridDim.x, R.timeout_ticks);
+        const bool ok1 = GBF_PBARRIER();
         t_bar += wall_clock64() - t0;
         if (!ok1) break;
         const uint32_t count = __hip_atomic_load(R.counts + round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1342,10 +1433,11 @@ void k_persistent(const Inst* __restrict__ It, Run R) {
         relax_round<T, MULTI, ENC, G, 1>(It, s_bases, R, count, round, acc);
         fold_acc(acc, s_acc);
         t0 = wall_clock64();
-        const bool ok2 = grid_barrier(R.barrier, R.error, gridDim.x, R.timeout_ticks);
+        const bool ok2 = GBF_PBARRIER();
         t_bar += wall_clock64() - t0;
         if (!ok2) break;
     }
+#undef GBF_PBARRIER
     if (blockIdx.x == 0 && threadIdx.x == 0) reinterpret_cast<uint64_t*>(R.result)[1] = t_bar;
     flush_acc(acc, s_acc, R.slots);
 }
