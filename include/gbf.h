@@ -124,7 +124,14 @@ typedef struct gbf_problem {
      *       at load stays within mem_budget, else the problem stays
      *       implicit as in 0.  gbf_stats.enc_used reports the choice. */
     int32_t expand_box;
-    int32_t reserved0;
+    /* Width of the (x,u) pair ids inside the solver.  Problems with
+     * n_states * n_inputs < 2^31 use 32-bit ids; larger ones (up to the
+     * 2^32 - 1 states that the box encoding addresses) use 64-bit ids, with
+     * GBF_BOX and expand_box 0, 2 or 3 only: one instance per solve, the
+     * host-loop mode and the plain order (Sect. VI-A solves a problem of
+     * 141.7 M states and 35 inputs, about 5 G pairs).  1 = 64-bit ids at any
+     * size (same restrictions); 0 = by size. */
+    int32_t pair_ids64;
     /* Optional per-edge part of the running cost (Sect. III-B defines the
      * running cost on transitions, g(x,y,u); the operator of Sect. III-C
      * and the sup of Algorithm 1 take g(x,y,u) + W(y) per successor).  The
@@ -162,13 +169,31 @@ typedef struct gbf_opts {
                                of the k buckets from the lowest occupied one up;
                                -1 = ascending sweeps, one bucket per round;
                                0 = default (GBF_BUCKET_SPAN_DEFAULT) */
-    int32_t reserved[2];
+    int32_t bucket_budget;  /* BUCKETS: work budget in percent of the reference
+                               (the pair evaluations of the handle's last
+                               plain solve, and twice its rounds; without
+                               one, 16 evaluations per pair): past it, or
+                               when from round 24 on the pair evaluations so
+                               far fall below half of that plain solve's at
+                               the same round (host-loop plain solves keep
+                               that profile), the solve finishes in plain
+                               order (gbf_stats.fallback 1).  0 = 100;
+                               -1 = no budget (the switch still comes by
+                               round 65536, so that the plain continuation
+                               keeps the plain round cap) */
+    int32_t reserved[1];
 } gbf_opts;
 
 /* ---- statistics ------------------------------------------------------- */
 typedef struct gbf_stats {
     int32_t status;         /* status of this solve */
-    int32_t fallback;       /* 1 = bucket order fell back to plain order */
+    int32_t fallback;       /* bucket order: 0 = ran in bucket order to the end;
+                               1 = exceeded its work budget
+                               (gbf_opts.bucket_budget) and finished in plain
+                               order from the current iterate; 2 = reached
+                               its round cap and
+                               the plain order was rerun from scratch.  The
+                               values and policy are the same in every case. */
     int64_t rounds;         /* rounds executed (passes of the while loop) */
     int64_t pair_evals;     /* pairs (x,u) whose successors were read */
     int64_t edge_relax;     /* sum of |F(x,u)| over those pairs */
@@ -207,7 +232,10 @@ typedef struct gbf_graph gbf_graph;
  * Errors: GBF_EINVAL (n or K <= 0, empty F(x,u), index or box outside the
  * grid, NaN or -inf cost, finite G on an avoid cell, m >= 2^31, per-edge
  * costs that are not finite or come with GBF_BOX, expand_box outside 0..3,
- * mem_budget < 0), GBF_ENOMEM, GBF_EHIP.  On error *out is NULL. */
+ * mem_budget < 0, n_states * n_inputs >= 2^31 or pair_ids64 = 1 without
+ * GBF_BOX and expand_box 0, 2 or 3, n_states >= 2^32, predecessor offsets
+ * of 2^31 pairs or more with 64-bit ids and expand_box 2), GBF_ENOMEM,
+ * GBF_EHIP.  On error *out is NULL. */
 int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph** out);
 
 /* Runs Algorithm 1 (Sect. IV-A) until the frontier is empty or the round

@@ -63,7 +63,7 @@ class _Problem(ctypes.Structure):
                 ("encoding", ctypes.c_int32), ("memspace", ctypes.c_int32), ("G", ctypes.c_void_p),
                 ("g", ctypes.c_void_p), ("avoid", ctypes.c_void_p), ("succ_ptr", ctypes.c_void_p),
                 ("succ_idx", ctypes.c_void_p), ("dims", ctypes.c_int32 * 4), ("box", ctypes.c_void_p),
-                ("expand_box", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("g_edge", ctypes.c_void_p),
+                ("expand_box", ctypes.c_int32), ("pair_ids64", ctypes.c_int32), ("g_edge", ctypes.c_void_p),
                 ("mem_budget", ctypes.c_int64)]
 
 
@@ -71,7 +71,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("mode", ctypes.c_int32), ("bucket_key", ctypes.c_void_p),
                 ("max_rounds", ctypes.c_int64), ("lanes", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("v_memspace", ctypes.c_int32), ("profile", ctypes.c_int32), ("batch_hint", ctypes.c_int32),
-                ("bucket_span", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("bucket_span", ctypes.c_int32), ("bucket_budget", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class _Stats(ctypes.Structure):
@@ -220,10 +220,12 @@ class Graph:
                 L.gbf_free_graph(self._h)
             self._h = None
 
-    def _opts(self, order, mode, max_rounds, grid, profile, bucket_key, v_space, lanes=0, bucket_span=0):
+    def _opts(self, order, mode, max_rounds, grid, profile, bucket_key, v_space, lanes=0, bucket_span=0,
+              bucket_budget=0):
         o = _Opts()
         o.lanes = int(lanes)
         o.bucket_span = int(bucket_span)
+        o.bucket_budget = int(bucket_budget)
         o.order = _ORDERS[order]
         o.mode = _MODES[mode]
         o.max_rounds = int(max_rounds)
@@ -239,7 +241,7 @@ class Graph:
         return o
 
     def solve(self, V_out=None, *, order="plain", mode="auto", max_rounds=0, grid=0, profile=False,
-              bucket_key=None, lanes=0, bucket_span=0, check=True):
+              bucket_key=None, lanes=0, bucket_span=0, bucket_budget=0, check=True):
         """Runs the solver; returns (status, stats dict, V_out).  V_out may be
         a numpy array (host) or a torch tensor on the GPU; if None a numpy
         array is allocated."""
@@ -247,7 +249,7 @@ class Graph:
         if V_out is None:
             V_out = np.empty(self.n, dtype=np.int32 if self.dtype == I32 else np.float32)
         vp, vs = _ptr(V_out)
-        o = self._opts(order, mode, max_rounds, grid, profile, bucket_key, vs, lanes, bucket_span)
+        o = self._opts(order, mode, max_rounds, grid, profile, bucket_key, vs, lanes, bucket_span, bucket_budget)
         st = _Stats()
         rc = L.gbf_solve(self._h, ctypes.byref(o), vp, ctypes.byref(st))
         if rc < 0 or (check and rc not in (OK, ENEGCYCLE)):
@@ -284,7 +286,8 @@ class Graph:
 
 
 def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=None, succ_idx=None,
-               dims=None, box=None, expand_box=False, g_edge=None, mem_budget=0, stream=None) -> Graph:
+               dims=None, box=None, expand_box=False, g_edge=None, mem_budget=0, pair_ids64=False,
+               stream=None) -> Graph:
     """gbf_load_graph.  Arrays are numpy (host) or torch tensors on the GPU
     (all of one kind).  G/g (and the optional per-edge costs g_edge, CSR
     only) are int32 or float32 bit patterns."""
@@ -324,6 +327,7 @@ def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=
             p.dims[a] = int(d[a])
         p.expand_box = int(expand_box)
         p.mem_budget = int(mem_budget)
+    p.pair_ids64 = 1 if pair_ids64 else 0
     if len(spaces) > 1:
         raise ValueError("problem arrays must all be host arrays or all device tensors")
     p.memspace = spaces.pop() if spaces else HOST
@@ -334,7 +338,7 @@ def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=
     return Graph(h, int(n), int(K), p.dtype, None)
 
 
-def load_problem(prob, encoding="csr", stream=None, mem_budget=0) -> Graph:
+def load_problem(prob, encoding="csr", stream=None, mem_budget=0, pair_ids64=False) -> Graph:
     """Loads an object with the fields of an optimal control problem
     (n, K, dtype, G, g, avoid, succ_ptr/succ_idx or dims/box_packed(), and
     optionally per-edge costs g_edge in succ_idx order).
@@ -353,18 +357,20 @@ def load_problem(prob, encoding="csr", stream=None, mem_budget=0) -> Graph:
     if encoding == "box:budget":
         return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="box", avoid=prob.avoid,
                           dims=prob.dims, box=prob.box_packed(), expand_box=3, mem_budget=mem_budget,
-                          stream=stream)
+                          pair_ids64=pair_ids64, stream=stream)
     if encoding == "box+rev":
         return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="box", avoid=prob.avoid,
-                          dims=prob.dims, box=prob.box_packed(), expand_box=2, stream=stream)
+                          dims=prob.dims, box=prob.box_packed(), expand_box=2, pair_ids64=pair_ids64,
+                          stream=stream)
     if encoding == "box->csr" or (encoding == "csr" and getattr(prob, "succ_ptr", None) is None):
         return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="box", avoid=prob.avoid,
-                          dims=prob.dims, box=prob.box_packed(), expand_box=1, stream=stream)
+                          dims=prob.dims, box=prob.box_packed(), expand_box=1, pair_ids64=pair_ids64,
+                          stream=stream)
     if encoding == "csr":
         return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="csr", avoid=prob.avoid,
                           succ_ptr=prob.succ_ptr, succ_idx=prob.succ_idx, stream=stream)
     return load_graph(prob.n, prob.K, prob.G, prob.g, dtype=prob.dtype, encoding="box", avoid=prob.avoid,
-                      dims=prob.dims, box=prob.box_packed(), stream=stream)
+                      dims=prob.dims, box=prob.box_packed(), pair_ids64=pair_ids64, stream=stream)
 
 
 def solve_batch(graphs: Sequence[Graph], V_outs=None, *, mode="auto", max_rounds=0, grid=0, profile=False,

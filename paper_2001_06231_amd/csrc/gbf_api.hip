@@ -33,6 +33,27 @@ constexpr int kPersistentBlocksPerCU = GBF_PBLOCKS;
 #endif
 constexpr int64_t kSingleBlockMaxPairs = GBF_SINGLE_BLOCK_MAX_PAIRS;
 
+// Bucket order: extra rounds allowed beyond the plain cap (one per possible
+// bucket key), a window spanning every bucket, and the work budget: at most
+// the pair evaluations and twice the rounds of the handle's last plain
+// solve, or without one 16 evaluations per pair.  Past the budget the solve
+// continues in plain order; the switch happens by round kBucketRounds at
+// the latest, so the continuation keeps at least the plain cap.
+constexpr int64_t kBucketRounds = 65536;
+constexpr int32_t kBucketsAll = 65536;
+constexpr double kBucketEvalFactor = 1.0;
+constexpr double kBucketRoundFactor = 2.0;
+constexpr int64_t kBucketEvalsPerPair = 16;
+// Progress test against the last plain solve's per-round profile: from
+// round kProgressRound on, a bucket order whose pair evaluations so far are
+// below kProgressFactor times the plain order's at the same round is taken
+// to be falling behind (keys that do not follow V), and the solve finishes
+// in plain order.  Measured on the learned-order instances: trained keys
+// stay above 0.6 of the plain profile, untrained ones drop to 0.3-0.5 by
+// round 24.
+constexpr int64_t kProgressRound = 24;
+constexpr double kProgressFactor = 0.5;
+
 static int fail(int code, const std::string& msg) {
     t_err = msg;
     return code;
@@ -80,6 +101,7 @@ struct DevMem {
 struct Scratch {
     int64_t total_pairs = 0;
     int64_t counts_cap = 0;
+    int64_t list_bytes = 0, counts_bytes = 0;  // allocated sizes (ids are 4 or 8 bytes)
     uint8_t* dirty[2] = {nullptr, nullptr};
     uint32_t* list = nullptr;
     uint32_t* counts = nullptr;
@@ -129,29 +151,47 @@ struct gbf_graph {
     DevMem mem;
     Inst inst{};
     bool solved = false;
+    bool wide = false;  // 64-bit pair ids
+    // the last plain-order solve of this handle (0 = none): the reference
+    // of the bucket order's work budget, and (host-loop solves) its pair
+    // evaluations accumulated round by round
+    int64_t ref_evals = 0, ref_rounds = 0;
+    std::vector<int64_t> ref_profile;
     Scratch scratch;
 };
 
-static int ensure_scratch(Scratch& S, int64_t total_pairs, int64_t max_rounds, int ninst, int nevents) {
+static int ensure_scratch(Scratch& S, int64_t total_pairs, int64_t max_rounds, int ninst, int nevents,
+                          int idbytes = 4) {
     if (S.fixed) {
-        if (total_pairs > S.total_pairs || max_rounds + 2 > S.counts_cap || ninst > S.ninst_cap)
+        if (total_pairs > S.total_pairs || max_rounds + 2 > S.counts_cap || ninst > S.ninst_cap || idbytes != 4)
             return fail(GBF_EINVAL, "problem exceeds the static scratch of the no-allocation solve");
         return GBF_OK;
     }
     const int64_t nchunks = (total_pairs + 15) / 16;
     if (S.total_pairs < total_pairs) {
-        if (S.dirty[0]) S.mem.release(S.dirty[0], 0), S.mem.release(S.dirty[1], 0), S.mem.release(S.list, 0);
+        const int64_t old = (S.total_pairs + 15) / 16 * 16;
+        if (S.dirty[0]) S.mem.release(S.dirty[0], old), S.mem.release(S.dirty[1], old);
         int rc;
         if ((rc = S.mem.alloc((void**)&S.dirty[0], nchunks * 16))) return rc;
         if ((rc = S.mem.alloc((void**)&S.dirty[1], nchunks * 16))) return rc;
-        if ((rc = S.mem.alloc((void**)&S.list, total_pairs * 4))) return rc;
         S.total_pairs = total_pairs;
     }
-    if (S.counts_cap < max_rounds + 2) {
-        if (S.counts) S.mem.release(S.counts, 0);
+    if (S.list_bytes < total_pairs * idbytes) {
+        if (S.list) S.mem.release(S.list, S.list_bytes);
+        S.list = nullptr;
+        S.list_bytes = 0;
         int rc;
-        if ((rc = S.mem.alloc((void**)&S.counts, (max_rounds + 2) * 4))) return rc;
-        S.counts_cap = max_rounds + 2;
+        if ((rc = S.mem.alloc((void**)&S.list, total_pairs * idbytes))) return rc;
+        S.list_bytes = total_pairs * idbytes;
+    }
+    if (S.counts_bytes < (max_rounds + 2) * idbytes) {
+        if (S.counts) S.mem.release(S.counts, S.counts_bytes);
+        S.counts = nullptr;
+        S.counts_bytes = 0;
+        int rc;
+        if ((rc = S.mem.alloc((void**)&S.counts, (max_rounds + 2) * idbytes))) return rc;
+        S.counts_bytes = (max_rounds + 2) * idbytes;
+        S.counts_cap = S.counts_bytes / 4;
     }
     if (!S.ctr) {
         int rc;
@@ -164,13 +204,13 @@ static int ensure_scratch(Scratch& S, int64_t total_pairs, int64_t max_rounds, i
         if ((rc = S.mem.alloc((void**)&S.thr, 64))) return rc;
     }
     if (S.ninst_cap < ninst) {
-        if (S.dinst) S.mem.release(S.dinst, 0), S.mem.release(S.inst_status, 0);
+        if (S.dinst) S.mem.release(S.dinst, sizeof(Inst) * S.ninst_cap), S.mem.release(S.inst_status, 4 * S.ninst_cap);
         int rc;
         if ((rc = S.mem.alloc((void**)&S.dinst, sizeof(Inst) * ninst))) return rc;
         if ((rc = S.mem.alloc((void**)&S.inst_status, 4 * ninst))) return rc;
         S.ninst_cap = ninst;
     }
-    const size_t hb = 4096 + 4 * (size_t)ninst + 1024;
+    const size_t hb = 16384 + 4 * (size_t)ninst;
     if (S.host_bytes < hb) {
         if (S.host) (void)hipHostFree(S.host);
         S.host = nullptr;
@@ -187,6 +227,94 @@ static int ensure_scratch(Scratch& S, int64_t total_pairs, int64_t max_rounds, i
 }
 
 // ------------------------------------------------------------------ load
+// The part of the loader after validation for 64-bit pair ids (GBF_BOX):
+// pruning, the per-input predecessor windows, and for expand_box 2 (or 3
+// within the memory budget) a reverse CSR built straight from the boxes,
+// whose entries are the predecessor pair ids relative to y*K (int32).
+static int load_wide(gbf_graph* gr, const gbf_problem* p, int eb, int32_t* err) {
+    Inst& I = gr->inst;
+    DevMem& M = gr->mem;
+    hipStream_t s = gr->stream;
+    const int64_t n = I.n, K = I.K;
+    int rc;
+    HIPC(launch_prune(I, p->dtype, s));
+    int32_t* win;
+    if ((rc = M.alloc((void**)&win, K * 8 * 4))) return rc;
+    std::vector<int32_t> hw(K * 8);
+    for (int64_t u = 0; u < K; ++u)
+        for (int a = 0; a < 4; ++a) {
+            hw[u * 8 + a] = 0x7fffffff;
+            hw[u * 8 + 4 + a] = (int32_t)0x80000000;
+        }
+    HIPC(hipMemcpyAsync(win, hw.data(), K * 8 * 4, hipMemcpyHostToDevice, s));
+    HIPC(launch_box_window(I, win, s));
+    HIPC(hipMemcpyAsync(hw.data(), win, K * 8 * 4, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    I.win = win;
+    M.release(err, 64);
+    if (eb != 2 && eb != 3) return GBF_OK;
+    // a reverse entry is (x - y)*K + u for y in F(x,u): bound |x - y| by the
+    // windows' offsets so that it fits int32
+    int64_t maxoff = 0;
+    for (int64_t u = 0; u < K; ++u) {
+        if (hw[u * 8] > hw[u * 8 + 4]) continue;  // no live pair with this input
+        int64_t off = 0;
+        for (int a = 0; a < 4; ++a)
+            off += std::max<int64_t>(std::abs((int64_t)hw[u * 8 + a]), std::abs((int64_t)hw[u * 8 + 4 + a])) *
+                   I.strides[a];
+        maxoff = std::max(maxoff, off);
+    }
+    if ((maxoff + 1) * K >= ((int64_t)1 << 31)) {
+        if (eb == 2) return fail(GBF_EINVAL, "64-bit pair ids with expand_box 2 need predecessor offsets below 2^31 pairs");
+        return GBF_OK;  // stays implicit
+    }
+    uint32_t* cnt;
+    uint64_t *rptr, *tmp;
+    const int64_t nb = (n + 1023) / 1024 + 1;
+    if ((rc = M.alloc((void**)&cnt, (n + 1) * 4)) || (rc = M.alloc((void**)&rptr, (n + 1) * 8)) ||
+        (rc = M.alloc((void**)&tmp, nb * 8)))
+        return rc;
+    HIPC(launch_fill_u32(cnt, 0, n + 1, s));
+    HIPC(launch_rev_count_box(I, cnt, s));
+    HIPC(launch_scan64(cnt, rptr, n, tmp, s));
+    uint64_t total = 0;
+    HIPC(hipMemcpyAsync(&total, rptr + n, 8, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    const int64_t need = (int64_t)total * 4 + n * 8;  // entries + fill cursors
+    if (eb == 3) {
+        int64_t budget = p->mem_budget;
+        if (budget == 0) {
+            size_t fr = 0, tot = 0;
+            HIPC(hipMemGetInfo(&fr, &tot));
+            budget = (int64_t)(kDefaultBudgetFraction * (double)(fr + M.bytes));
+        }
+        gr->budget_bytes = budget;
+        gr->budget_need = (int64_t)M.bytes + need;
+        if ((int64_t)M.bytes + need > budget) {
+            M.release(cnt, (n + 1) * 4);
+            M.release(rptr, (n + 1) * 8);
+            M.release(tmp, nb * 8);
+            return GBF_OK;  // stays implicit
+        }
+    }
+    int32_t* rel;
+    unsigned long long* cursor;
+    if ((rc = M.alloc((void**)&rel, (size_t)total * 4)) || (rc = M.alloc((void**)&cursor, n * 8))) return rc;
+    HIPC(hipMemcpyAsync(cursor, rptr, n * 8, hipMemcpyDeviceToDevice, s));
+    HIPC(launch_rev_fill_box(I, cursor, rel, s));
+    HIPC(launch_sort_rows64(rptr, rel, n, s));
+    HIPC(hipStreamSynchronize(s));
+    M.release(cursor, n * 8);
+    M.release(cnt, (n + 1) * 4);
+    M.release(tmp, nb * 8);
+    I.rptr64 = rptr;
+    I.rrel = rel;
+    I.enc = 2;
+    gr->enc = 2;
+    gr->m = (int64_t)total;
+    return GBF_OK;
+}
+
 extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph** out) {
     if (!out) return fail(GBF_EINVAL, "out is NULL");
     *out = nullptr;
@@ -201,7 +329,13 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
     if (!p->G || !p->g) return fail(GBF_EINVAL, "G and g are required");
     if (p->g_edge && p->encoding != GBF_CSR) return fail(GBF_EINVAL, "per-edge costs need GBF_CSR");
     const int64_t n = p->n_states, K = p->n_inputs, np = n * K;
-    if (np >= (int64_t)1 << 31) return fail(GBF_EINVAL, "n_states * n_inputs must be < 2^31");
+    if (p->pair_ids64 != 0 && p->pair_ids64 != 1) return fail(GBF_EINVAL, "pair_ids64 must be 0 or 1");
+    // 64-bit pair ids: by request, or when the 32-bit ids would not reach
+    const bool wide = p->pair_ids64 == 1 || np >= ((int64_t)1 << 31);
+    if (wide && (p->encoding != GBF_BOX || p->expand_box == 1))
+        return fail(GBF_EINVAL, "64-bit pair ids (n_states * n_inputs >= 2^31, or pair_ids64) need GBF_BOX with "
+                                "expand_box 0, 2 or 3");
+    if (n >= ((int64_t)1 << 32) - 1) return fail(GBF_EINVAL, "n_states must be < 2^32 - 1");
     const hipMemcpyKind kind = p->memspace == GBF_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
 
     std::unique_ptr<gbf_graph> gr(new gbf_graph());
@@ -224,6 +358,8 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
     I.dtype = p->dtype;
     I.pair_base = 0;
     I.max_rounds = n;
+    I.wide = wide ? 1 : 0;
+    gr->wide = wide;
     for (int a = 0; a < 4; ++a) I.dims[a] = 1;
 
     int64_t m = 0;
@@ -308,9 +444,14 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
         return fail(GBF_EINVAL, msg);
     }
 
+    int eb = p->encoding == GBF_BOX ? p->expand_box : 0;
+    if (wide) {
+        if ((rc = load_wide(gr.get(), p, eb, err))) return rc;
+        *out = gr.release();
+        return GBF_OK;
+    }
     // expand_box 3: keep the predecessor images (HYB) if their peak at load
     // fits the memory budget, else stay implicit (BOX)
-    int eb = p->encoding == GBF_BOX ? p->expand_box : 0;
     if (eb == 3) {
         uint32_t* sizes;
         unsigned long long* tot64;
@@ -446,6 +587,7 @@ struct SolveOut {
     double solve_ms = 0, relax_ms = 0, barrier_ms = 0;
     int64_t relax_launches = 0;
     int mode = 0, grid = 0, block = 0, lanes = 0, graph = 0, sweeps = 0;
+    int switched = 0;  // bucket order: 1 = the work budget moved the rest of the solve to the plain order
     int32_t inst_status[kMaxBatch] = {};  // per instance: 1 = round cap reached with work left
 };
 
@@ -456,6 +598,12 @@ struct Plan {
     int64_t max_rounds = 0, max_states = 0;
     int enc_mask = 0, lanes = 4, mode = GBF_MODE_HOSTLOOP, grid = 0, dtype = 0;
     bool bucket = false;
+    bool wide = false;  // 64-bit pair ids
+    // bucket order: work budget (pair evaluations, rounds) after which the
+    // remaining rounds list every dirty pair, i.e. continue in plain order
+    int64_t budget_evals = INT64_MAX, budget_rounds = INT64_MAX;
+    const std::vector<int64_t>* ref_profile = nullptr;  // bucket order: plain profile to keep up with
+    std::vector<int64_t>* record = nullptr;             // plain order: per-round profile out
 };
 
 static int plan_solve(Scratch& S, const Inst* insts, int ninst, int dtype, const gbf_opts& o, int cus,
@@ -470,14 +618,24 @@ static int plan_solve(Scratch& S, const Inst* insts, int ninst, int dtype, const
         P.max_states = std::max<int64_t>(P.max_states, I.n);
         P.enc_mask |= I.enc == 0 ? (I.ge ? 8 : 1) : I.enc == 1 ? 2 : 4;
     }
+    P.wide = insts[0].wide != 0;
+    if (P.wide) {
+        // 64-bit pair ids: one instance, host loop, plain order
+        if (ninst != 1) return fail(GBF_EINVAL, "a problem with 64-bit pair ids is solved on its own, not in a batch");
+        if (o.order != GBF_ORDER_PLAIN) return fail(GBF_EINVAL, "64-bit pair ids use the plain order");
+        if (o.mode == GBF_MODE_PERSISTENT || o.mode == GBF_MODE_SINGLE_BLOCK)
+            return fail(GBF_EINVAL, "64-bit pair ids run in host-loop mode");
+    }
     const int nevents = o.profile ? 2 * (int)std::min<int64_t>(P.max_rounds + 2, 4096) + 2 : 4;
-    int rc = ensure_scratch(S, total_pairs, P.max_rounds, P.ninst, nevents);
+    int rc = ensure_scratch(S, total_pairs, P.max_rounds, P.ninst, nevents, P.wide ? 8 : 4);
     if (rc) return rc;
     Run& R = P.R;
     R.dirty[0] = S.dirty[0];
     R.dirty[1] = S.dirty[1];
-    R.list = S.list;
-    R.counts = S.counts;
+    R.list = P.wide ? nullptr : S.list;
+    R.counts = P.wide ? nullptr : S.counts;
+    R.list64 = P.wide ? reinterpret_cast<uint64_t*>(S.list) : nullptr;
+    R.counts64 = P.wide ? reinterpret_cast<unsigned long long*>(S.counts) : nullptr;
     R.ctr = S.ctr;
     R.slots = S.slots;
     R.inst_status = S.inst_status;
@@ -512,7 +670,7 @@ static int plan_solve(Scratch& S, const Inst* insts, int ninst, int dtype, const
     P.lanes = (o.lanes == 1 || o.lanes == 2 || o.lanes == 4 || o.lanes == 8 || o.lanes == 16 || o.lanes == 32)
                   ? o.lanes
                   : 4;
-    P.mode = P.bucket ? GBF_MODE_HOSTLOOP : o.mode;
+    P.mode = (P.bucket || P.wide) ? GBF_MODE_HOSTLOOP : o.mode;
     if (P.mode == GBF_MODE_SINGLE_BLOCK && P.ninst != 1)
         return fail(GBF_EINVAL, "single-block mode solves one instance");
     if (P.mode == GBF_MODE_AUTO && P.ninst == 1 && total_pairs <= kSingleBlockMaxPairs)
@@ -528,11 +686,11 @@ static int plan_solve(Scratch& S, const Inst* insts, int ninst, int dtype, const
             P.mode = GBF_MODE_HOSTLOOP;
         } else {
             if (P.mode == GBF_MODE_AUTO) {
-                // measured on MI355X: one launch pair per round beats the
-                // cooperative kernel for single instances and for batches
-                // (every grid barrier writes back and invalidates the L2 of
-                // each XCD, once per block); the persistent form is kept for
-                // callers that want one graph-capturable launch
+                // measured on MI355X: one launch pair per round is as fast as
+                // the cooperative kernel on single CSR instances and faster
+                // on box instances (whose round kernel runs one block per
+                // CU); the persistent form serves callers that want one
+                // graph-capturable launch, and the autotuner times both
                 P.mode = GBF_MODE_HOSTLOOP;
             }
             // co-residency is required; stay below the occupancy limit
@@ -549,7 +707,8 @@ static int enqueue_init(Scratch& S, const Plan& P, const Inst* insts, hipStream_
     const Run& R = P.R;
     HIPC(launch_fill_u32((uint32_t*)R.dirty[0], 0, R.nchunks * 4, s));
     HIPC(launch_fill_u32((uint32_t*)R.dirty[1], 0, R.nchunks * 4, s));
-    HIPC(launch_fill_u32(R.counts, 0, P.max_rounds + 2, s));
+    HIPC(launch_fill_u32(P.wide ? reinterpret_cast<uint32_t*>(R.counts64) : R.counts, 0,
+                         (P.max_rounds + 2) * (P.wide ? 2 : 1), s));
     HIPC(launch_fill_u32((uint32_t*)R.ctr, 0, 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.slots, 0, (int64_t)kMaxGrid * 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.inst_status, 0, P.ninst, s));
@@ -558,7 +717,7 @@ static int enqueue_init(Scratch& S, const Plan& P, const Inst* insts, hipStream_
     HIPC(launch_fill_u32((uint32_t*)R.result, 0, 16, s));
     if (P.bucket) HIPC(launch_fill_u32((uint32_t*)R.occ, 0, 65536 / 4, s));
     for (int i = 0; i < P.ninst; ++i) HIPC(launch_init(S.dinst, insts[i], P.dtype, s));
-    HIPC(launch_seed(S.dinst, P.ninst, R, P.max_states, P.dtype, P.enc_mask, s));
+    HIPC(launch_seed(S.dinst, P.ninst, R, P.max_states, P.dtype, P.enc_mask, s, P.wide));
     return GBF_OK;
 }
 
@@ -598,36 +757,58 @@ static void read_host(const Scratch& S, const Plan& P, SolveOut& out, bool round
 // frontier sizes after each batch of rounds (rounds launched after the
 // frontier drained exit at once).
 static int enqueue_hostloop(Scratch& S, const Plan& P, const gbf_opts& o, hipStream_t s, SolveOut& out) {
-    const Run& R = P.R;
+    Run R = P.R;
     int32_t* host = (int32_t*)S.host;
     int64_t r = 0;
     int64_t batch = o.batch_hint > 0 ? o.batch_hint : 8;
     int ev = 2;
     bool done = false;
+    int64_t evals = 0;  // pairs listed so far (bucket order's work budget)
     // the round after the last allowed one only flags capped instances, so a
     // zero count appears at round max_rounds + 1 at the latest
     while (!done && r <= P.max_rounds + 1) {
         const int64_t nb = std::min<int64_t>(batch, P.max_rounds + 2 - r);
+        bool behind = false;
+        if (P.bucket && P.ref_profile && !P.ref_profile->empty() && r >= kProgressRound) {
+            const auto& pr = *P.ref_profile;
+            const int64_t ref = pr[(size_t)std::min<int64_t>(r - 1, (int64_t)pr.size() - 1)];
+            behind = (double)evals < kProgressFactor * (double)ref;
+        }
+        if (P.bucket && !out.switched && (behind || evals > P.budget_evals || r + nb > P.budget_rounds)) {
+            // over budget: every later round lists all dirty pairs (a
+            // window over every bucket), which is the plain order continued
+            // from the current iterate; any order reaches the same fixed
+            // point, so only the work changes
+            R.bspan = kBucketsAll;
+            out.switched = 1;
+        }
         for (int64_t k = 0; k < nb; ++k) {
             if (P.bucket) HIPC(launch_bucket_compact(R, (int)(r + k), 0, s));
-            else HIPC(launch_compact(R, (int)(r + k), 0, s));
+            else HIPC(launch_compact(R, (int)(r + k), 0, s, P.wide));
             const bool timed = o.profile && ev + 1 < (int)S.events.size();
             if (timed) HIPC(hipEventRecord(S.events[ev], s));
-            HIPC(launch_relax(S.dinst, R, (int)(r + k), P.grid, P.lanes, P.dtype, P.enc_mask, s));
+            HIPC(launch_relax(S.dinst, R, (int)(r + k), P.grid, P.lanes, P.dtype, P.enc_mask, s, P.wide));
             if (timed) {
                 HIPC(hipEventRecord(S.events[ev + 1], s));
                 ev += 2;
             }
         }
         const int64_t nread = std::min<int64_t>(nb, 1000);
-        HIPC(hipMemcpyAsync(host + 256, R.counts + r, nread * 4, hipMemcpyDeviceToHost, s));
+        if (P.wide) HIPC(hipMemcpyAsync(host + 256, R.counts64 + r, nread * 8, hipMemcpyDeviceToHost, s));
+        else HIPC(hipMemcpyAsync(host + 256, R.counts + r, nread * 4, hipMemcpyDeviceToHost, s));
         HIPC(hipStreamSynchronize(s));
-        for (int64_t k = 0; k < nread; ++k)
-            if (host[256 + k] == 0) {
+        for (int64_t k = 0; k < nread; ++k) {
+            uint64_t c;
+            if (P.wide) std::memcpy(&c, host + 256 + 2 * k, 8);
+            else c = (uint32_t)host[256 + k];
+            if (c == 0) {
                 out.rounds = r + k;
                 done = true;
                 break;
             }
+            evals += (int64_t)c;
+            if (P.record && (int64_t)P.record->size() == r + k) P.record->push_back(evals);
+        }
         r += nb;
         // speculative rounds after the frontier drains cost a launch each,
         // host reads a round trip: grow the batch moderately
@@ -647,10 +828,16 @@ static int enqueue_hostloop(Scratch& S, const Plan& P, const gbf_opts& o, hipStr
 
 // Runs one solve over `insts`, not captured.
 static int run_rounds(Scratch& S, const Inst* insts, int ninst, int dtype, const gbf_opts& o, hipStream_t s,
-                      int cus, int clock_khz, SolveOut& out) {
+                      int cus, int clock_khz, SolveOut& out, int64_t budget_evals = INT64_MAX,
+                      int64_t budget_rounds = INT64_MAX, const std::vector<int64_t>* ref_profile = nullptr,
+                      std::vector<int64_t>* record = nullptr) {
     Plan P;
     int rc = plan_solve(S, insts, ninst, dtype, o, cus, clock_khz, P);
     if (rc) return rc;
+    P.budget_evals = budget_evals;
+    P.budget_rounds = budget_rounds;
+    P.ref_profile = ref_profile;
+    P.record = record;
     if (!S.events.empty()) HIPC(hipEventRecord(S.events[0], s));
     HIPC(hipMemcpyAsync(S.dinst, insts, sizeof(Inst) * P.ninst, hipMemcpyHostToDevice, s));
     if ((rc = enqueue_init(S, P, insts, s))) return rc;
@@ -681,7 +868,8 @@ static int run_rounds(Scratch& S, const Inst* insts, int ninst, int dtype, const
                 gbf_opts o2 = o;
                 o2.mode = GBF_MODE_HOSTLOOP;
                 out = SolveOut();
-                return run_rounds(S, insts, ninst, dtype, o2, s, cus, clock_khz, out);
+                return run_rounds(S, insts, ninst, dtype, o2, s, cus, clock_khz, out, budget_evals, budget_rounds,
+                                  ref_profile, record);
             }
             return fail(GBF_ETIMEOUT, "grid barrier timed out (blocks not co-resident?)");
         }
@@ -764,13 +952,31 @@ extern "C" int gbf_solve(gbf_graph* g, const gbf_opts* opts, void* V_out, gbf_st
         if (rc) return rc;
         I.key = o.bucket_key;
         I.occ = g->scratch.occ;
-        I.max_rounds += 65536;
+        I.max_rounds += kBucketRounds;
     }
+    // bucket order: the work budget, from the handle's last plain solve
+    int64_t budget_evals = INT64_MAX, budget_rounds = INT64_MAX;
+    if (bucket && o.bucket_budget < -1) return fail(GBF_EINVAL, "bucket_budget must be >= -1");
+    if (bucket && o.bucket_budget != -1) {
+        const double pct = (o.bucket_budget == 0 ? 100.0 : (double)o.bucket_budget) / 100.0;
+        budget_evals = (int64_t)(pct * (g->ref_evals > 0 ? kBucketEvalFactor * (double)g->ref_evals
+                                                         : (double)(kBucketEvalsPerPair * g->n * g->K)));
+        budget_rounds = kBucketRounds;
+        if (g->ref_rounds > 0)
+            budget_rounds =
+                std::min<int64_t>(budget_rounds, (int64_t)(pct * kBucketRoundFactor * (double)g->ref_rounds) + 1);
+    }
+    // the switch to the plain order comes by round kBucketRounds at the
+    // latest, so the continuation keeps at least the plain cap
+    if (bucket) budget_rounds = std::min<int64_t>(budget_rounds, kBucketRounds);
     const Inst insts[1] = {I};
     SolveOut so;
-    int rc = run_rounds(g->scratch, insts, 1, g->dtype, o, s, g->cus, g->clock_khz, so);
+    std::vector<int64_t> profile;
+    const bool use_ref = bucket && o.bucket_budget != -1 && !g->ref_profile.empty();
+    int rc = run_rounds(g->scratch, insts, 1, g->dtype, o, s, g->cus, g->clock_khz, so, budget_evals, budget_rounds,
+                        use_ref ? &g->ref_profile : nullptr, bucket ? nullptr : &profile);
     if (rc) return rc;
-    int fallback = 0;
+    int fallback = so.switched ? 1 : 0;
     if (bucket && so.inst_status[0]) {
         gbf_opts o2 = o;
         o2.order = GBF_ORDER_PLAIN;
@@ -779,7 +985,7 @@ extern "C" int gbf_solve(gbf_graph* g, const gbf_opts* opts, void* V_out, gbf_st
         rc = gbf_solve(g, &o2, V_out, &st2);
         if (st) {
             *st = st2;
-            st->fallback = 1;
+            st->fallback = 2;
         }
         return rc;
     }
@@ -793,6 +999,11 @@ extern "C" int gbf_solve(gbf_graph* g, const gbf_opts* opts, void* V_out, gbf_st
     fill_stats(st, status, so, I.max_rounds, g->mem.bytes + g->scratch.mem.bytes, g->enc);
     if (st) st->fallback = fallback;
     g->solved = true;
+    if (!bucket && status == GBF_OK) {
+        g->ref_evals = (int64_t)so.ctr[0];
+        g->ref_rounds = so.rounds;
+        g->ref_profile.swap(profile);  // empty unless the solve ran in host-loop mode
+    }
     if (status != GBF_OK) fail(status, "round cap reached with a non-empty frontier");
     return status;
 }
@@ -855,6 +1066,7 @@ extern "C" int gbf_solve_noalloc(gbf_graph* g, const gbf_opts* opts, void* V_out
     const auto t0 = std::chrono::steady_clock::now();
     if (!g) return fail(GBF_EINVAL, "graph is NULL");
     gbf_opts o = opts ? *opts : default_opts();
+    if (g->wide) return fail(GBF_EINVAL, "the no-allocation solve takes 32-bit pair ids only");
     if (o.order != GBF_ORDER_PLAIN) return fail(GBF_EINVAL, "the no-allocation solve uses the plain order");
     if (o.v_memspace != GBF_HOST && o.v_memspace != GBF_DEVICE) return fail(GBF_EINVAL, "bad v_memspace");
     o.profile = 0;  // per-launch timing needs events, which are allocated

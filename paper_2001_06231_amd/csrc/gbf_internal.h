@@ -22,6 +22,8 @@ struct Inst {
     const uint8_t* avoid;   // [n]
     void* V;                // value words [n] (int32 or fp32 key)
     const int32_t* win;     // BOX: per input 8 ints: min (lo-x) per axis, max (hi-x) per axis
+    const uint64_t* rptr64; // 64-bit pair ids: reverse CSR row pointers [n+1]
+    const int32_t* rrel;    // 64-bit pair ids: reverse CSR entries, pair id minus y*K of row y
     const uint16_t* key;    // bucket order: bucket key of each state [n], else NULL
     uint8_t* occ;           // bucket order: occupancy flag per bucket [65536]
     int64_t n;
@@ -33,6 +35,7 @@ struct Inst {
     int32_t strides[4];
     int32_t index;          // position in the batch
     int32_t dtype;          // 0 int32, 1 fp32
+    int32_t wide;           // 1 = 64-bit pair ids (Run.list64 / counts64; HYB: rptr64 / rrel)
 };
 
 // Device-side solver state shared by all instances of one solve.
@@ -40,6 +43,8 @@ struct Run {
     uint8_t* dirty[2];          // dirty-pair byte maps (frontiers F1 / F2), 1 = pair is dirty
     uint32_t* list;             // compacted frontier (global pair ids)
     uint32_t* counts;           // frontier size per round [max_rounds + 2]
+    uint64_t* list64;           // 64-bit pair ids: compacted frontier
+    unsigned long long* counts64;  // 64-bit pair ids: frontier size per round
     unsigned long long* ctr;    // [8]: pair evals, edges, improvements, saturations, expansions, marks
     unsigned long long* slots;  // per-block statistics [kMaxGrid * 8]
     int32_t* inst_status;       // per instance: 1 = cap reached with work left
@@ -80,15 +85,18 @@ hipError_t launch_box_sizes(const Inst& I, uint32_t* sizes, unsigned long long* 
 hipError_t launch_box_fill(const Inst& I, const uint32_t* sptr, int32_t* sidx, hipStream_t s);
 
 hipError_t launch_init(const Inst* dI, const Inst& I, int dtype, hipStream_t s);
+// `wide`: 64-bit pair ids (one instance, host loop, BOX or HYB encoding):
+// the list and counts are R.list64 / R.counts64, the reverse CSR of HYB is
+// rptr64 / rrel
 hipError_t launch_seed(const Inst* dI, int ninst, const Run& R, int64_t max_states, int dtype, int enc_mask,
-                       hipStream_t s);
-hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s);
+                       hipStream_t s, bool wide = false);
+hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s, bool wide = false);
 // bucket order: bucket selection + compaction of the selected pairs (one
 // byte map, R.dirty[0] == R.dirty[1])
 hipError_t launch_bucket_compact(const Run& R, int round, int grid, hipStream_t s);
 // `lanes`: lanes per listed pair in the relax step (4, 8, 16 or 32)
 hipError_t launch_relax(const Inst* dI, const Run& R, int round, int grid, int lanes, int dtype, int enc_mask,
-                        hipStream_t s);
+                        hipStream_t s, bool wide = false);
 // `attr_launch`: launch through hipLaunchKernelExC with the cooperative
 // attribute (the form that stream capture records as a graph node)
 hipError_t launch_persistent(const Inst* dI, const Run& R, int grid, int lanes, int dtype, int enc_mask,
@@ -99,6 +107,12 @@ hipError_t launch_single(const Inst* dI, const Run& R, int lanes, int dtype, int
                          hipStream_t s);
 hipError_t launch_sum_slots(const unsigned long long* slots, int nslots, unsigned long long* ctr, hipStream_t s);
 hipError_t launch_sort_rows(const uint32_t* rptr, uint32_t* rev, int64_t n, hipStream_t s);
+// 64-bit pair ids, HYB: the reverse CSR built straight from the boxes
+// (counts per state, a 64-bit scan, relative entries, rows sorted)
+hipError_t launch_rev_count_box(const Inst& I, uint32_t* cnt, hipStream_t s);
+hipError_t launch_scan64(const uint32_t* in, uint64_t* out, int64_t n, uint64_t* tmp, hipStream_t s);
+hipError_t launch_rev_fill_box(const Inst& I, unsigned long long* cursor, int32_t* rel, hipStream_t s);
+hipError_t launch_sort_rows64(const uint64_t* rptr, int32_t* rel, int64_t n, hipStream_t s);
 hipError_t launch_decode(const Inst& I, int dtype, void* out, hipStream_t s);
 hipError_t launch_policy(const Inst& I, int dtype, int32_t* pol, unsigned long long* bad, hipStream_t s);
 

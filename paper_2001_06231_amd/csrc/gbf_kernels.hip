@@ -85,6 +85,25 @@ constexpr int kCtrSlot = 8;
 
 constexpr int kMaxWavesPerBlock = 16;
 
+// Pair-id width.  32-bit ids serve every workload below 2^31 pairs (and
+// batches below 2^32); one instance with more pairs runs with 64-bit ids
+// (host loop, BOX or HYB encoding): its frontier list and per-round counts
+// are R.list64 / R.counts64.
+template <bool WIDE>
+struct Ids {
+    using id_t = uint32_t;
+    using cnt_t = uint32_t;
+    __device__ static __forceinline__ id_t* list(const Run& R) { return R.list; }
+    __device__ static __forceinline__ cnt_t* counts(const Run& R) { return R.counts; }
+};
+template <>
+struct Ids<true> {
+    using id_t = uint64_t;
+    using cnt_t = unsigned long long;
+    __device__ static __forceinline__ id_t* list(const Run& R) { return R.list64; }
+    __device__ static __forceinline__ cnt_t* counts(const Run& R) { return R.counts64; }
+};
+
 struct AccLds {
     unsigned long long v[kMaxWavesPerBlock][6];
 };
@@ -435,8 +454,18 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* t
 // pred(y,u) is contained in { x : y_a - hi_off <= x_a <= y_a - lo_off }, a
 // superset of pred (Sect. V-B allows pred to be replaced by a superset);
 // candidates are filtered exactly by decoding their box.
-__global__ void k_box_window(Inst I, int dtype, int32_t* win) {
+// The window table of up to kWinLds inputs is reduced in LDS first (one
+// global atomic per entry and block instead of eight per pair).
+constexpr int kWinLds = 512;
+__global__ __launch_bounds__(256) void k_box_window(Inst I, int dtype, int32_t* win) {
+    __shared__ int32_t s_win[kWinLds * 8];
     const int64_t npairs = I.n * I.K;
+    const bool lds = I.K <= kWinLds;
+    if (lds) {
+        for (int i = threadIdx.x; i < I.K * 8; i += blockDim.x) s_win[i] = (i & 4) ? (int32_t)0x80000000 : 0x7fffffff;
+        __syncthreads();
+    }
+    int32_t* w = lds ? s_win : win;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npairs; p += (int64_t)gridDim.x * blockDim.x) {
         if (!pair_live(I, p, dtype)) continue;
         const int u = (int)(p % I.K);
@@ -448,14 +477,25 @@ __global__ void k_box_window(Inst I, int dtype, int32_t* win) {
             int lc = (int)(lo % I.dims[a]);
             x /= I.dims[a];
             lo /= I.dims[a];
-            atomicMin(win + u * 8 + a, lc - xc);
-            atomicMax(win + u * 8 + 4 + a, lc + d.e[a] - xc);
+            atomicMin(w + u * 8 + a, lc - xc);
+            atomicMax(w + u * 8 + 4 + a, lc + d.e[a] - xc);
+        }
+    }
+    if (lds) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < I.K * 8; i += blockDim.x) {
+            const int32_t v = s_win[i];
+            if (i & 4) {
+                if (v != (int32_t)0x80000000) atomicMax(win + i, v);
+            } else if (v != 0x7fffffff) {
+                atomicMin(win + i, v);
+            }
         }
     }
 }
 
 hipError_t launch_box_window(const Inst& I, int32_t* win32, hipStream_t s) {
-    k_box_window<<<grid_for(I.n * I.K, 256), 256, 0, s>>>(I, I.dtype, win32);
+    k_box_window<<<grid_for(I.n * I.K, 256, 4096), 256, 0, s>>>(I, I.dtype, win32);
     return hipGetLastError();
 }
 
@@ -499,6 +539,159 @@ hipError_t launch_box_fill(const Inst& I, const uint32_t* sptr, int32_t* sidx, h
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ loader, 64-bit pair ids
+// HYB with 64-bit pair ids: the reverse CSR is built straight from the boxes
+// (no temporary successor lists).  Each live pair visits the cells of its
+// box; pass 1 counts the in-degree of every state, a 64-bit scan gives the
+// row pointers, pass 2 writes each predecessor pair as its id minus y*K
+// (a small signed offset: the loader checks that the predecessor windows
+// keep it within int32), and the rows are sorted ascending.
+template <class F>
+__device__ __forceinline__ void for_box_cells(const Inst& I, uint64_t bx, F f) {
+    const BoxDec d = decode_box(bx);
+    for (int j3 = 0; j3 <= d.e[3]; ++j3)
+        for (int j2 = 0; j2 <= d.e[2]; ++j2)
+            for (int j1 = 0; j1 <= d.e[1]; ++j1) {
+                const int64_t r0 =
+                    d.lo + (int64_t)j1 * I.strides[1] + (int64_t)j2 * I.strides[2] + (int64_t)j3 * I.strides[3];
+                for (int j0 = 0; j0 <= d.e[0]; ++j0) f(r0 + j0);
+            }
+}
+
+__global__ void k_rev_count_box(Inst I, int dtype, uint32_t* cnt) {
+    const int64_t npairs = I.n * I.K;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npairs; p += (int64_t)gridDim.x * blockDim.x) {
+        if (!pair_live(I, p, dtype)) continue;
+        for_box_cells(I, I.box[p], [&](int64_t y) { atomicAdd(cnt + y, 1u); });
+    }
+}
+
+hipError_t launch_rev_count_box(const Inst& I, uint32_t* cnt, hipStream_t s) {
+    k_rev_count_box<<<grid_for(I.n * I.K, 256), 256, 0, s>>>(I, I.dtype, cnt);
+    return hipGetLastError();
+}
+
+__global__ void k_rev_fill_box(Inst I, int dtype, unsigned long long* cursor, int32_t* rel) {
+    const int64_t npairs = I.n * I.K;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npairs; p += (int64_t)gridDim.x * blockDim.x) {
+        if (!pair_live(I, p, dtype)) continue;
+        for_box_cells(I, I.box[p], [&](int64_t y) {
+            const unsigned long long pos = atomicAdd(cursor + y, 1ull);
+            rel[pos] = (int32_t)(p - y * I.K);
+        });
+    }
+}
+
+hipError_t launch_rev_fill_box(const Inst& I, unsigned long long* cursor, int32_t* rel, hipStream_t s) {
+    k_rev_fill_box<<<grid_for(I.n * I.K, 256), 256, 0, s>>>(I, I.dtype, cursor, rel);
+    return hipGetLastError();
+}
+
+// Exclusive scan of n uint32 into uint64 out[0..n] (out[n] = total).
+__global__ void k_scan64_local(const uint32_t* in, uint64_t* out, int64_t n, uint64_t* blocksum) {
+    __shared__ uint64_t s[1024 / kWave];
+    const int64_t i = blockIdx.x * (int64_t)1024 + threadIdx.x;
+    const uint64_t v = i < n ? in[i] : 0u;
+    uint64_t incl = v;
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t t = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += t;
+    }
+    const int w = threadIdx.x / kWave;
+    if (lane == kWave - 1) s[w] = incl;
+    __syncthreads();
+    uint64_t wofs = 0;
+    for (int k = 0; k < w; ++k) wofs += s[k];
+    const uint64_t excl = wofs + incl - v;
+    if (i < n) out[i] = excl;
+    if (threadIdx.x == 1023) blocksum[blockIdx.x] = excl + v;
+}
+
+__global__ void k_scan64_blocks(uint64_t* blocksum, int64_t nb) {
+    __shared__ uint64_t s[1024 / kWave];
+    __shared__ uint64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int lane = lane_id();
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const uint64_t v = i < nb ? blocksum[i] : 0u;
+        uint64_t incl = v;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint64_t t = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += t;
+        }
+        const int w = threadIdx.x / kWave;
+        if (lane == kWave - 1) s[w] = incl;
+        __syncthreads();
+        uint64_t wofs = 0;
+        for (int k = 0; k < w; ++k) wofs += s[k];
+        const uint64_t excl = carry + wofs + incl - v;
+        if (i < nb) blocksum[i] = excl;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = excl + v;
+        __syncthreads();
+    }
+}
+
+__global__ void k_scan64_add(uint64_t* out, int64_t n, const uint64_t* blocksum, const uint32_t* in) {
+    const int64_t i = blockIdx.x * (int64_t)1024 + threadIdx.x;
+    if (i < n) out[i] += blocksum[blockIdx.x];
+    if (i == n - 1) out[n] = out[i] + in[i];
+}
+
+hipError_t launch_scan64(const uint32_t* in, uint64_t* out, int64_t n, uint64_t* tmp, hipStream_t s) {
+    const int64_t nb = (n + 1023) / 1024;
+    k_scan64_local<<<(unsigned)nb, 1024, 0, s>>>(in, out, n, tmp);
+    k_scan64_blocks<<<1, 1024, 0, s>>>(tmp, nb);
+    k_scan64_add<<<(unsigned)nb, 1024, 0, s>>>(out, n, tmp, in);
+    return hipGetLastError();
+}
+
+// Sorts every 64-bit-indexed reverse row ascending (as k_sort_rows).
+__global__ __launch_bounds__(kBlock) void k_sort_rows64(const uint64_t* __restrict__ rptr, int32_t* __restrict__ rel,
+                                                       int64_t n) {
+    __shared__ int32_t buf[kWavesPerBlock][kSortCap];
+    int32_t* B = buf[threadIdx.x / kWave];
+    const int lane = lane_id();
+    for (int64_t row = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave; row < n;
+         row += (int64_t)gridDim.x * kWavesPerBlock) {
+        const uint64_t s0 = rptr[row];
+        const uint64_t len = rptr[row + 1] - s0;
+        if (len <= 1 || len > (uint64_t)kSortCap) continue;
+        uint32_t np2 = 2;
+        while (np2 < len) np2 <<= 1;
+        for (uint32_t i = lane; i < np2; i += kWave) B[i] = i < len ? rel[s0 + i] : 0x7fffffff;
+        wave_sync();
+        for (uint32_t k = 2; k <= np2; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t i = lane; i < np2; i += kWave) {
+                    const uint32_t ixj = i ^ j;
+                    if (ixj > i) {
+                        const int32_t a = B[i], b = B[ixj];
+                        const bool asc = (i & k) == 0;
+                        if ((a > b) == asc) {
+                            B[i] = b;
+                            B[ixj] = a;
+                        }
+                    }
+                }
+                wave_sync();
+            }
+        }
+        for (uint32_t i = lane; i < len; i += kWave) rel[s0 + i] = B[i];
+        wave_sync();
+    }
+}
+
+hipError_t launch_sort_rows64(const uint64_t* rptr, int32_t* rel, int64_t n, hipStream_t s) {
+    k_sort_rows64<<<grid_for((n + kWavesPerBlock - 1) / kWavesPerBlock, 1, 4096), kBlock, 0, s>>>(rptr, rel, n);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ init
 // W <- G (Algorithm 1 initialisation), avoid cells pinned to INF.
 template <class T>
@@ -524,13 +717,13 @@ hipError_t launch_init(const Inst* dI, const Inst& I, int dtype, hipStream_t s) 
 // marked (a stale read only misses marks, never invents them).
 // Bucket order: the first mark of a pair also flags its state's bucket as
 // occupied (another idempotent byte store).
-__device__ __forceinline__ void mark_pair(const Inst& I, uint8_t* __restrict__ dirty, uint32_t base, uint32_t q,
-                                          bool valid) {
+template <class IdT>
+__device__ __forceinline__ void mark_pair(const Inst& I, uint8_t* __restrict__ dirty, IdT base, IdT q, bool valid) {
     if (valid) {
         GBF_GLOBAL uint8_t* b = gp(dirty) + base + q;
         if (*b == 0) {
             *b = 1;
-            if (I.key) gp(I.occ)[gp(I.key)[q / (uint32_t)I.K]] = 1;
+            if (I.key) gp(I.occ)[gp(I.key)[q / (IdT)I.K]] = 1;
         }
     }
 }
@@ -558,10 +751,40 @@ constexpr bool kMayEdge = ENC == 5 || ENC == 3;
 // pair (x',u') with y in F(x',u') is marked.  CSR: the (sorted) reverse row
 // of y is streamed by the wave.  BOX: for every input the predecessor
 // window is streamed and each candidate's box is decoded to filter it.
-template <int ENC>
+template <int ENC, bool WIDE = false>
 __device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint8_t* __restrict__ dirty, Acc& acc) {
+    using Id = typename Ids<WIDE>::id_t;
     const int lane = lane_id();
-    const uint32_t base = (uint32_t)I.pair_base;
+    const Id base = (Id)I.pair_base;
+    if (WIDE && rev_csr<ENC>(I)) {
+        // 64-bit reverse rows hold each predecessor pair as its id minus y*K
+        const GBF_GLOBAL uint64_t* rptr = gp(I.rptr64);
+        const GBF_GLOBAL int32_t* rel = gp(I.rrel);
+        const uint64_t s0 = rptr[y];
+        const uint32_t len = (uint32_t)(rptr[y + 1] - s0);
+        const int64_t yK = y * (int64_t)I.K;
+        if (lane == 0) {
+            acc.expanded += 1;
+            acc.marks += len;
+        }
+        for (uint32_t t0 = 0; t0 < len; t0 += kWave * kExpBatch) {
+            Id q[kExpBatch];
+            bool v[kExpBatch];
+#pragma unroll
+            for (int k = 0; k < kExpBatch; ++k) {
+                const uint32_t t = t0 + (uint32_t)(k * kWave + lane);
+                v[k] = t < len;
+                q[k] = v[k] ? (Id)(yK + (int64_t)ldx<GBF_NT_MISC>(rel + s0 + t)) : (Id)0;
+            }
+            uint8_t b[kExpBatch];
+#pragma unroll
+            for (int k = 0; k < kExpBatch; ++k) b[k] = v[k] ? gp(dirty)[base + q[k]] : (uint8_t)1;
+#pragma unroll
+            for (int k = 0; k < kExpBatch; ++k)
+                if (b[k] == 0) gp(dirty)[base + q[k]] = 1;
+        }
+        return;
+    }
     if (rev_csr<ENC>(I)) {
         const GBF_GLOBAL uint32_t* rptr = gp(I.rptr);
         const GBF_GLOBAL uint32_t* rev = gp(I.rev);
@@ -619,7 +842,7 @@ __device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint8_t* 
         for (uint32_t t0 = 0; t0 < total; t0 += kWave) {
             const uint32_t t = t0 + (uint32_t)lane;
             bool hit = false;
-            uint32_t q = 0;
+            Id q = 0;
             if (t < total) {
                 uint32_t rr = t;
                 const int c0 = (int)(rr % (uint32_t)sz[0]);
@@ -642,10 +865,10 @@ __device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint8_t* 
                         in &= (yc[a] >= lc) && (yc[a] <= lc + d.e[a]);
                     }
                     hit = in;
-                    q = (uint32_t)qq;
+                    q = (Id)qq;
                 }
             }
-            mark_pair(I, dirty, base, q, hit);
+            mark_pair<Id>(I, dirty, base, q, hit);
         }
     }
 }
@@ -653,7 +876,7 @@ __device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint8_t* 
 // Seed: F1 <- union of pred(y) over states with G(y) < INF (Algorithm 1
 // initialisation), at pair level.  Each wave looks at 64 states and expands
 // the targets among them one after the other.
-template <class T, int ENC>
+template <class T, int ENC, bool WIDE = false>
 __global__ __launch_bounds__(kBlock) void k_seed(const Inst* __restrict__ It, int ninst, Run R) {
     Acc acc;
     for (int ii = 0; ii < ninst; ++ii) {
@@ -668,7 +891,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(const Inst* __restrict__ It, in
             while (bal) {
                 const int l = __ffsll(bal) - 1;
                 bal &= bal - 1;
-                expand_state<ENC>(I, w * kWave + l, R.dirty[0], acc);
+                expand_state<ENC, WIDE>(I, w * kWave + l, R.dirty[0], acc);
             }
         }
     }
@@ -813,12 +1036,15 @@ __device__ __forceinline__ uint32_t chunk_select(const uint32_t v4[4], int64_t c
 // block reserves their slots (device-scope atomics serialise at the memory
 // side, so the grid is kept small); pass 2 re-reads the chunks, now in L2,
 // and writes the ids in ascending order, clearing the listed bytes.
-template <bool BK>
+template <bool BK, bool WIDE = false>
 __device__ __forceinline__ void compact_range(uint8_t* __restrict__ dirty, int64_t nchunks, int64_t t0, int64_t t1,
-                                              uint32_t* __restrict__ list, uint32_t* cnt, const BucketSel& bs) {
+                                              typename Ids<WIDE>::id_t* __restrict__ list,
+                                              typename Ids<WIDE>::cnt_t* cnt, const BucketSel& bs) {
+    using Id = typename Ids<WIDE>::id_t;
+    using Cnt = typename Ids<WIDE>::cnt_t;
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     __shared__ int s_w[kWavesPerBlock];
-    __shared__ uint32_t s_base;
+    __shared__ Cnt s_base;
     const int t = threadIdx.x;
     const int w = t / kWave;
     GBF_GLOBAL u32x4* chunks = reinterpret_cast<GBF_GLOBAL u32x4*>(gp(dirty));
@@ -840,10 +1066,10 @@ __device__ __forceinline__ void compact_range(uint8_t* __restrict__ dirty, int64
 #pragma unroll
     for (int k = 0; k < kWavesPerBlock; ++k) total += s_w[k];
     if (total == 0) return;  // block-uniform
-    if (t == 0) s_base = atomicAdd(cnt, (uint32_t)total);
+    if (t == 0) s_base = atomicAdd(cnt, (Cnt)total);
     __syncthreads();
-    uint32_t off = s_base;
-    GBF_GLOBAL uint32_t* out = gp(list);
+    Id off = (Id)s_base;
+    GBF_GLOBAL Id* out = gp(list);
     for (int64_t tile = t0; tile < t1; ++tile) {
         const int64_t ci = tile * kBlock + t;
         uint32_t m = 0, keep = 0;
@@ -873,27 +1099,29 @@ __device__ __forceinline__ void compact_range(uint8_t* __restrict__ dirty, int64
                 rest.w = spread_bytes4(keep >> 12);
             }
             chunks[ci] = rest;
-            uint32_t pos = off + (uint32_t)(wofs + incl - cc);
-            const uint32_t pbase = (uint32_t)(ci * 16);
+            Id pos = off + (Id)(wofs + incl - cc);
+            const Id pbase = (Id)(ci * 16);
             while (m) {
                 const int b = __ffs(m) - 1;
-                out[pos++] = pbase + (uint32_t)b;
+                out[pos++] = pbase + (Id)b;
                 m &= m - 1u;
             }
         }
-        off += (uint32_t)tot;
+        off += (Id)tot;
     }
 }
 
 constexpr int kCompactGrid = GBF_COMPACT_GRID;
 
+template <bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_compact(Run R, int round) {
-    if (round > 0 && R.counts[round - 1] == 0) return;  // frontier already empty
+    auto* counts = Ids<WIDE>::counts(R);
+    if (round > 0 && counts[round - 1] == 0) return;  // frontier already empty
     const int64_t ntiles = (R.nchunks + kBlock - 1) / kBlock;
     const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
     const int64_t t0 = blockIdx.x * per, t1 = min(ntiles, t0 + per);
-    compact_range<false>(R.dirty[round & 1], R.nchunks, t0, t1, R.list, R.counts + round,
-                         BucketSel{nullptr, 0u, 0u, 1u});
+    compact_range<false, WIDE>(R.dirty[round & 1], R.nchunks, t0, t1, Ids<WIDE>::list(R), counts + round,
+                               BucketSel{nullptr, 0u, 0u, 1u});
 }
 
 // Bucket order, one round: picks the range of buckets [lo, hi] whose dirty
@@ -985,11 +1213,12 @@ hipError_t launch_bucket_compact(const Run& R, int round, int grid, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s) {
+hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s, bool wide) {
     const int64_t ntiles = (R.nchunks + kBlock - 1) / kBlock;
     int g = (int)std::min<int64_t>(ntiles, grid > 0 ? grid : kCompactGrid);
     if (g < 1) g = 1;
-    k_compact<<<g, kBlock, 0, s>>>(R, round);
+    if (wide) k_compact<true><<<g, kBlock, 0, s>>>(R, round);
+    else k_compact<false><<<g, kBlock, 0, s>>>(R, round);
     return hipGetLastError();
 }
 
@@ -1014,24 +1243,29 @@ __device__ __forceinline__ typename T::wide_t group_wmax(typename T::wide_t v) {
 }
 
 // Per-lane view of the listed pair that a lane group works on.
-struct PairCtx {
+template <class IdT>
+struct PairCtxT {
     uint32_t s0, len;  // CSR row of the pair (BOX: unused)
-    uint32_t p;        // instance-local pair id
+    IdT p;             // instance-local pair id
     int ii;            // instance
     bool valid;
 };
+template <bool WIDE>
+using PairCtx = PairCtxT<typename Ids<WIDE>::id_t>;
 
-template <bool MULTI, int ENC, int G>
-__device__ __forceinline__ PairCtx load_pair(const Inst* __restrict__ It, const int64_t* bases, const Run& R,
-                                             uint32_t count, uint32_t first, int round) {
-    PairCtx c;
+template <bool MULTI, int ENC, int G, bool WIDE = false>
+__device__ __forceinline__ PairCtx<WIDE> load_pair(const Inst* __restrict__ It, const int64_t* bases, const Run& R,
+                                                   typename Ids<WIDE>::id_t count, typename Ids<WIDE>::id_t first,
+                                                   int round) {
+    using Id = typename Ids<WIDE>::id_t;
+    PairCtx<WIDE> c;
     const int sub = lane_id() & (G - 1);
-    const uint32_t i = first + (uint32_t)(lane_id() / G);
+    const Id i = first + (Id)(lane_id() / G);
     c.valid = i < count;
-    const uint32_t q = c.valid ? ldx<GBF_NT_MISC>(gp(R.list) + i) : 0u;
+    const Id q = c.valid ? ldx<GBF_NT_MISC>(gp(Ids<WIDE>::list(R)) + i) : (Id)0;
     c.ii = find_inst<MULTI>(bases, R.ninst, (int64_t)q);
     const Inst& I = It[c.ii];
-    c.p = q - (MULTI ? (uint32_t)I.pair_base : 0u);
+    c.p = q - (MULTI ? (Id)I.pair_base : (Id)0);
     if (c.valid && round >= I.max_rounds) {
         // the instance's round cap (second condition of Algorithm 1's while
         // loop) is reached with work left: drop the pair, flag the instance
@@ -1060,13 +1294,14 @@ struct PairVal {
 
 // Gather phase of one wave step (64/G pairs, G lanes each): loads only, so
 // the gathers of several wave steps can be in flight together.
-template <class T, bool MULTI, int ENC, int G>
-__device__ __forceinline__ PairVal<T> pair_gather(const Inst* __restrict__ It, const PairCtx& c) {
+template <class T, bool MULTI, int ENC, int G, bool WIDE = false>
+__device__ __forceinline__ PairVal<T> pair_gather(const Inst* __restrict__ It, const PairCtx<WIDE>& c) {
     using K = typename T::key_t;
+    using Id = typename Ids<WIDE>::id_t;
     const int sub = lane_id() & (G - 1);
     const Inst& I = It[c.ii];
     const GBF_GLOBAL K* V = gp(static_cast<const K*>(I.V));
-    const uint32_t x = c.p / (uint32_t)I.K;
+    const uint32_t x = (uint32_t)(c.p / (Id)I.K);
     K cur = (K)T::INF;
     int32_t graw = 0;
     if (c.valid) {
@@ -1135,17 +1370,18 @@ __device__ __forceinline__ PairVal<T> pair_gather(const Inst* __restrict__ It, c
 
 // Commit phase: max over the group, backup, one candidate per state, strict
 // improvement, expansion.
-template <class T, bool MULTI, int ENC, int G, int SCOPE = __HIP_MEMORY_SCOPE_AGENT>
-__device__ __forceinline__ void pair_commit(const Inst* __restrict__ It, const PairCtx& c, const PairVal<T>& pv,
-                                            uint8_t* __restrict__ next, Acc& acc) {
+template <class T, bool MULTI, int ENC, int G, int SCOPE = __HIP_MEMORY_SCOPE_AGENT, bool WIDE = false>
+__device__ __forceinline__ void pair_commit(const Inst* __restrict__ It, const PairCtx<WIDE>& c,
+                                            const PairVal<T>& pv, uint8_t* __restrict__ next, Acc& acc) {
     using K = typename T::key_t;
+    using Id = typename Ids<WIDE>::id_t;
     constexpr int W = kWave / G;
     const int lane = lane_id();
     const int sub = lane & (G - 1);
     const int grp = lane / G;
     const Inst& I = It[c.ii];
     GBF_GLOBAL K* V = gp(static_cast<K*>(I.V));
-    const uint32_t x = c.p / (uint32_t)I.K;
+    const uint32_t x = (uint32_t)(c.p / (Id)I.K);
     const K cur = pv.cur;
     const int32_t graw = pv.graw;
     const uint32_t len = pv.len;
@@ -1197,9 +1433,9 @@ __device__ __forceinline__ void pair_commit(const Inst* __restrict__ It, const P
         const uint32_t xl = __shfl(x, l, kWave);
         if (MULTI) {
             const int il = __shfl(c.ii, l, kWave);
-            expand_state<ENC>(It[il], xl, next, acc);
+            expand_state<ENC, WIDE>(It[il], xl, next, acc);
         } else {
-            expand_state<ENC>(It[0], xl, next, acc);
+            expand_state<ENC, WIDE>(It[0], xl, next, acc);
         }
     }
 }
@@ -1207,30 +1443,32 @@ __device__ __forceinline__ void pair_commit(const Inst* __restrict__ It, const P
 // One round over the listed pairs.  Each wave takes ILP consecutive wave
 // steps at a time: their loads are issued before any commit, so ILP times
 // as many gathers are in flight per wave.
-template <class T, bool MULTI, int ENC, int G, int ILP, int SCOPE = __HIP_MEMORY_SCOPE_AGENT>
+template <class T, bool MULTI, int ENC, int G, int ILP, int SCOPE = __HIP_MEMORY_SCOPE_AGENT, bool WIDE = false>
 __device__ __forceinline__ void relax_round(const Inst* __restrict__ It, const int64_t* bases, const Run& R,
-                                            uint32_t count, int round, Acc& acc) {
-    constexpr uint32_t W = kWave / G;  // pairs per wave and step
+                                            typename Ids<WIDE>::id_t count, int round, Acc& acc) {
+    using Id = typename Ids<WIDE>::id_t;
+    constexpr Id W = kWave / G;  // pairs per wave and step
     uint8_t* next = R.dirty[(round + 1) & 1];
-    const uint32_t wpb = blockDim.x / kWave;
-    const uint32_t wave = blockIdx.x * wpb + threadIdx.x / kWave;
-    const uint32_t stride = gridDim.x * wpb * W * ILP;
-    for (uint32_t first = wave * W * ILP; first < count; first += stride) {
-        PairCtx c[ILP];
+    const Id wpb = blockDim.x / kWave;
+    const Id wave = (Id)blockIdx.x * wpb + threadIdx.x / kWave;
+    const Id stride = (Id)gridDim.x * wpb * W * ILP;
+    for (Id first = wave * W * ILP; first < count; first += stride) {
+        PairCtx<WIDE> c[ILP];
         PairVal<T> v[ILP];
 #pragma unroll
-        for (int i = 0; i < ILP; ++i) c[i] = load_pair<MULTI, ENC, G>(It, bases, R, count, first + i * W, round);
+        for (int i = 0; i < ILP; ++i)
+            c[i] = load_pair<MULTI, ENC, G, WIDE>(It, bases, R, count, first + (Id)(i * W), round);
 #pragma unroll
-        for (int i = 0; i < ILP; ++i) v[i] = pair_gather<T, MULTI, ENC, G>(It, c[i]);
+        for (int i = 0; i < ILP; ++i) v[i] = pair_gather<T, MULTI, ENC, G, WIDE>(It, c[i]);
 #pragma unroll
-        for (int i = 0; i < ILP; ++i) pair_commit<T, MULTI, ENC, G, SCOPE>(It, c[i], v[i], next, acc);
+        for (int i = 0; i < ILP; ++i) pair_commit<T, MULTI, ENC, G, SCOPE, WIDE>(It, c[i], v[i], next, acc);
     }
 }
 
-template <class T, bool MULTI, int ENC, int G>
+template <class T, bool MULTI, int ENC, int G, bool WIDE = false>
 __global__ __launch_bounds__(kBlock) void k_relax(const Inst* __restrict__ It, Run R, int round) {
     __shared__ int64_t s_bases[MULTI ? kMaxBatch : 1];
-    const uint32_t count = R.counts[round];
+    const typename Ids<WIDE>::id_t count = Ids<WIDE>::counts(R)[round];
     if (count == 0) return;
     if (MULTI) {
         for (int k = threadIdx.x; k < R.ninst; k += blockDim.x) s_bases[k] = It[k].pair_base;
@@ -1239,7 +1477,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(const Inst* __restrict__ It, R
     __shared__ AccLds s_acc;
     acc_init(s_acc);
     Acc acc;
-    relax_round<T, MULTI, ENC, G, kILP>(It, s_bases, R, count, round, acc);
+    relax_round<T, MULTI, ENC, G, kILP, __HIP_MEMORY_SCOPE_AGENT, WIDE>(It, s_bases, R, count, round, acc);
     flush_acc(acc, s_acc, R.slots);
 }
 
@@ -1692,9 +1930,15 @@ static void pick_all(const Run& R, int dtype, int enc_mask, int G, RelaxFn* rf, 
 }
 
 hipError_t launch_seed(const Inst* dI, int ninst, const Run& R, int64_t max_states, int dtype, int enc_mask,
-                       hipStream_t s) {
+                       hipStream_t s, bool wide) {
     const int grid = grid_for((max_states + kWave - 1) / kWave, kWavesPerBlock, 4096);
     SeedFn f;
+    if (wide) {
+        // the seed marks pairs only: the value type does not matter
+        f = enc_mask == 2 ? k_seed<TI32, 2, true> : k_seed<TI32, 4, true>;
+        f<<<grid, kBlock, 0, s>>>(dI, ninst, R);
+        return hipGetLastError();
+    }
     // the seed reads only the successor structure: per-edge costs do not matter
     if (enc_mask == 8) enc_mask = 1;
     if (dtype == 1)
@@ -1755,11 +1999,27 @@ hipError_t launch_single(const Inst* dI, const Run& R, int lanes, int dtype, int
     return hipGetLastError();
 }
 
+// 64-bit pair ids: one instance, BOX (2) or HYB (4), lanes 2, 4 or 8.
+template <class T, int ENC>
+static RelaxFn pick_wide_enc(int G) {
+    switch (G) {
+        case 2: return k_relax<T, false, ENC, 2, true>;
+        case 8: return k_relax<T, false, ENC, 8, true>;
+        default: return k_relax<T, false, ENC, 4, true>;
+    }
+}
+
+static RelaxFn pick_wide(int dtype, int enc_mask, int G) {
+    if (dtype == 1) return enc_mask == 2 ? pick_wide_enc<TF32, 2>(G) : pick_wide_enc<TF32, 4>(G);
+    return enc_mask == 2 ? pick_wide_enc<TI32, 2>(G) : pick_wide_enc<TI32, 4>(G);
+}
+
 hipError_t launch_relax(const Inst* dI, const Run& R, int round, int grid, int lanes, int dtype, int enc_mask,
-                        hipStream_t s) {
+                        hipStream_t s, bool wide) {
     RelaxFn rf;
     PersistFn pf;
-    pick_all(R, dtype, enc_mask, lanes, &rf, &pf);
+    if (wide) rf = pick_wide(dtype, enc_mask, lanes);
+    else pick_all(R, dtype, enc_mask, lanes, &rf, &pf);
     rf<<<grid > 0 ? std::min(grid, kMaxGrid) : 1024, kBlock, 0, s>>>(dI, R, round);
     return hipGetLastError();
 }

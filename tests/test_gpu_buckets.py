@@ -64,6 +64,9 @@ def test_bucket_schedules(span, kind):
 
 def _solve_buckets(prob, keys, encoding="csr", **kw):
     import torch
+    # the schedule itself, without the work budget that would finish a
+    # costly schedule in plain order
+    kw.setdefault("bucket_budget", -1)
     kt = torch.from_numpy(keys.view(np.int16)).cuda()
     gr = gbf.load_problem(prob, encoding=encoding)
     status, st, V = gr.solve(order="buckets", bucket_key=kt, **kw)
@@ -136,15 +139,16 @@ def test_buckets_ragged_pairs():
 
 
 def test_buckets_fallback_on_cap():
-    """A negative cycle: the bucket schedule hits its cap, the plain order
-    reruns and reports the capped status; the result equals the plain run."""
+    """A negative cycle: the bucket schedule hits its cap (after its work
+    budget moved it to the plain order), the plain order reruns from scratch
+    and reports the capped status; the result equals the plain run."""
     import torch
     prob, _, _ = golden_io.load("negcycle.txt")
     _case("buckets fallback")
     gr = gbf.load_problem(prob, encoding="csr")
     kt = torch.zeros(prob.n, dtype=torch.int16, device="cuda")
     status, st, V = gr.solve(order="buckets", bucket_key=kt)
-    assert status == gbf.ENEGCYCLE and st["fallback"] == 1
+    assert status == gbf.ENEGCYCLE and st["fallback"] == 2
     status_p, st_p, Vp = gr.solve(order="plain")
     assert status_p == gbf.ENEGCYCLE and st_p["fallback"] == 0
     assert np.array_equal(V, Vp)
@@ -164,4 +168,36 @@ def test_buckets_rejects_bad_use():
         gr.solve(order="buckets")  # no key
     with pytest.raises(gbf.GbfError):
         gr.solve(order="buckets", bucket_key=kt, bucket_span=-2)
+    with pytest.raises(gbf.GbfError):
+        gr.solve(order="buckets", bucket_key=kt, bucket_budget=-2)
+    gr.free()
+
+
+@pytest.mark.parametrize("encoding", ["csr", "box+rev"])
+def test_work_budget_finishes_in_plain_order(encoding):
+    """Keys that order the frontier badly (a random bucket per state, one
+    bucket per round): after a plain solve on the handle, the bucket order
+    stops at the plain solve's work, finishes in plain order from where it
+    was (fallback 1), does less work than the same schedule without the
+    budget, and gives the oracle's values and policy."""
+    import torch
+    prob = synth.grid4d(synth.instance_seed(55, 0), dims=(20, 18, 10, 6), K=12)
+    ref = oracle.solve(prob)
+    keys = (synth.Stream(4242, 9).raw(prob.n) % np.uint64(4096)).astype(np.uint16)
+    kt = torch.from_numpy(keys.view(np.int16)).cuda()
+    _case(f"bucket work budget {encoding}")
+    gr = gbf.load_problem(prob, encoding=encoding)
+    status_p, st_p, Vp = gr.solve(order="plain")
+    assert status_p == gbf.OK
+    status_n, st_n, Vn = gr.solve(order="buckets", bucket_key=kt, bucket_span=1, bucket_budget=-1)
+    status, st, V = gr.solve(order="buckets", bucket_key=kt, bucket_span=1)
+    pol, res = gr.policy()
+    assert status == gbf.OK and status_n == gbf.OK
+    assert st["fallback"] == 1, st
+    assert res == 0
+    assert np.array_equal(V, ref["V"]) and np.array_equal(Vn, ref["V"]) and np.array_equal(Vp, ref["V"])
+    assert np.array_equal(pol, ref["policy"])
+    assert st["pair_evals"] < st_n["pair_evals"] and st["rounds"] < st_n["rounds"], (st, st_n)
+    print(f"pair evaluations: plain {st_p['pair_evals']} budget {st['pair_evals']} "
+          f"unbounded {st_n['pair_evals']}; rounds {st_p['rounds']} / {st['rounds']} / {st_n['rounds']}", flush=True)
     gr.free()
