@@ -73,6 +73,8 @@ def _bind(L):
     L.oracle_box_to_csr.restype = i64
     L.oracle_dijkstra_i32.argtypes = [i64, i64, P, P, P, P, P, P, P]
     L.oracle_dijkstra_i32.restype = ctypes.c_int
+    L.oracle_residual_box_sample.argtypes = [P, i64, P, i64, P, P, P, P, P, P]
+    L.oracle_residual_box_sample.restype = i64
     return L
 
 
@@ -224,6 +226,31 @@ def box_to_csr(dims, box: np.ndarray):
     idx = np.empty(m, dtype=np.int32)
     L.oracle_box_to_csr(_p(d), npairs, _p(b), _p(ptr), _p(idx))
     return ptr, idx
+
+
+def residual_box_sample(dims, K, states, box_rows, g_rows, G_rows, avoid, V):
+    """One application of P at the sampled states of an int32 box problem
+    (gbf_oracle.c, oracle_residual_box_sample): `box_rows`/`g_rows` hold the
+    K boxes and costs of each sampled state in order, `G_rows` its terminal
+    cost, `avoid` and `V` are full arrays.  Returns (number of sampled states
+    where P(V)(x) != V(x), the first offenders)."""
+    L = lib()
+    d = np.ascontiguousarray(np.array(list(dims) + [1] * (4 - len(dims)), dtype=np.int32))
+    xs = np.ascontiguousarray(states, dtype=np.int64)
+    b = np.ascontiguousarray(box_rows, dtype=np.uint64)
+    g = np.ascontiguousarray(g_rows, dtype=np.int32)
+    G = np.ascontiguousarray(G_rows, dtype=np.int32)
+    av = np.ascontiguousarray(avoid, dtype=np.uint8)
+    W = np.ascontiguousarray(V, dtype=np.int32)
+    if b.size != xs.size * K or g.size != xs.size * K or G.size != xs.size:
+        raise ValueError("one row of K boxes and costs, and one G, per sampled state")
+    if xs.size and (xs.min() < 0 or xs.max() >= W.size):
+        raise ValueError("sampled state out of range")
+    out = np.zeros(16, dtype=np.int64)
+    bad = L.oracle_residual_box_sample(_p(d), int(K), _p(xs), xs.size, _p(b), _p(g), _p(G), _p(av), _p(W), _p(out))
+    if bad < 0:
+        raise ValueError("box outside the grid")
+    return int(bad), out[:min(int(bad), 16)].copy()
 
 
 def dijkstra(prob) -> np.ndarray:

@@ -415,6 +415,82 @@ int64_t oracle_box_to_csr(const int32_t* dims, int64_t npairs, const uint64_t* b
 }
 
 /* ------------------------------------------------------------------ */
+/* Sampled fixed-point check for problems too large for Algorithm 1 on  */
+/* the CPU: one application of the operator P (Sect. III-C; the test   */
+/* that certifies a fixed point) at the sampled states only, with the  */
+/* oracle's own box decoding and the int32 reading of costs.  For each */
+/* sampled state x (states[i], ascending or not) the caller passes its */
+/* K boxes and costs (rows i*K .. i*K+K-1), G(x), and the full V and    */
+/* avoid arrays.  An avoid state must have V = INF; otherwise           */
+/*   P(V)(x) = min{ G(x), min_u g(x,u) + max_{y in F(x,u)} V(y) }      */
+/* with INF for g = INF or any V(y) = INF (an avoid successor has       */
+/* V = INF, which is the pruning of pairs that lead into the avoid set),*/
+/* sums formed in 64 bits, >= INT32_MAX as INF and below -INT32_MAX     */
+/* clamped.  Returns the number of sampled states with P(V)(x) != V(x)  */
+/* (first offenders in bad_out, up to 16), or OR_EINVAL for a box that  */
+/* leaves the grid.                                                    */
+/* ------------------------------------------------------------------ */
+int64_t oracle_residual_box_sample(const int32_t* dims, int64_t K, const int64_t* states, int64_t count,
+                                   const uint64_t* box, const int32_t* g, const int32_t* G,
+                                   const uint8_t* avoid, const int32_t* V, int64_t* bad_out) {
+    int64_t s1 = dims[0], s2 = (int64_t)dims[0] * dims[1], s3 = (int64_t)dims[0] * dims[1] * dims[2];
+    int64_t ncell = s3 * dims[3];
+    int64_t bad = 0;
+    oracle_counters dummy;
+    memset(&dummy, 0, sizeof(dummy));
+    for (int64_t i = 0; i < count; ++i) {
+        int64_t x = states[i];
+        int ok;
+        if (avoid[x]) {
+            ok = IS_INF_I32(V[x]);
+        } else {
+            int32_t best = G[i];
+            for (int64_t u = 0; u < K; ++u) {
+                uint64_t b = box[i * K + u];
+                int32_t gu = g[i * K + u];
+                int64_t lo = (int64_t)(b & 0xffffffffu);
+                int e[4], c[4];
+                for (int a = 0; a < 4; ++a) e[a] = (int)((b >> (32 + 8 * a)) & 0xffu);
+                int64_t r = lo;
+                c[0] = (int)(r % dims[0]);
+                r /= dims[0];
+                c[1] = (int)(r % dims[1]);
+                r /= dims[1];
+                c[2] = (int)(r % dims[2]);
+                r /= dims[2];
+                c[3] = (int)r;
+                if (lo >= ncell) return OR_EINVAL;
+                for (int a = 0; a < 4; ++a)
+                    if (c[a] + e[a] >= dims[a]) return OR_EINVAL;
+                if (IS_INF_I32(gu)) continue;
+                int32_t mx = INT32_MIN;
+                int inf = 0;
+                for (int j3 = 0; j3 <= e[3] && !inf; ++j3)
+                    for (int j2 = 0; j2 <= e[2] && !inf; ++j2)
+                        for (int j1 = 0; j1 <= e[1] && !inf; ++j1)
+                            for (int j0 = 0; j0 <= e[0]; ++j0) {
+                                int32_t vy = V[lo + j0 + j1 * s1 + j2 * s2 + j3 * s3];
+                                if (IS_INF_I32(vy)) {
+                                    inf = 1;
+                                    break;
+                                }
+                                if (vy > mx) mx = vy;
+                            }
+                if (inf) continue;
+                int32_t d;
+                if (backup_i32(gu, mx, &d, &dummy) && d < best) best = d;
+            }
+            ok = best == V[x];
+        }
+        if (!ok) {
+            if (bad_out && bad < 16) bad_out[bad] = x;
+            ++bad;
+        }
+    }
+    return bad;
+}
+
+/* ------------------------------------------------------------------ */
 /* Independent solver for non-negative running costs: a min-max        */
 /* Dijkstra (Knuth's generalisation to superior functions, 1977).      */
 /* States are settled in order of value; a pair becomes a candidate    */
