@@ -540,6 +540,81 @@ def learned_eval(args, pool):
     return {"summary": summary, "instances": recs}
 
 
+def paper_scale_run(args):
+    """The paper-scale grid (200x70x75x135 = 141.75 M cells, 35 inputs, 4.96 G
+    pairs; synth.paper_scale): generated on the device, loaded with 64-bit
+    pair ids (box successors with a reverse CSR, or implicit boxes), solved
+    once with per-launch events (roofline) and once for the solve time; the
+    GPU's fixed-point residual over every state, and the oracle's own
+    one-application-of-P check at sampled states.  Prints one JSON object."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2001_06231_amd as gbf
+    from synth import paper_scale as ps
+
+    def log(msg):
+        print(f"[paper-scale] {msg}", file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    m = ps.meta()
+    n, K = m["n"], ps.K
+    t0 = time.time()
+    box, g, G, av = ps.build(m, "cuda", log=log)
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    av_host = av.cpu().numpy()
+    log(f"generated n={n} pairs={n * K} in {gen_s:.1f}s")
+    t0 = time.time()
+    gr = gbf.load_graph(n, K, G, g, encoding="box", dims=ps.DIMS, box=box, avoid=av,
+                        expand_box=args.paper_expand, mem_budget=0)
+    torch.cuda.synchronize()
+    load_s = time.time() - t0
+    del box, g, G, av
+    torch.cuda.empty_cache()
+    log(f"loaded in {load_s:.1f}s")
+    V = torch.empty(n, dtype=torch.int32, device="cuda")
+    status, st_prof, _ = gr.solve(V, profile=True)
+    log(f"profiled solve: status {status} {st_prof['solve_ms']:.0f} ms rounds {st_prof['rounds']}")
+    status, st, _ = gr.solve(V)
+    log(f"solve: status {status} {st['solve_ms']:.0f} ms")
+    pol = torch.empty(n, dtype=torch.int32, device="cuda")
+    _, res = gr.policy(pol)
+    Vh = V.cpu().numpy()
+    enc = PER_EDGE_BYTES["box+rev" if st["enc_used"] == 2 else "box"]
+    rl = roofline([st_prof], n * K, enc)
+    gr.free()
+    t0 = time.time()
+    xs = ps.sample_states(args.paper_samples, m)
+    rows_b, rows_g = [], []
+    for i0 in range(0, xs.size, 100000):
+        xi = xs[i0:i0 + 100000]
+        pid = (xi[:, None] * K + np.arange(K)[None, :]).reshape(-1)
+        b, c = ps.pair_rows(torch.from_numpy(pid), m)
+        rows_b.append(b.numpy().view(np.uint64))
+        rows_g.append(c.numpy())
+    Gs, _ = ps.state_rows(torch.from_numpy(xs), m)
+    bad, first = oracle.residual_box_sample(ps.DIMS, K, xs, np.concatenate(rows_b), np.concatenate(rows_g),
+                                            Gs.numpy(), av_host, Vh)
+    check_s = time.time() - t0
+    log(f"oracle check at {xs.size} states: {bad} mismatches in {check_s:.1f}s")
+    fin = Vh != gbf.INF_I32
+    return {
+        "workload": "paper-scale grid 200x70x75x135 (141.75 M cells), 35 inputs, int32 potential-form costs, "
+                    "box successors, 64-bit pair ids",
+        "n_states": n, "pairs": n * K, "status": int(status), "enc_used": int(st["enc_used"]),
+        "device_bytes": int(st["device_bytes"]),
+        "gen_s": gen_s, "load_s": load_s, "solve_ms": st["solve_ms"], "rounds": int(st["rounds"]),
+        "pair_evals": int(st["pair_evals"]), "edge_relax": int(st["edge_relax"]),
+        "edge_relax_per_s": st["edge_relax"] / (st["solve_ms"] * 1e-3), "roofline": rl,
+        "gpu_residual_states": int(res), "oracle_sample_states": int(xs.size), "oracle_sample_mismatches": bad,
+        "oracle_first_mismatches": [int(v) for v in first], "oracle_check_s": check_s,
+        "finite_fraction": float(fin.mean()), "V_min": int(Vh[fin].min()) if fin.any() else None,
+        "V_max_finite": int(Vh[fin].max()) if fin.any() else None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -555,6 +630,10 @@ def main():
     ap.add_argument("--learned-eval", type=int, default=0,
                     help="instead: evaluate the trained network on this many held-out instances")
     ap.add_argument("--eval-reps", type=int, default=3)
+    ap.add_argument("--paper-scale", action="store_true",
+                    help="instead: the 141.75 M-cell, 35-input grid with 64-bit pair ids (~200 GB of device memory)")
+    ap.add_argument("--paper-expand", type=int, default=2, help="expand_box for --paper-scale (2 = reverse CSR)")
+    ap.add_argument("--paper-samples", type=int, default=1000000)
     ap.add_argument("--workers", type=int, default=8,
                     help="worker processes for input generation and the CPU oracle (1 = none, e.g. under a "
                          "profiler)")
@@ -565,11 +644,13 @@ def main():
         sys.exit(2)
     # the worker processes are forked before the first GPU call
     pool = None
-    if args.workers > 1 and (args.learned_eval or not args.no_extras or not args.no_cpu):
+    if args.workers > 1 and not args.paper_scale and (args.learned_eval or not args.no_extras or not args.no_cpu):
         import multiprocessing as mp
         pool = mp.get_context("fork").Pool(args.workers)
     try:
-        if args.learned_eval:
+        if args.paper_scale:
+            print(json.dumps(paper_scale_run(args)), flush=True)
+        elif args.learned_eval:
             print(json.dumps(learned_eval(args, pool)), flush=True)
         else:
             print(json.dumps(run(args, pool)), flush=True)
