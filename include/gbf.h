@@ -181,7 +181,15 @@ typedef struct gbf_opts {
                                -1 = no budget (the switch still comes by
                                round 65536, so that the plain continuation
                                keeps the plain round cap) */
-    int32_t reserved[1];
+    int32_t mem_floor_mib;  /* handles holding predecessor images (box successors
+                               with a reverse CSR): if at a frontier-size check of
+                               a host-loop solve the device's free memory is
+                               below this many MiB, the reverse CSR is released
+                               and the rest of the solve, and later solves of
+                               the handle, search predecessors in the per-input
+                               windows as the implicit form does
+                               (gbf_stats.images_dropped, enc_used 1); the
+                               values are the same.  0 = never. */
 } gbf_opts;
 
 /* ---- statistics ------------------------------------------------------- */
@@ -215,7 +223,8 @@ typedef struct gbf_stats {
     int32_t enc_used;       /* representation the handle holds: 0 CSR, 1 implicit
                                boxes, 2 boxes + reverse CSR (expand_box 2, or
                                3 when the predecessor images fit the budget) */
-    int32_t reserved_s;
+    int32_t images_dropped; /* 1 = this solve released the predecessor images
+                               (gbf_opts.mem_floor_mib) */
 } gbf_stats;
 
 typedef struct gbf_graph gbf_graph;

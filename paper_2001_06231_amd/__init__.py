@@ -71,7 +71,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("mode", ctypes.c_int32), ("bucket_key", ctypes.c_void_p),
                 ("max_rounds", ctypes.c_int64), ("lanes", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("v_memspace", ctypes.c_int32), ("profile", ctypes.c_int32), ("batch_hint", ctypes.c_int32),
-                ("bucket_span", ctypes.c_int32), ("bucket_budget", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("bucket_span", ctypes.c_int32), ("bucket_budget", ctypes.c_int32), ("mem_floor_mib", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -83,7 +83,7 @@ class _Stats(ctypes.Structure):
                 ("relax_launches", ctypes.c_int64), ("barrier_ms", ctypes.c_double), ("device_bytes", ctypes.c_int64),
                 ("mode_used", ctypes.c_int32), ("grid_used", ctypes.c_int32), ("block_used", ctypes.c_int32),
                 ("lanes_used", ctypes.c_int32), ("graph_used", ctypes.c_int32), ("sweeps", ctypes.c_int32),
-                ("enc_used", ctypes.c_int32), ("reserved_s", ctypes.c_int32)]
+                ("enc_used", ctypes.c_int32), ("images_dropped", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
@@ -221,8 +221,9 @@ class Graph:
             self._h = None
 
     def _opts(self, order, mode, max_rounds, grid, profile, bucket_key, v_space, lanes=0, bucket_span=0,
-              bucket_budget=0):
+              bucket_budget=0, mem_floor_mib=0):
         o = _Opts()
+        o.mem_floor_mib = int(mem_floor_mib)
         o.lanes = int(lanes)
         o.bucket_span = int(bucket_span)
         o.bucket_budget = int(bucket_budget)
@@ -241,7 +242,7 @@ class Graph:
         return o
 
     def solve(self, V_out=None, *, order="plain", mode="auto", max_rounds=0, grid=0, profile=False,
-              bucket_key=None, lanes=0, bucket_span=0, bucket_budget=0, check=True):
+              bucket_key=None, lanes=0, bucket_span=0, bucket_budget=0, mem_floor_mib=0, check=True):
         """Runs the solver; returns (status, stats dict, V_out).  V_out may be
         a numpy array (host) or a torch tensor on the GPU; if None a numpy
         array is allocated."""
@@ -249,7 +250,8 @@ class Graph:
         if V_out is None:
             V_out = np.empty(self.n, dtype=np.int32 if self.dtype == I32 else np.float32)
         vp, vs = _ptr(V_out)
-        o = self._opts(order, mode, max_rounds, grid, profile, bucket_key, vs, lanes, bucket_span, bucket_budget)
+        o = self._opts(order, mode, max_rounds, grid, profile, bucket_key, vs, lanes, bucket_span, bucket_budget,
+                       mem_floor_mib)
         st = _Stats()
         rc = L.gbf_solve(self._h, ctypes.byref(o), vp, ctypes.byref(st))
         if rc < 0 or (check and rc not in (OK, ENEGCYCLE)):

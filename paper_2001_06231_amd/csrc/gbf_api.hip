@@ -152,6 +152,7 @@ struct gbf_graph {
     Inst inst{};
     bool solved = false;
     bool wide = false;  // 64-bit pair ids
+    int64_t rev_bytes = 0, rptr_bytes = 0;  // predecessor images (reverse CSR)
     // the last plain-order solve of this handle (0 = none): the reference
     // of the bucket order's work budget, and (host-loop solves) its pair
     // evaluations accumulated round by round
@@ -197,7 +198,7 @@ static int ensure_scratch(Scratch& S, int64_t total_pairs, int64_t max_rounds, i
         int rc;
         if ((rc = S.mem.alloc((void**)&S.ctr, 8 * sizeof(unsigned long long)))) return rc;
         if ((rc = S.mem.alloc((void**)&S.slots, (size_t)kMaxGrid * 8 * sizeof(unsigned long long)))) return rc;
-        if ((rc = S.mem.alloc((void**)&S.barrier, 4096))) return rc;
+        if ((rc = S.mem.alloc((void**)&S.barrier, kBarrierBytes))) return rc;
         if ((rc = S.mem.alloc((void**)&S.error, 64))) return rc;
         if ((rc = S.mem.alloc((void**)&S.result, 64))) return rc;
         if ((rc = S.mem.alloc((void**)&S.occ, 65536))) return rc;
@@ -226,6 +227,31 @@ static int ensure_scratch(Scratch& S, int64_t total_pairs, int64_t max_rounds, i
     return GBF_OK;
 }
 
+// Per-input predecessor windows of a box problem (Sect. V-B: pred may be
+// replaced by a superset): for input u and axis a the range of lo_a - x_a
+// and hi_a - x_a over the live pairs.  Copied to `host` if it is not NULL.
+static int make_windows(Inst& I, DevMem& M, hipStream_t s, std::vector<int32_t>* host) {
+    const int64_t K = I.K;
+    int32_t* win;
+    int rc;
+    if ((rc = M.alloc((void**)&win, K * 8 * 4))) return rc;
+    std::vector<int32_t> hw(K * 8);
+    for (int64_t u = 0; u < K; ++u)
+        for (int a = 0; a < 4; ++a) {
+            hw[u * 8 + a] = 0x7fffffff;
+            hw[u * 8 + 4 + a] = (int32_t)0x80000000;
+        }
+    HIPC(hipMemcpyAsync(win, hw.data(), K * 8 * 4, hipMemcpyHostToDevice, s));
+    HIPC(launch_box_window(I, win, s));
+    if (host) {
+        host->resize(K * 8);
+        HIPC(hipMemcpyAsync(host->data(), win, K * 8 * 4, hipMemcpyDeviceToHost, s));
+    }
+    HIPC(hipStreamSynchronize(s));
+    I.win = win;
+    return GBF_OK;
+}
+
 // ------------------------------------------------------------------ load
 // The part of the loader after validation for 64-bit pair ids (GBF_BOX):
 // pruning, the per-input predecessor windows, and for expand_box 2 (or 3
@@ -238,19 +264,8 @@ static int load_wide(gbf_graph* gr, const gbf_problem* p, int eb, int32_t* err) 
     const int64_t n = I.n, K = I.K;
     int rc;
     HIPC(launch_prune(I, p->dtype, s));
-    int32_t* win;
-    if ((rc = M.alloc((void**)&win, K * 8 * 4))) return rc;
-    std::vector<int32_t> hw(K * 8);
-    for (int64_t u = 0; u < K; ++u)
-        for (int a = 0; a < 4; ++a) {
-            hw[u * 8 + a] = 0x7fffffff;
-            hw[u * 8 + 4 + a] = (int32_t)0x80000000;
-        }
-    HIPC(hipMemcpyAsync(win, hw.data(), K * 8 * 4, hipMemcpyHostToDevice, s));
-    HIPC(launch_box_window(I, win, s));
-    HIPC(hipMemcpyAsync(hw.data(), win, K * 8 * 4, hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    I.win = win;
+    std::vector<int32_t> hw;
+    if ((rc = make_windows(I, M, s, &hw))) return rc;
     M.release(err, 64);
     if (eb != 2 && eb != 3) return GBF_OK;
     // a reverse entry is (x - y)*K + u for y in F(x,u): bound |x - y| by the
@@ -307,6 +322,8 @@ static int load_wide(gbf_graph* gr, const gbf_problem* p, int eb, int32_t* err) 
     M.release(cursor, n * 8);
     M.release(cnt, (n + 1) * 4);
     M.release(tmp, nb * 8);
+    gr->rev_bytes = (int64_t)total * 4;
+    gr->rptr_bytes = (n + 1) * 8;
     I.rptr64 = rptr;
     I.rrel = rel;
     I.enc = 2;
@@ -539,6 +556,8 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
         if (sptr64) M.release(sptr64, (np + 1) * 8);
         M.release(cnt, (n + 1) * 4);
         M.release(tmp, nb * 4);
+        gr->rev_bytes = (int64_t)total * 4;
+        gr->rptr_bytes = (n + 1) * 4;
         if (hyb) {
             M.release(const_cast<uint32_t*>(I.sptr), (np + 1) * 4);
             M.release(const_cast<int32_t*>(I.sidx), (size_t)m * 4);
@@ -546,21 +565,12 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
             I.sidx = nullptr;
             I.enc = 2;
             gr->enc = 2;
+            // the windows, for a solve that drops the predecessor images
+            if ((rc = make_windows(I, M, s, nullptr))) return rc;
         }
     } else {
         HIPC(launch_prune(I, p->dtype, s));
-        int32_t* win;
-        if ((rc = M.alloc((void**)&win, K * 8 * 4))) return rc;
-        std::vector<int32_t> init(K * 8);
-        for (int64_t u = 0; u < K; ++u)
-            for (int a = 0; a < 4; ++a) {
-                init[u * 8 + a] = 0x7fffffff;
-                init[u * 8 + 4 + a] = (int32_t)0x80000000;
-            }
-        HIPC(hipMemcpyAsync(win, init.data(), K * 8 * 4, hipMemcpyHostToDevice, s));
-        HIPC(launch_box_window(I, win, s));
-        HIPC(hipStreamSynchronize(s));
-        I.win = win;
+        if ((rc = make_windows(I, M, s, nullptr))) return rc;
     }
     M.release(err, 64);
     *out = gr.release();
@@ -588,6 +598,7 @@ struct SolveOut {
     int64_t relax_launches = 0;
     int mode = 0, grid = 0, block = 0, lanes = 0, graph = 0, sweeps = 0;
     int switched = 0;  // bucket order: 1 = the work budget moved the rest of the solve to the plain order
+    int dropped = 0;   // 1 = the predecessor images were released during the solve
     int32_t inst_status[kMaxBatch] = {};  // per instance: 1 = round cap reached with work left
 };
 
@@ -604,7 +615,29 @@ struct Plan {
     int64_t budget_evals = INT64_MAX, budget_rounds = INT64_MAX;
     const std::vector<int64_t>* ref_profile = nullptr;  // bucket order: plain profile to keep up with
     std::vector<int64_t>* record = nullptr;             // plain order: per-round profile out
+    // memory floor: the handle whose predecessor images are released when
+    // the device's free memory falls below mem_floor bytes
+    gbf_graph* owner = nullptr;
+    int64_t mem_floor = 0;
 };
+
+// Releases the predecessor images (reverse CSR) of a handle with box
+// successors; later expansions search the per-input windows.  The caller
+// has synchronised the stream, so no launch still reads them.
+static void drop_images(gbf_graph* g) {
+    Inst& I = g->inst;
+    if (I.rev) g->mem.release(const_cast<uint32_t*>(I.rev), g->rev_bytes);
+    if (I.rptr) g->mem.release(const_cast<uint32_t*>(I.rptr), g->rptr_bytes);
+    if (I.rrel) g->mem.release(const_cast<int32_t*>(I.rrel), g->rev_bytes);
+    if (I.rptr64) g->mem.release(const_cast<uint64_t*>(I.rptr64), g->rptr_bytes);
+    I.rev = nullptr;
+    I.rptr = nullptr;
+    I.rrel = nullptr;
+    I.rptr64 = nullptr;
+    I.enc = 1;
+    g->enc = 1;
+    g->rev_bytes = g->rptr_bytes = 0;
+}
 
 static int plan_solve(Scratch& S, const Inst* insts, int ninst, int dtype, const gbf_opts& o, int cus,
                       int clock_khz, Plan& P) {
@@ -712,7 +745,7 @@ static int enqueue_init(Scratch& S, const Plan& P, const Inst* insts, hipStream_
     HIPC(launch_fill_u32((uint32_t*)R.ctr, 0, 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.slots, 0, (int64_t)kMaxGrid * 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.inst_status, 0, P.ninst, s));
-    HIPC(launch_fill_u32(R.barrier, 0, 1024, s));
+    HIPC(launch_fill_u32(R.barrier, 0, kBarrierBytes / 4, s));
     HIPC(launch_fill_u32((uint32_t*)R.error, 0, 16, s));
     HIPC(launch_fill_u32((uint32_t*)R.result, 0, 16, s));
     if (P.bucket) HIPC(launch_fill_u32((uint32_t*)R.occ, 0, 65536 / 4, s));
@@ -766,8 +799,19 @@ static int enqueue_hostloop(Scratch& S, const Plan& P, const gbf_opts& o, hipStr
     int64_t evals = 0;  // pairs listed so far (bucket order's work budget)
     // the round after the last allowed one only flags capped instances, so a
     // zero count appears at round max_rounds + 1 at the latest
+    int enc_mask = P.enc_mask;
     while (!done && r <= P.max_rounds + 1) {
         const int64_t nb = std::min<int64_t>(batch, P.max_rounds + 2 - r);
+        if (P.owner && P.mem_floor > 0 && enc_mask == 4 && r > 0 && !out.dropped) {
+            // the stream is idle here: the previous batch was synchronised
+            size_t fr = 0, tot = 0;
+            HIPC(hipMemGetInfo(&fr, &tot));
+            if ((int64_t)fr < P.mem_floor) {
+                drop_images(P.owner);
+                enc_mask = 2;  // box successors, predecessor windows
+                out.dropped = 1;
+            }
+        }
         bool behind = false;
         if (P.bucket && P.ref_profile && !P.ref_profile->empty() && r >= kProgressRound) {
             const auto& pr = *P.ref_profile;
@@ -787,7 +831,7 @@ static int enqueue_hostloop(Scratch& S, const Plan& P, const gbf_opts& o, hipStr
             else HIPC(launch_compact(R, (int)(r + k), 0, s, P.wide));
             const bool timed = o.profile && ev + 1 < (int)S.events.size();
             if (timed) HIPC(hipEventRecord(S.events[ev], s));
-            HIPC(launch_relax(S.dinst, R, (int)(r + k), P.grid, P.lanes, P.dtype, P.enc_mask, s, P.wide));
+            HIPC(launch_relax(S.dinst, R, (int)(r + k), P.grid, P.lanes, P.dtype, enc_mask, s, P.wide));
             if (timed) {
                 HIPC(hipEventRecord(S.events[ev + 1], s));
                 ev += 2;
@@ -830,7 +874,7 @@ static int enqueue_hostloop(Scratch& S, const Plan& P, const gbf_opts& o, hipStr
 static int run_rounds(Scratch& S, const Inst* insts, int ninst, int dtype, const gbf_opts& o, hipStream_t s,
                       int cus, int clock_khz, SolveOut& out, int64_t budget_evals = INT64_MAX,
                       int64_t budget_rounds = INT64_MAX, const std::vector<int64_t>* ref_profile = nullptr,
-                      std::vector<int64_t>* record = nullptr) {
+                      std::vector<int64_t>* record = nullptr, gbf_graph* owner = nullptr) {
     Plan P;
     int rc = plan_solve(S, insts, ninst, dtype, o, cus, clock_khz, P);
     if (rc) return rc;
@@ -838,6 +882,10 @@ static int run_rounds(Scratch& S, const Inst* insts, int ninst, int dtype, const
     P.budget_rounds = budget_rounds;
     P.ref_profile = ref_profile;
     P.record = record;
+    if (owner && ninst == 1 && o.mem_floor_mib > 0) {
+        P.owner = owner;
+        P.mem_floor = (int64_t)o.mem_floor_mib << 20;
+    }
     if (!S.events.empty()) HIPC(hipEventRecord(S.events[0], s));
     HIPC(hipMemcpyAsync(S.dinst, insts, sizeof(Inst) * P.ninst, hipMemcpyHostToDevice, s));
     if ((rc = enqueue_init(S, P, insts, s))) return rc;
@@ -869,7 +917,7 @@ static int run_rounds(Scratch& S, const Inst* insts, int ninst, int dtype, const
                 o2.mode = GBF_MODE_HOSTLOOP;
                 out = SolveOut();
                 return run_rounds(S, insts, ninst, dtype, o2, s, cus, clock_khz, out, budget_evals, budget_rounds,
-                                  ref_profile, record);
+                                  ref_profile, record, owner);
             }
             return fail(GBF_ETIMEOUT, "grid barrier timed out (blocks not co-resident?)");
         }
@@ -918,6 +966,7 @@ static void fill_stats(gbf_stats* st, int status, const SolveOut& so, int64_t ro
     st->graph_used = so.graph;
     st->sweeps = so.sweeps;
     st->enc_used = enc;
+    st->images_dropped = so.dropped;
 }
 
 static int write_values(gbf_graph* g, void* V_out, int memspace, hipStream_t s) {
@@ -973,8 +1022,9 @@ extern "C" int gbf_solve(gbf_graph* g, const gbf_opts* opts, void* V_out, gbf_st
     SolveOut so;
     std::vector<int64_t> profile;
     const bool use_ref = bucket && o.bucket_budget != -1 && !g->ref_profile.empty();
+    if (o.mem_floor_mib < 0) return fail(GBF_EINVAL, "mem_floor_mib must be >= 0");
     int rc = run_rounds(g->scratch, insts, 1, g->dtype, o, s, g->cus, g->clock_khz, so, budget_evals, budget_rounds,
-                        use_ref ? &g->ref_profile : nullptr, bucket ? nullptr : &profile);
+                        use_ref ? &g->ref_profile : nullptr, bucket ? nullptr : &profile, g);
     if (rc) return rc;
     int fallback = so.switched ? 1 : 0;
     if (bucket && so.inst_status[0]) {
@@ -1027,7 +1077,7 @@ constexpr size_t kNaOffCounts = kNaOffList + na_up((size_t)kNaPairs * 4);
 constexpr size_t kNaOffCtr = kNaOffCounts + na_up((size_t)kNaRounds * 4);
 constexpr size_t kNaOffSlots = kNaOffCtr + na_up(8 * sizeof(unsigned long long));
 constexpr size_t kNaOffBarrier = kNaOffSlots + na_up((size_t)kMaxGrid * 8 * sizeof(unsigned long long));
-constexpr size_t kNaOffError = kNaOffBarrier + na_up(4096);
+constexpr size_t kNaOffError = kNaOffBarrier + na_up(kBarrierBytes);
 constexpr size_t kNaOffResult = kNaOffError + na_up(64);
 constexpr size_t kNaOffOcc = kNaOffResult + na_up(64);
 constexpr size_t kNaOffThr = kNaOffOcc + na_up(65536);

@@ -48,7 +48,7 @@ struct Run {
     unsigned long long* ctr;    // [8]: pair evals, edges, improvements, saturations, expansions, marks
     unsigned long long* slots;  // per-block statistics [kMaxGrid * 8]
     int32_t* inst_status;       // per instance: 1 = cap reached with work left
-    uint32_t* barrier;          // persistent mode: barrier words (see grid_barrier), 2304 bytes
+    uint32_t* barrier;          // persistent mode: barrier words (see the grid barriers), kBarrierBytes
     int32_t* error;             // persistent mode: barrier timeout flag
     int32_t* result;            // persistent mode: [0] rounds executed
     uint64_t timeout_ticks;     // persistent mode: bound of one barrier wait (device clock ticks)
@@ -69,6 +69,7 @@ struct Run {
 int set_error(int code, const std::string& msg);
 
 constexpr int kMaxBatch = 1024;
+constexpr int kBarrierBytes = 4096;  // persistent mode: barrier words (see the grid barriers)
 constexpr int kMaxGrid = 8192;  // most blocks of any solver launch
 
 // Launch wrappers (all asynchronous on `s`).

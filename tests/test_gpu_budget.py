@@ -1,6 +1,9 @@
-"""Memory-budgeted images (expand_box 3): the loader keeps the predecessor
-images when they fit the budget and stays implicit otherwise; either way the
-solve is exact against the oracle and the stats report the choice."""
+"""Memory-budgeted images (Sect. IV-B, VI-A: images kept in memory up to a
+threshold, recomputed beyond it).  At load (expand_box 3) the predecessor
+images are kept when they fit the budget, else the problem stays implicit;
+during a solve (mem_floor_mib) they are released once the device's free
+memory falls below a floor.  Every way the solve is exact against the
+oracle and the stats report the representation."""
 import numpy as np
 import pytest
 
@@ -54,3 +57,27 @@ def test_enc_used_reported(grid):
     small = _run(prob, ref, "box:budget", mem_budget=1)["device_bytes"]
     big = _run(prob, ref, "box:budget", mem_budget=1 << 40)["device_bytes"]
     assert small < big
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_images_dropped_under_memory_pressure(wide):
+    """Predecessor images released during a solve once the device's free
+    memory is below the floor (here a floor above the device's memory, so
+    the first frontier-size check releases them): the rest of the solve and
+    later solves search predecessors in the windows; values and policy stay
+    the oracle's, and the handle holds less memory."""
+    prob = synth.grid4d(synth.instance_seed(60, 1), dims=(20, 18, 10, 6), K=12)
+    ref = oracle.solve(prob)
+    print(f"\n[case] images dropped wide={wide}", flush=True)
+    gr = gbf.load_problem(prob, encoding="box+rev", pair_ids64=wide)
+    status, st0, V = gr.solve(mode="hostloop")
+    assert status == gbf.OK and st0["enc_used"] == 2 and st0["images_dropped"] == 0
+    status, st, V = gr.solve(mode="hostloop", mem_floor_mib=1 << 30)
+    pol, res = gr.policy()
+    assert status == gbf.OK and st["images_dropped"] == 1 and st["enc_used"] == 1, st
+    assert st["device_bytes"] < st0["device_bytes"]
+    assert res == 0 and np.array_equal(V, ref["V"]) and np.array_equal(pol, ref["policy"])
+    status, st2, V2 = gr.solve(mode="hostloop")
+    assert status == gbf.OK and st2["enc_used"] == 1 and st2["images_dropped"] == 0
+    assert np.array_equal(V2, ref["V"])
+    gr.free()
