@@ -296,9 +296,11 @@ def learned_compare(prob, params, untrained, reps=3):
 def batch_compare(probs, reps=3):
     """One batched solve of the 64 instances in the encoding and launch
     configuration the autotuner picks, against 64 sequential plain solves
-    (library defaults) in the same encoding and in CSR; the persistent form
-    replayed from its HIP graph; wall time around the calls (device
-    outputs)."""
+    (library defaults) in the same encoding and in CSR; in the chosen
+    encoding also the best host-loop configuration against the best
+    persistent one replayed from its HIP graph (each tuned within its own
+    mode), so the graph form is compared like for like; wall time around the
+    calls (device outputs)."""
     import numpy as np
     import torch
 
@@ -325,19 +327,22 @@ def batch_compare(probs, reps=3):
            "pairs": int(sum(p.npairs for p in probs)),
            "tuned": {k: tuned[k] for k in ("encoding", "mode", "lanes", "grid")}, "tune_s": tune_s}
     exact = True
+
+    def same():
+        return all(bool(torch.equal(a, b)) for a, b in zip(outs, seq))
     for enc in dict.fromkeys(["csr", tuned["encoding"]]):
         graphs = [gbf.load_problem(p, encoding=enc) for p in probs]
         seq_ms, seq_stats = wall(lambda: [gr.solve(v)[1] for gr, v in zip(graphs, seq)])
         res[f"sequential_{enc}_ms"] = seq_ms
         res[f"edge_relax_sequential_{enc}"] = int(sum(s["edge_relax"] for s in seq_stats))
         per_ms, (_, per_stats, _) = wall(lambda: gbf.solve_batch(graphs, outs, mode="persistent"))
-        exact = exact and all(bool(torch.equal(a, b)) for a, b in zip(outs, seq))
+        exact = exact and same()
         res[f"persistent_graph_{enc}_ms"] = per_ms
         res[f"graph_used_{enc}"] = int(per_stats[0]["graph_used"])
         if enc == tuned["encoding"]:
             kw = dict(mode=tuned["mode"], lanes=tuned["lanes"], grid=tuned["grid"])
             bat_ms, (_, bat_stats, _) = wall(lambda: gbf.solve_batch(graphs, outs, **kw))
-            exact = exact and all(bool(torch.equal(a, b)) for a, b in zip(outs, seq))
+            exact = exact and same()
             prof = [gbf.solve_batch(graphs, outs, profile=True, **kw)[1][0] for _ in range(reps)]
             per_edge = PER_EDGE_BYTES[enc]
             res["roofline"] = roofline(prof, res["pairs"], per_edge)
@@ -345,6 +350,17 @@ def batch_compare(probs, reps=3):
             res["edge_relax_batched"] = int(bat_stats[0]["edge_relax"])
             res["rounds_batched"] = int(bat_stats[0]["rounds"])
             res["edge_relax_per_s_batched"] = bat_stats[0]["edge_relax"] / (bat_ms * 1e-3)
+            # like for like: each launch form at its own best configuration
+            forms = {}
+            for mode in ("hostloop", "persistent"):
+                o, _ = gbf.tune(graphs, reps=2, mode=mode)
+                ms, (_, fst, _) = wall(lambda: gbf.solve_batch(graphs, outs, **o))
+                exact = exact and same()
+                forms[mode] = {"ms": ms, "lanes": int(o["lanes"]), "grid": int(fst[0]["grid_used"]),
+                               "graph_used": int(fst[0]["graph_used"]), "barrier_ms": fst[0]["barrier_ms"]}
+            res["best_hostloop"] = forms["hostloop"]
+            res["best_persistent_graph"] = forms["persistent"]
+            res["graph_speedup_over_hostloop"] = forms["hostloop"]["ms"] / forms["persistent"]["ms"]
         for gr in graphs:
             gr.free()
     res["speedup_same_encoding"] = res[f"sequential_{tuned['encoding']}_ms"] / res["batched_ms"]

@@ -301,7 +301,9 @@ int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gbf_opts* opt
  * lanes 2/4/8 in single-block mode) and writes the fastest into *best (the other
  * fields are copied from `base`, which may be NULL).  Each candidate runs
  * one untimed and `reps` (0 = 3) timed solves; the median decides.
- * best_ms (may be NULL) receives its median solve time.  The handles keep
+ * best_ms (may be NULL) receives its median solve time.  A base->mode
+ * other than GBF_MODE_AUTO times that mode's candidates only (GBF_EINVAL if
+ * it has none, e.g. single-block for a batch).  The handles keep
  * the last candidate's solve.  The encoding is fixed by the handles: load
  * an instance in several encodings to choose between them.
  * Errors: GBF_EINVAL, GBF_EHIP (no candidate ran). */

@@ -406,13 +406,13 @@ def solve_batch(graphs: Sequence[Graph], V_outs=None, *, mode="auto", max_rounds
 _MODE_NAMES = {v: k for k, v in _MODES.items()}  # includes "single_block"
 
 
-def tune(graphs: Sequence[Graph], reps=3, order="plain", bucket_key=None, bucket_span=0):
+def tune(graphs: Sequence[Graph], reps=3, order="plain", bucket_key=None, bucket_span=0, mode="auto"):
     """gbf_tune: the fastest launch configuration for these handles (one
-    instance, or a batch).  Returns (options dict for Graph.solve /
-    solve_batch, median solve ms)."""
+    instance, or a batch), over every mode or within `mode`.  Returns
+    (options dict for Graph.solve / solve_batch, median solve ms)."""
     L = lib()
     cnt = len(graphs)
-    base = graphs[0]._opts(order, "auto", 0, 0, False, bucket_key, DEVICE, 0, bucket_span)
+    base = graphs[0]._opts(order, mode, 0, 0, False, bucket_key, DEVICE, 0, bucket_span)
     best = _Opts()
     ms = ctypes.c_double(0.0)
     hs = (ctypes.c_void_p * cnt)(*[gr._h for gr in graphs])

@@ -26,10 +26,10 @@ def signature(probs) -> str:
     return hashlib.sha1(";".join(parts).encode()).hexdigest()[:20]
 
 
-def _measure(probs, encoding, reps):
+def _measure(probs, encoding, reps, mode):
     graphs = [load_problem(p, encoding=encoding) for p in probs]
     try:
-        return tune(graphs, reps=reps)
+        return tune(graphs, reps=reps, mode=mode)
     finally:
         for g in graphs:
             g.free()
@@ -42,10 +42,11 @@ def _load_cache(path):
     return {}
 
 
-def autotune(probs, encodings=ENCODINGS, reps=3, cache=None, log=None):
-    """Returns {"encoding", "mode", "lanes", "grid", "ms"} for the set.
-    `cache`: path of a JSON file (read and updated), or None."""
-    key = signature(probs)
+def autotune(probs, encodings=ENCODINGS, reps=3, cache=None, log=None, mode="auto"):
+    """Returns {"encoding", "mode", "lanes", "grid", "ms"} for the set, over
+    every launch mode or within `mode`.  `cache`: path of a JSON file (read
+    and updated), or None."""
+    key = signature(probs) + ("" if mode == "auto" else f":{mode}")
     table = _load_cache(cache)
     if key in table:
         return table[key]
@@ -55,7 +56,7 @@ def autotune(probs, encodings=ENCODINGS, reps=3, cache=None, log=None):
             continue  # no boxes: only explicit successor lists
         if enc != "csr" and any(getattr(p, "g_edge", None) is not None for p in probs):
             continue  # per-edge costs are attached to explicit successor lists
-        opts, ms = _measure(probs, enc, reps)
+        opts, ms = _measure(probs, enc, reps, mode)
         if log:
             log(f"tune {enc}: {opts} {ms:.3f} ms")
         if best is None or ms < best["ms"]:

@@ -1417,14 +1417,21 @@ extern "C" int gbf_tune(gbf_graph* const* graphs, int32_t count, const gbf_opts*
     struct Cand {
         int mode, lanes, grid;
     };
+    if (o.mode != GBF_MODE_AUTO && o.mode != GBF_MODE_HOSTLOOP && o.mode != GBF_MODE_PERSISTENT &&
+        o.mode != GBF_MODE_SINGLE_BLOCK)
+        return fail(GBF_EINVAL, "unknown mode");
+    const bool any = o.mode == GBF_MODE_AUTO;
     std::vector<Cand> cands;
-    for (int lanes : {2, 4, 8})
-        for (int per_cu : {4, 8, 16}) cands.push_back({GBF_MODE_HOSTLOOP, lanes, per_cu * cus});
-    if (o.order == GBF_ORDER_PLAIN)
+    if (any || o.mode == GBF_MODE_HOSTLOOP)
+        for (int lanes : {2, 4, 8})
+            for (int per_cu : {4, 8, 16}) cands.push_back({GBF_MODE_HOSTLOOP, lanes, per_cu * cus});
+    if (o.order == GBF_ORDER_PLAIN && (any || o.mode == GBF_MODE_PERSISTENT))
         for (int lanes : {2, 4, 8}) cands.push_back({GBF_MODE_PERSISTENT, lanes, 0});
     // one workgroup is only worth timing on small single instances
-    if (o.order == GBF_ORDER_PLAIN && count == 1 && graphs[0]->n * graphs[0]->K <= 4 * kSingleBlockMaxPairs)
+    if (o.order == GBF_ORDER_PLAIN && count == 1 && graphs[0]->n * graphs[0]->K <= 4 * kSingleBlockMaxPairs &&
+        (any || o.mode == GBF_MODE_SINGLE_BLOCK))
         for (int lanes : {2, 4, 8}) cands.push_back({GBF_MODE_SINGLE_BLOCK, lanes, 0});
+    if (cands.empty()) return fail(GBF_EINVAL, "no candidate configuration for this mode and order");
     double best_t = 1e300;
     gbf_opts bo = o;
     bool found = false;

@@ -38,6 +38,12 @@
 #ifndef GBF_PBLOCKS
 #define GBF_PBLOCKS 2  // persistent kernel: 1024-thread blocks per CU
 #endif
+#ifndef GBF_PHYB
+#define GBF_PHYB 2  // persistent kernel, box successors with a reverse CSR: 1024-thread blocks per CU
+#endif
+#ifndef GBF_PEDGE
+#define GBF_PEDGE 2  // persistent kernel, CSR with per-edge costs: 1024-thread blocks per CU
+#endif
 #ifndef GBF_EXP_BATCH
 #define GBF_EXP_BATCH 4  // reverse-row slices of 64 loaded together when expanding a state
 #endif
@@ -1620,10 +1626,13 @@ __device__ __forceinline__ bool xcd_barrier(uint32_t* bar, int32_t* err, uint32_
 
 constexpr int kPBlock = 1024;  // persistent kernel: one 16-wave block per CU
 
-// CSR variants fit 64 VGPRs (two 16-wave blocks per CU); the box
-// variants need more registers and run one block per CU.
+// The CSR and HYB variants and CSR with per-edge costs are built for 64
+// VGPRs (two 16-wave blocks per CU; a few bytes of spill in the wider lane
+// groups); the variants that decode forward boxes (BOX, mixed) would spill
+// some 300 bytes per lane at that budget and run one block per CU.
 template <class T, bool MULTI, int ENC, int G>
-__global__ __launch_bounds__(kPBlock) __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 4 * GBF_PBLOCKS : 4)))
+__global__ __launch_bounds__(kPBlock) __attribute__((amdgpu_waves_per_eu(
+    4 * (ENC == 1 ? GBF_PBLOCKS : ENC == 4 ? GBF_PHYB : ENC == 5 ? GBF_PEDGE : 1))))
 void k_persistent(const Inst* __restrict__ It, Run R) {
     __shared__ int64_t s_bases[MULTI ? kMaxBatch : 1];
     __shared__ int s_w[kPCompactC * (kPBlock / kWave)];

@@ -47,3 +47,29 @@ def test_autotune_batch(tmp_path):
     for g in graphs:
         g.free()
     assert autotune.autotune(probs, cache=cache) == best
+
+
+def test_tune_within_a_mode():
+    """gbf_tune restricted to one launch mode returns that mode's best
+    configuration, which solves exactly; a mode without candidates (one
+    workgroup for a batch, persistent with the bucket order) is rejected."""
+    print("\n[case] tune within a mode", flush=True)
+    import torch
+    prob = synth.grid4d(synth.instance_seed(60, 1), dims=(12, 10, 6, 4))
+    ref = oracle.solve(prob)
+    g = gbf.load_problem(prob, encoding="box+rev")
+    for mode in ("hostloop", "persistent", "single_block"):
+        opts, ms = gbf.tune([g], reps=1, mode=mode)
+        assert opts["mode"] == mode and ms > 0, (mode, opts)
+        st, _, V = g.solve(**opts)
+        assert st == gbf.OK and np.array_equal(V, ref["V"]), mode
+    g2 = gbf.load_problem(synth.grid4d(synth.instance_seed(60, 2), dims=(10, 9, 6, 4)), encoding="box+rev")
+    with pytest.raises(gbf.GbfError) as e:
+        gbf.tune([g, g2], reps=1, mode="single_block")
+    assert e.value.code == gbf.EINVAL
+    keys = torch.zeros(prob.n, dtype=torch.int16, device="cuda")
+    with pytest.raises(gbf.GbfError) as e:
+        gbf.tune([g], reps=1, mode="persistent", order="buckets", bucket_key=keys)
+    assert e.value.code == gbf.EINVAL
+    g.free()
+    g2.free()

@@ -18,7 +18,7 @@ def test_signature_depends_on_shape_only():
 def test_choice_and_cache(tmp_path, monkeypatch):
     calls = []
 
-    def fake(probs, enc, reps):
+    def fake(probs, enc, reps, mode):
         calls.append(enc)
         return ({"mode": "hostloop", "lanes": 4 if enc == "csr" else 2, "grid": 2048},
                 {"csr": 5.0, "box+rev": 4.0}[enc])
@@ -38,7 +38,7 @@ def test_choice_and_cache(tmp_path, monkeypatch):
 def test_lists_only_problem_skips_box(monkeypatch):
     prob = synth.explicit_problem(2, 1, [[1], [1]], [1, 0], [2**31 - 1, 0])
     seen = []
-    monkeypatch.setattr(T, "_measure", lambda p, e, r: (seen.append(e) or ({"mode": "hostloop", "lanes": 4,
+    monkeypatch.setattr(T, "_measure", lambda p, e, r, m: (seen.append(e) or ({"mode": "hostloop", "lanes": 4,
                                                                             "grid": 0}, 1.0)))
     assert T.autotune([prob])["encoding"] == "csr"
     assert seen == ["csr"]
@@ -52,10 +52,30 @@ def test_edge_costs_tune_only_lists(monkeypatch):
     assert T.signature([prob]) != T.signature([base])
     seen = []
 
-    def fake(probs, enc, reps):
+    def fake(probs, enc, reps, mode):
         seen.append(enc)
         return {"mode": "hostloop", "lanes": 4, "grid": 1024}, 1.0
 
     monkeypatch.setattr(T, "_measure", fake)
     best = T.autotune([prob])
     assert seen == ["csr"] and best["encoding"] == "csr"
+
+
+def test_mode_restricted_tuning_has_its_own_cache_entry(tmp_path, monkeypatch):
+    """Tuning within one launch mode passes the mode down and is cached
+    under a key of its own, beside the unrestricted result."""
+    seen = []
+
+    def fake(probs, enc, reps, mode):
+        seen.append(mode)
+        return {"mode": "hostloop" if mode == "auto" else mode, "lanes": 2, "grid": 0}, 1.0
+
+    monkeypatch.setattr(T, "_measure", fake)
+    probs = [synth.grid2d_small()]
+    cache = str(tmp_path / "tune.json")
+    a = T.autotune(probs, cache=cache)
+    b = T.autotune(probs, cache=cache, mode="persistent")
+    assert a["mode"] == "hostloop" and b["mode"] == "persistent"
+    assert set(seen) == {"auto", "persistent"}
+    table = json.load(open(cache))
+    assert table[T.signature(probs)] == a and table[T.signature(probs) + ":persistent"] == b
