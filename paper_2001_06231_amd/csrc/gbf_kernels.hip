@@ -753,6 +753,42 @@ __device__ __forceinline__ bool has_edge(const Inst& I) {
 template <int ENC>
 constexpr bool kMayEdge = ENC == 5 || ENC == 3;
 
+// NS slices of 64 reverse entries of one state, starting at entry t0.
+// Every load is unconditional -- lanes past the row end read its last entry
+// again -- so all NS entry loads, then all NS dirty-byte loads, issue back
+// to back before one wait each (a load under a lane condition would be
+// followed by its own wait); the marks stay guarded.  entry(t) gives the
+// pair id of entry t.
+template <int NS, class Id, class Entry>
+__device__ __forceinline__ void mark_slices(const Inst& I, uint8_t* __restrict__ dirty, Id base, uint32_t t0,
+                                            uint32_t len, Entry entry) {
+    const int lane = lane_id();
+    Id q[NS];
+    bool v[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const uint32_t t = t0 + (uint32_t)(k * kWave + lane);
+        v[k] = t < len;
+        q[k] = entry(min(t, len - 1u));
+    }
+    uint8_t b[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) b[k] = gp(dirty)[base + q[k]];
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+        if (v[k] && b[k] == 0) {
+            gp(dirty)[base + q[k]] = 1;
+            if (I.key) gp(I.occ)[gp(I.key)[q[k] / (Id)I.K]] = 1;
+        }
+}
+
+// Streams a reverse row of `len` entries, kExpBatch slices per step.
+template <class Id, class Entry>
+__device__ __forceinline__ void mark_row(const Inst& I, uint8_t* __restrict__ dirty, Id base, uint32_t len,
+                                         Entry entry) {
+    for (uint32_t t0 = 0; t0 < len; t0 += kWave * kExpBatch) mark_slices<kExpBatch, Id>(I, dirty, base, t0, len, entry);
+}
+
 // Whole-wave expansion of one state y (wave-uniform arguments): every live
 // pair (x',u') with y in F(x',u') is marked.  CSR: the (sorted) reverse row
 // of y is streamed by the wave.  BOX: for every input the predecessor
@@ -773,22 +809,8 @@ __device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint8_t* 
             acc.expanded += 1;
             acc.marks += len;
         }
-        for (uint32_t t0 = 0; t0 < len; t0 += kWave * kExpBatch) {
-            Id q[kExpBatch];
-            bool v[kExpBatch];
-#pragma unroll
-            for (int k = 0; k < kExpBatch; ++k) {
-                const uint32_t t = t0 + (uint32_t)(k * kWave + lane);
-                v[k] = t < len;
-                q[k] = v[k] ? (Id)(yK + (int64_t)ldx<GBF_NT_MISC>(rel + s0 + t)) : (Id)0;
-            }
-            uint8_t b[kExpBatch];
-#pragma unroll
-            for (int k = 0; k < kExpBatch; ++k) b[k] = v[k] ? gp(dirty)[base + q[k]] : (uint8_t)1;
-#pragma unroll
-            for (int k = 0; k < kExpBatch; ++k)
-                if (b[k] == 0) gp(dirty)[base + q[k]] = 1;
-        }
+        mark_row<Id>(I, dirty, base, len,
+                     [&](uint32_t t) { return (Id)(yK + (int64_t)ldx<GBF_NT_MISC>(rel + s0 + t)); });
         return;
     }
     if (rev_csr<ENC>(I)) {
@@ -801,25 +823,8 @@ __device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint8_t* 
         }
         // kExpBatch slices of 64 entries per step: all their reverse
         // entries, then all their dirty bytes, are loaded before any store
-        for (uint32_t t0 = 0; t0 < len; t0 += kWave * kExpBatch) {
-            uint32_t q[kExpBatch];
-            bool v[kExpBatch];
-#pragma unroll
-            for (int k = 0; k < kExpBatch; ++k) {
-                const uint32_t t = t0 + (uint32_t)(k * kWave + lane);
-                v[k] = t < len;
-                q[k] = v[k] ? ldx<GBF_NT_MISC>(rev + s0 + t) : 0u;
-            }
-            uint8_t b[kExpBatch];
-#pragma unroll
-            for (int k = 0; k < kExpBatch; ++k) b[k] = v[k] ? gp(dirty)[base + q[k]] : (uint8_t)1;
-#pragma unroll
-            for (int k = 0; k < kExpBatch; ++k)
-                if (b[k] == 0) {
-                    gp(dirty)[base + q[k]] = 1;
-                    if (I.key) gp(I.occ)[gp(I.key)[q[k] / (uint32_t)I.K]] = 1;
-                }
-        }
+        mark_row<uint32_t>(I, dirty, (uint32_t)base, len,
+                           [&](uint32_t t) { return ldx<GBF_NT_MISC>(rev + s0 + t); });
         return;
     }
     int yc[4];
@@ -1298,6 +1303,33 @@ struct PairVal {
     uint32_t len;
 };
 
+// NK loads per lane of a successor row segment starting at entry t (lane
+// stride G), then the NK values: all unconditional -- lanes past the row
+// end take its last entry again, a real successor, so the max does not
+// change -- so the loads of a batch issue back to back before one wait.
+// EDGE: per-edge costs h stream beside the indices.
+template <class T, int NK, int G, bool EDGE>
+__device__ __forceinline__ void row_batch(const GBF_GLOBAL int32_t* row, const GBF_GLOBAL int32_t* hrow,
+                                          const GBF_GLOBAL typename T::key_t* V, uint32_t t, uint32_t len,
+                                          typename T::key_t& mx, typename T::wide_t& mw) {
+    using K = typename T::key_t;
+    int32_t y[NK], hv[NK];
+    K w[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const uint32_t tk = min(t + (uint32_t)(k * G), len - 1u);
+        y[k] = ldx<GBF_NT_ROWS>(row + tk);
+        if constexpr (EDGE) hv[k] = ldx<GBF_NT_ROWS>(hrow + tk);
+    }
+#pragma unroll
+    for (int k = 0; k < NK; ++k) w[k] = V[y[k]];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        if constexpr (EDGE) mw = T::wmax2(mw, T::edge(hv[k], w[k]));
+        else mx = T::max2(mx, w[k]);
+    }
+}
+
 // Gather phase of one wave step (64/G pairs, G lanes each): loads only, so
 // the gathers of several wave steps can be in flight together.
 template <class T, bool MULTI, int ENC, int G, bool WIDE = false>
@@ -1322,32 +1354,13 @@ __device__ __forceinline__ PairVal<T> pair_gather(const Inst* __restrict__ It, c
             // per-edge costs: the row's h values stream beside its indices
             const GBF_GLOBAL int32_t* row = gp(I.sidx) + c.s0;
             const GBF_GLOBAL int32_t* hrow = gp(I.ge) + c.s0;
-            for (uint32_t t = (uint32_t)sub; t < len; t += kRowBatch * G) {
-                int32_t y[kRowBatch], hv[kRowBatch];
-#pragma unroll
-                for (int k = 0; k < kRowBatch; ++k) {
-                    const uint32_t tk = t + (uint32_t)(k * G);
-                    y[k] = tk < len ? ldx<GBF_NT_ROWS>(row + tk) : -1;
-                    hv[k] = tk < len ? ldx<GBF_NT_ROWS>(hrow + tk) : 0;
-                }
-#pragma unroll
-                for (int k = 0; k < kRowBatch; ++k)
-                    if (y[k] >= 0) mw = T::wmax2(mw, T::edge(hv[k], V[y[k]]));
-            }
+            for (uint32_t t = (uint32_t)sub; t < len; t += kRowBatch * G)
+                row_batch<T, kRowBatch, G, true>(row, hrow, V, t, len, mx, mw);
         } else if (fwd_csr<ENC>(I)) {
             // kRowBatch successor indices per lane in flight, then their values
             const GBF_GLOBAL int32_t* row = gp(I.sidx) + c.s0;
-            for (uint32_t t = (uint32_t)sub; t < len; t += kRowBatch * G) {
-                int32_t y[kRowBatch];
-#pragma unroll
-                for (int k = 0; k < kRowBatch; ++k) {
-                    const uint32_t tk = t + (uint32_t)(k * G);
-                    y[k] = tk < len ? ldx<GBF_NT_ROWS>(row + tk) : -1;
-                }
-#pragma unroll
-                for (int k = 0; k < kRowBatch; ++k)
-                    if (y[k] >= 0) mx = T::max2(mx, V[y[k]]);
-            }
+            for (uint32_t t = (uint32_t)sub; t < len; t += kRowBatch * G)
+                row_batch<T, kRowBatch, G, false>(row, nullptr, V, t, len, mx, mw);
         } else {
             // the box is w1*w2*w3 rows of w0 consecutive cells along axis 0;
             // the G lanes of the group take the rows in turn
@@ -1357,15 +1370,18 @@ __device__ __forceinline__ PairVal<T> pair_gather(const Inst* __restrict__ It, c
                            st3 = (uint32_t)I.strides[3];
             const uint32_t nrows = w1 * w2 * (uint32_t)(d.e[3] + 1);
             len = w0 * nrows;
+            // the first three cells of a row are read with clamped offsets (a
+            // repeated cell leaves the max unchanged), so that the three loads
+            // carry no branch and issue together
+            const uint32_t c1 = min(1u, w0 - 1u), c2 = min(2u, w0 - 1u);
             for (uint32_t r = (uint32_t)sub; r < nrows; r += G) {
                 const uint32_t r2 = r / w1;
                 const uint32_t j1 = r - r2 * w1;
                 const uint32_t j3 = r2 / w2;
                 const uint32_t j2 = r2 - j3 * w2;
                 const GBF_GLOBAL K* row = V + (lo + j1 * st1 + j2 * st2 + j3 * st3);
-                K m0 = row[0];
-                if (w0 > 1) m0 = T::max2(m0, row[1]);
-                if (w0 > 2) m0 = T::max2(m0, row[2]);
+                const K a0 = row[0], a1 = row[c1], a2 = row[c2];
+                K m0 = T::max2(a0, T::max2(a1, a2));
                 for (uint32_t j0 = 3; j0 < w0; ++j0) m0 = T::max2(m0, row[j0]);
                 mx = T::max2(mx, m0);
             }
@@ -1471,8 +1487,13 @@ __device__ __forceinline__ void relax_round(const Inst* __restrict__ It, const i
     }
 }
 
+// The CSR, HYB and per-edge variants are built for 64 VGPRs: 8 waves per
+// SIMD, so that the default grid (8 blocks of 4 waves per CU) is resident
+// in one pass.  The variants that decode forward boxes need about twice
+// that and run at 4.
 template <class T, bool MULTI, int ENC, int G, bool WIDE = false>
-__global__ __launch_bounds__(kBlock) void k_relax(const Inst* __restrict__ It, Run R, int round) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ENC == 2 || ENC == 3 ? 4 : 8)))
+void k_relax(const Inst* __restrict__ It, Run R, int round) {
     __shared__ int64_t s_bases[MULTI ? kMaxBatch : 1];
     const typename Ids<WIDE>::id_t count = Ids<WIDE>::counts(R)[round];
     if (count == 0) return;
