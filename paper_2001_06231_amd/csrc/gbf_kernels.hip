@@ -24,6 +24,7 @@
 // over the byte map driven by per-state keys) change only the work, never
 // the result.
 #include <cstring>
+#include <type_traits>
 
 #include "gbf_device.h"
 #include "gbf_internal.h"
@@ -48,13 +49,16 @@
 #define GBF_EXP_BATCH 4  // reverse-row slices of 64 loaded together when expanding a state
 #endif
 #ifndef GBF_ROW_BATCH
-#define GBF_ROW_BATCH 4  // successor indices loaded together per lane (CSR relax)
+#define GBF_ROW_BATCH 6  // successor indices loaded together per lane at most (CSR relax)
 #endif
 #ifndef GBF_SMALL_LDS
 #define GBF_SMALL_LDS 1  // single-block mode on small CSR instances keeps V, frontiers and list in LDS
 #endif
 #ifndef GBF_ILP
 #define GBF_ILP 1  // wave steps whose gathers a host-loop relax wave keeps in flight together (2+ measured slower)
+#endif
+#ifndef GBF_EDGE_BATCH
+#define GBF_EDGE_BATCH 4  // successor indices and edge costs loaded together per lane (per-edge costs)
 #endif
 #ifndef GBF_XCD_BARRIER
 #define GBF_XCD_BARRIER 1  // persistent kernel: one L2 write-back per XCD and barrier
@@ -67,6 +71,7 @@ namespace gbf {
 
 constexpr int kExpBatch = GBF_EXP_BATCH;
 constexpr int kRowBatch = GBF_ROW_BATCH;
+constexpr int kEdgeBatch = GBF_EDGE_BATCH;
 constexpr int kILP = GBF_ILP;
 
 template <bool NT, class P>
@@ -789,6 +794,55 @@ __device__ __forceinline__ void mark_row(const Inst& I, uint8_t* __restrict__ di
     for (uint32_t t0 = 0; t0 < len; t0 += kWave * kExpBatch) mark_slices<kExpBatch, Id>(I, dirty, base, t0, len, entry);
 }
 
+// Bounds of the reverse row of state y: 64-bit rows start at a 64-bit
+// offset.
+template <bool WIDE>
+struct RevRow {
+    typename std::conditional<WIDE, uint64_t, uint32_t>::type s0;
+    uint32_t len;
+};
+template <bool WIDE>
+__device__ __forceinline__ RevRow<WIDE> rev_bounds(const Inst& I, int64_t y) {
+    RevRow<WIDE> r;
+    if constexpr (WIDE) {
+        const GBF_GLOBAL uint64_t* rptr = gp(I.rptr64);
+        r.s0 = rptr[y];
+        r.len = (uint32_t)(rptr[y + 1] - r.s0);
+    } else {
+        const GBF_GLOBAL uint32_t* rptr = gp(I.rptr);
+        r.s0 = rptr[y];
+        r.len = rptr[y + 1] - r.s0;
+    }
+    return r;
+}
+
+// Marks every pair of the reverse row of y (wave-uniform arguments).
+// 64-bit reverse rows hold each predecessor pair as its id minus y*K.
+template <bool WIDE>
+__device__ __forceinline__ void expand_rev(const Inst& I, int64_t y, const RevRow<WIDE>& rr,
+                                           uint8_t* __restrict__ dirty, Acc& acc) {
+    using Id = typename Ids<WIDE>::id_t;
+    const Id base = (Id)I.pair_base;
+    const auto s0 = rr.s0;
+    const uint32_t len = rr.len;
+    if (lane_id() == 0) {
+        acc.expanded += 1;
+        acc.marks += len;
+    }
+    if constexpr (WIDE) {
+        const GBF_GLOBAL int32_t* rel = gp(I.rrel);
+        const int64_t yK = y * (int64_t)I.K;
+        mark_row<Id>(I, dirty, base, len,
+                     [&](uint32_t t) { return (Id)(yK + (int64_t)ldx<GBF_NT_MISC>(rel + s0 + t)); });
+    } else {
+        // kExpBatch slices of 64 entries per step: all their reverse
+        // entries, then all their dirty bytes, are loaded before any store
+        const GBF_GLOBAL uint32_t* rev = gp(I.rev);
+        mark_row<uint32_t>(I, dirty, (uint32_t)base, len,
+                           [&](uint32_t t) { return ldx<GBF_NT_MISC>(rev + s0 + t); });
+    }
+}
+
 // Whole-wave expansion of one state y (wave-uniform arguments): every live
 // pair (x',u') with y in F(x',u') is marked.  CSR: the (sorted) reverse row
 // of y is streamed by the wave.  BOX: for every input the predecessor
@@ -798,33 +852,9 @@ __device__ __forceinline__ void expand_state(const Inst& I, int64_t y, uint8_t* 
     using Id = typename Ids<WIDE>::id_t;
     const int lane = lane_id();
     const Id base = (Id)I.pair_base;
-    if (WIDE && rev_csr<ENC>(I)) {
-        // 64-bit reverse rows hold each predecessor pair as its id minus y*K
-        const GBF_GLOBAL uint64_t* rptr = gp(I.rptr64);
-        const GBF_GLOBAL int32_t* rel = gp(I.rrel);
-        const uint64_t s0 = rptr[y];
-        const uint32_t len = (uint32_t)(rptr[y + 1] - s0);
-        const int64_t yK = y * (int64_t)I.K;
-        if (lane == 0) {
-            acc.expanded += 1;
-            acc.marks += len;
-        }
-        mark_row<Id>(I, dirty, base, len,
-                     [&](uint32_t t) { return (Id)(yK + (int64_t)ldx<GBF_NT_MISC>(rel + s0 + t)); });
-        return;
-    }
     if (rev_csr<ENC>(I)) {
-        const GBF_GLOBAL uint32_t* rptr = gp(I.rptr);
-        const GBF_GLOBAL uint32_t* rev = gp(I.rev);
-        const uint32_t s0 = rptr[y], len = rptr[y + 1] - s0;
-        if (lane == 0) {
-            acc.expanded += 1;
-            acc.marks += len;
-        }
-        // kExpBatch slices of 64 entries per step: all their reverse
-        // entries, then all their dirty bytes, are loaded before any store
-        mark_row<uint32_t>(I, dirty, (uint32_t)base, len,
-                           [&](uint32_t t) { return ldx<GBF_NT_MISC>(rev + s0 + t); });
+        const RevRow<WIDE> rr = rev_bounds<WIDE>(I, y);
+        expand_rev<WIDE>(I, y, rr, dirty, acc);
         return;
     }
     int yc[4];
@@ -1330,6 +1360,22 @@ __device__ __forceinline__ void row_batch(const GBF_GLOBAL int32_t* row, const G
     }
 }
 
+// The batch size is the largest number of entries any lane of the wave has
+// left in this step (wave-uniform), so that no load instruction is issued
+// for lanes that all ran past their rows.
+template <class T, int NK, int G, bool EDGE>
+__device__ __forceinline__ void row_step(const GBF_GLOBAL int32_t* row, const GBF_GLOBAL int32_t* hrow,
+                                         const GBF_GLOBAL typename T::key_t* V, uint32_t t, uint32_t len,
+                                         typename T::key_t& mx, typename T::wide_t& mw) {
+    if constexpr (NK > 1) {
+        if (!__ballot(t + (uint32_t)((NK - 1) * G) < len)) {
+            row_step<T, NK - 1, G, EDGE>(row, hrow, V, t, len, mx, mw);
+            return;
+        }
+    }
+    row_batch<T, NK, G, EDGE>(row, hrow, V, t, len, mx, mw);
+}
+
 // Gather phase of one wave step (64/G pairs, G lanes each): loads only, so
 // the gathers of several wave steps can be in flight together.
 template <class T, bool MULTI, int ENC, int G, bool WIDE = false>
@@ -1354,13 +1400,13 @@ __device__ __forceinline__ PairVal<T> pair_gather(const Inst* __restrict__ It, c
             // per-edge costs: the row's h values stream beside its indices
             const GBF_GLOBAL int32_t* row = gp(I.sidx) + c.s0;
             const GBF_GLOBAL int32_t* hrow = gp(I.ge) + c.s0;
-            for (uint32_t t = (uint32_t)sub; t < len; t += kRowBatch * G)
-                row_batch<T, kRowBatch, G, true>(row, hrow, V, t, len, mx, mw);
+            for (uint32_t t = (uint32_t)sub; t < len; t += kEdgeBatch * G)
+                row_batch<T, kEdgeBatch, G, true>(row, hrow, V, t, len, mx, mw);
         } else if (fwd_csr<ENC>(I)) {
             // kRowBatch successor indices per lane in flight, then their values
             const GBF_GLOBAL int32_t* row = gp(I.sidx) + c.s0;
             for (uint32_t t = (uint32_t)sub; t < len; t += kRowBatch * G)
-                row_batch<T, kRowBatch, G, false>(row, nullptr, V, t, len, mx, mw);
+                row_step<T, kRowBatch, G, false>(row, nullptr, V, t, len, mx, mw);
         } else {
             // the box is w1*w2*w3 rows of w0 consecutive cells along axis 0;
             // the G lanes of the group take the rows in turn
@@ -1449,6 +1495,7 @@ __device__ __forceinline__ void pair_commit(const Inst* __restrict__ It, const P
         expand = true;
     }
     unsigned long long bal = __ballot(expand);
+    if (!bal) return;
     while (bal) {
         const int l = __ffsll(bal) - 1;
         bal &= bal - 1;
