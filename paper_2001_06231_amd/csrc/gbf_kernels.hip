@@ -57,6 +57,9 @@
 #ifndef GBF_ILP
 #define GBF_ILP 1  // wave steps whose gathers a host-loop relax wave keeps in flight together (2+ measured slower)
 #endif
+#ifndef GBF_XCD_MAP
+#define GBF_XCD_MAP 1  // host-loop relax: the blocks of each XCD take one contiguous part of the list
+#endif
 #ifndef GBF_EDGE_BATCH
 #define GBF_EDGE_BATCH 4  // successor indices and edge costs loaded together per lane (per-edge costs)
 #endif
@@ -72,6 +75,7 @@ namespace gbf {
 constexpr int kExpBatch = GBF_EXP_BATCH;
 constexpr int kRowBatch = GBF_ROW_BATCH;
 constexpr int kEdgeBatch = GBF_EDGE_BATCH;
+constexpr int kXcdParts = 8;  // XCDs of an MI355X
 constexpr int kILP = GBF_ILP;
 
 template <bool NT, class P>
@@ -1512,16 +1516,32 @@ __device__ __forceinline__ void pair_commit(const Inst* __restrict__ It, const P
 // One round over the listed pairs.  Each wave takes ILP consecutive wave
 // steps at a time: their loads are issued before any commit, so ILP times
 // as many gathers are in flight per wave.
-template <class T, bool MULTI, int ENC, int G, int ILP, int SCOPE = __HIP_MEMORY_SCOPE_AGENT, bool WIDE = false>
+template <class T, bool MULTI, int ENC, int G, int ILP, int SCOPE = __HIP_MEMORY_SCOPE_AGENT, bool WIDE = false,
+          bool XMAP = false>
 __device__ __forceinline__ void relax_round(const Inst* __restrict__ It, const int64_t* bases, const Run& R,
                                             typename Ids<WIDE>::id_t count, int round, Acc& acc) {
     using Id = typename Ids<WIDE>::id_t;
     constexpr Id W = kWave / G;  // pairs per wave and step
     uint8_t* next = R.dirty[(round + 1) & 1];
     const Id wpb = blockDim.x / kWave;
-    const Id wave = (Id)blockIdx.x * wpb + threadIdx.x / kWave;
-    const Id stride = (Id)gridDim.x * wpb * W * ILP;
-    for (Id first = wave * W * ILP; first < count; first += stride) {
+    Id wave = (Id)blockIdx.x * wpb + threadIdx.x / kWave;
+    Id stride = (Id)gridDim.x * wpb * W * ILP;
+    Id lo = 0;
+    if constexpr (XMAP) {
+        // blocks b with b % kXcdParts == k take the k-th contiguous part of
+        // the (ascending) list.  The hardware deals consecutive blocks to the
+        // XCDs in turn (block b runs on XCD b % 8, read back from the XCC id
+        // register on MI355X), so each XCD's L2 sees about one part of V and
+        // of the maps: in a batch, a few instances per XCD.  Every part is
+        // covered whatever the placement, so results never depend on it.
+        const Id part = (Id)(blockIdx.x % kXcdParts);
+        const Id nbp = (Id)(gridDim.x / kXcdParts);
+        lo = (Id)((uint64_t)count * (uint64_t)part / kXcdParts);
+        count = (Id)((uint64_t)count * (uint64_t)(part + 1) / kXcdParts);
+        wave = (Id)(blockIdx.x / kXcdParts) * wpb + threadIdx.x / kWave;
+        stride = nbp * wpb * W * ILP;
+    }
+    for (Id first = lo + wave * W * ILP; first < count; first += stride) {
         PairCtx<WIDE> c[ILP];
         PairVal<T> v[ILP];
 #pragma unroll
@@ -1551,7 +1571,10 @@ void k_relax(const Inst* __restrict__ It, Run R, int round) {
     __shared__ AccLds s_acc;
     acc_init(s_acc);
     Acc acc;
-    relax_round<T, MULTI, ENC, G, kILP, __HIP_MEMORY_SCOPE_AGENT, WIDE>(It, s_bases, R, count, round, acc);
+    if (GBF_XCD_MAP && gridDim.x % kXcdParts == 0)
+        relax_round<T, MULTI, ENC, G, kILP, __HIP_MEMORY_SCOPE_AGENT, WIDE, true>(It, s_bases, R, count, round, acc);
+    else
+        relax_round<T, MULTI, ENC, G, kILP, __HIP_MEMORY_SCOPE_AGENT, WIDE>(It, s_bases, R, count, round, acc);
     flush_acc(acc, s_acc, R.slots);
 }
 
