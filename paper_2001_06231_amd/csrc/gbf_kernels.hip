@@ -89,6 +89,10 @@ __device__ __forceinline__ P ldx(const GBF_GLOBAL P* p) {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
+#ifndef GBF_RELAX_BLOCK
+#define GBF_RELAX_BLOCK 512  // threads per block of the host-loop relax kernel (measured: 256 and 1024 3-5% slower)
+#endif
+constexpr int kRelaxBlock = GBF_RELAX_BLOCK;
 
 // Per-lane statistics (32-bit; folded into the wave's 64-bit LDS slot after
 // every round, so they cannot overflow).
@@ -1588,7 +1592,7 @@ __device__ __forceinline__ void relax_round(const Inst* __restrict__ It, const i
 // in one pass.  The variants that decode forward boxes need about twice
 // that and run at 4.
 template <class T, bool MULTI, int ENC, int G, bool WIDE = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ENC == 2 || ENC == 3 ? 4 : 8)))
+__global__ __launch_bounds__(kRelaxBlock) __attribute__((amdgpu_waves_per_eu(ENC == 2 || ENC == 3 ? 4 : 8)))
 void k_relax(const Inst* __restrict__ It, Run R, int round) {
     __shared__ int64_t s_bases[MULTI ? kMaxBatch : 1];
     const typename Ids<WIDE>::id_t count = Ids<WIDE>::counts(R)[round];
@@ -2155,7 +2159,9 @@ hipError_t launch_relax(const Inst* dI, const Run& R, int round, int grid, int l
     PersistFn pf;
     if (wide) rf = pick_wide(dtype, enc_mask, lanes);
     else pick_all(R, dtype, enc_mask, lanes, &rf, &pf);
-    rf<<<grid > 0 ? std::min(grid, kMaxGrid) : 1024, kBlock, 0, s>>>(dI, R, round);
+    // `grid` counts kBlock-thread blocks; the relax kernel runs kRelaxBlock
+    const int g = grid > 0 ? std::min(grid, kMaxGrid) : 1024;
+    rf<<<std::max(1, g * kBlock / kRelaxBlock), kRelaxBlock, 0, s>>>(dI, R, round);
     return hipGetLastError();
 }
 
