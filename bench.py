@@ -325,7 +325,8 @@ def batch_compare(probs, reps=3):
     seq = [torch.empty_like(o) for o in outs]
     res = {"instances": len(probs), "n_states": int(sum(p.n for p in probs)),
            "pairs": int(sum(p.npairs for p in probs)),
-           "tuned": {k: tuned[k] for k in ("encoding", "mode", "lanes", "grid")}, "tune_s": tune_s}
+           "tuned": {k: tuned.get(k, 0) for k in ("encoding", "mode", "lanes", "grid", "block", "compact_grid")},
+           "tune_s": tune_s}
     exact = True
 
     def same():
@@ -340,7 +341,8 @@ def batch_compare(probs, reps=3):
         res[f"persistent_graph_{enc}_ms"] = per_ms
         res[f"graph_used_{enc}"] = int(per_stats[0]["graph_used"])
         if enc == tuned["encoding"]:
-            kw = dict(mode=tuned["mode"], lanes=tuned["lanes"], grid=tuned["grid"])
+            kw = dict(mode=tuned["mode"], lanes=tuned["lanes"], grid=tuned["grid"], block=tuned.get("block", 0),
+                      compact_grid=tuned.get("compact_grid", 0))
             bat_ms, (_, bat_stats, _) = wall(lambda: gbf.solve_batch(graphs, outs, **kw))
             exact = exact and same()
             prof = [gbf.solve_batch(graphs, outs, profile=True, **kw)[1][0] for _ in range(reps)]
@@ -356,7 +358,7 @@ def batch_compare(probs, reps=3):
                 o, _ = gbf.tune(graphs, reps=2, mode=mode)
                 ms, (_, fst, _) = wall(lambda: gbf.solve_batch(graphs, outs, **o))
                 exact = exact and same()
-                forms[mode] = {"ms": ms, "lanes": int(o["lanes"]), "grid": int(fst[0]["grid_used"]),
+                forms[mode] = {"ms": ms, "lanes": int(o["lanes"]), "block": int(o["block"]), "grid": int(fst[0]["grid_used"]),
                                "graph_used": int(fst[0]["graph_used"]), "barrier_ms": fst[0]["barrier_ms"]}
             res["best_hostloop"] = forms["hostloop"]
             res["best_persistent_graph"] = forms["persistent"]

@@ -190,6 +190,15 @@ typedef struct gbf_opts {
                                windows as the implicit form does
                                (gbf_stats.images_dropped, enc_used 1); the
                                values are the same.  0 = never. */
+    int32_t block;          /* host-loop mode: threads per block of the relax
+                               kernel, a multiple of 64 from 64 to 1024;
+                               0 = default (512).  `grid` still counts
+                               256-thread blocks: the launch has
+                               grid * 256 / block blocks. */
+    int32_t compact_grid;   /* host-loop mode: blocks of the frontier
+                               compaction (a frontier chunk is 16 pairs, a
+                               block scans 256 chunks per tile); 0 = default
+                               (512) */
 } gbf_opts;
 
 /* ---- statistics ------------------------------------------------------- */
@@ -215,8 +224,8 @@ typedef struct gbf_stats {
     double barrier_ms;      /* persistent mode: time block 0 spent in grid barriers */
     int64_t device_bytes;   /* device memory held by the graph handle */
     int32_t mode_used;      /* GBF_MODE_HOSTLOOP or GBF_MODE_PERSISTENT */
-    int32_t grid_used;
-    int32_t block_used;
+    int32_t grid_used;      /* host-loop mode: in 256-thread blocks (gbf_opts.grid) */
+    int32_t block_used;     /* threads per block of the relax (host loop) or round kernel */
     int32_t lanes_used;
     int32_t graph_used;     /* 1 = batched solve replayed from a HIP graph */
     int32_t sweeps;         /* bucket order: ascending passes over the buckets */
@@ -295,10 +304,11 @@ int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gbf_opts* opt
                     void* const* V_outs, gbf_stats* st);
 
 /* Autotuner: times gbf_solve (count == 1) or gbf_solve_batch (count > 1)
- * on the given handles for each candidate launch configuration (lanes per
- * pair 2/4/8 x relax grid 4/8/16 blocks per CU in host-loop mode, lanes
- * 2/4/8 in persistent mode, and for one instance of at most 262144 pairs
- * lanes 2/4/8 in single-block mode) and writes the fastest into *best (the other
+ * on the given handles for each candidate launch configuration (host-loop
+ * mode: lanes per pair 2/4/8 x relax grid 4/8/16 256-thread blocks per CU x
+ * relax block 256/512/1024 threads, then the compaction grid 256/512/1024
+ * blocks for the best of those; persistent mode: lanes 2/4/8; for one
+ * instance of at most 262144 pairs, single-block mode: lanes 2/4/8) and writes the fastest into *best (the other
  * fields are copied from `base`, which may be NULL).  Each candidate runs
  * one untimed and `reps` (0 = 3) timed solves; the median decides.
  * best_ms (may be NULL) receives its median solve time.  A base->mode

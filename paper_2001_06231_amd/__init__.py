@@ -71,7 +71,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("mode", ctypes.c_int32), ("bucket_key", ctypes.c_void_p),
                 ("max_rounds", ctypes.c_int64), ("lanes", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("v_memspace", ctypes.c_int32), ("profile", ctypes.c_int32), ("batch_hint", ctypes.c_int32),
-                ("bucket_span", ctypes.c_int32), ("bucket_budget", ctypes.c_int32), ("mem_floor_mib", ctypes.c_int32)]
+                ("bucket_span", ctypes.c_int32), ("bucket_budget", ctypes.c_int32), ("mem_floor_mib", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("compact_grid", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -221,9 +222,11 @@ class Graph:
             self._h = None
 
     def _opts(self, order, mode, max_rounds, grid, profile, bucket_key, v_space, lanes=0, bucket_span=0,
-              bucket_budget=0, mem_floor_mib=0):
+              bucket_budget=0, mem_floor_mib=0, block=0, compact_grid=0):
         o = _Opts()
         o.mem_floor_mib = int(mem_floor_mib)
+        o.block = int(block)
+        o.compact_grid = int(compact_grid)
         o.lanes = int(lanes)
         o.bucket_span = int(bucket_span)
         o.bucket_budget = int(bucket_budget)
@@ -242,7 +245,8 @@ class Graph:
         return o
 
     def solve(self, V_out=None, *, order="plain", mode="auto", max_rounds=0, grid=0, profile=False,
-              bucket_key=None, lanes=0, bucket_span=0, bucket_budget=0, mem_floor_mib=0, check=True):
+              bucket_key=None, lanes=0, bucket_span=0, bucket_budget=0, mem_floor_mib=0, block=0, compact_grid=0,
+              check=True):
         """Runs the solver; returns (status, stats dict, V_out).  V_out may be
         a numpy array (host) or a torch tensor on the GPU; if None a numpy
         array is allocated."""
@@ -251,14 +255,15 @@ class Graph:
             V_out = np.empty(self.n, dtype=np.int32 if self.dtype == I32 else np.float32)
         vp, vs = _ptr(V_out)
         o = self._opts(order, mode, max_rounds, grid, profile, bucket_key, vs, lanes, bucket_span, bucket_budget,
-                       mem_floor_mib)
+                       mem_floor_mib, block, compact_grid)
         st = _Stats()
         rc = L.gbf_solve(self._h, ctypes.byref(o), vp, ctypes.byref(st))
         if rc < 0 or (check and rc not in (OK, ENEGCYCLE)):
             raise _err(L, rc)
         return rc, st.as_dict(), V_out
 
-    def solve_noalloc(self, V_out=None, *, mode="auto", max_rounds=0, grid=0, lanes=0, check=True):
+    def solve_noalloc(self, V_out=None, *, mode="auto", max_rounds=0, grid=0, lanes=0, block=0, compact_grid=0,
+                      check=True):
         """gbf_solve_noalloc: the plain-order solve with all scratch in the
         library's static device array (no allocation in the call).  Returns
         (status, stats dict, V_out) as solve()."""
@@ -266,7 +271,7 @@ class Graph:
         if V_out is None:
             V_out = np.empty(self.n, dtype=np.int32 if self.dtype == I32 else np.float32)
         vp, vs = _ptr(V_out)
-        o = self._opts("plain", mode, max_rounds, grid, False, None, vs, lanes, 0)
+        o = self._opts("plain", mode, max_rounds, grid, False, None, vs, lanes, 0, 0, 0, block, compact_grid)
         st = _Stats()
         rc = L.gbf_solve_noalloc(self._h, ctypes.byref(o), vp, ctypes.byref(st))
         if rc < 0 or (check and rc not in (OK, ENEGCYCLE)):
@@ -376,7 +381,7 @@ def load_problem(prob, encoding="csr", stream=None, mem_budget=0, pair_ids64=Fal
 
 
 def solve_batch(graphs: Sequence[Graph], V_outs=None, *, mode="auto", max_rounds=0, grid=0, profile=False,
-                lanes=0, check=True):
+                lanes=0, block=0, compact_grid=0, check=True):
     """gbf_solve_batch: one frontier over all instances.  Returns (worst
     status, list of per-instance stats, V_outs)."""
     L = lib()
@@ -392,6 +397,8 @@ def solve_batch(graphs: Sequence[Graph], V_outs=None, *, mode="auto", max_rounds
     o.max_rounds = int(max_rounds)
     o.grid = int(grid)
     o.lanes = int(lanes)
+    o.block = int(block)
+    o.compact_grid = int(compact_grid)
     o.profile = 1 if profile else 0
     o.v_memspace = spaces.pop()
     hs = (ctypes.c_void_p * cnt)(*[gr._h for gr in graphs])
@@ -419,7 +426,8 @@ def tune(graphs: Sequence[Graph], reps=3, order="plain", bucket_key=None, bucket
     rc = L.gbf_tune(hs, cnt, ctypes.byref(base), int(reps), ctypes.byref(best), ctypes.byref(ms))
     if rc != OK:
         raise _err(L, rc)
-    return {"mode": _MODE_NAMES[best.mode], "lanes": best.lanes, "grid": best.grid}, ms.value
+    return {"mode": _MODE_NAMES[best.mode], "lanes": best.lanes, "grid": best.grid, "block": best.block,
+            "compact_grid": best.compact_grid}, ms.value
 
 
 # ---------------------------------------------------------------------------

@@ -1,8 +1,11 @@
 """Autotuner: picks the successor encoding and the launch configuration for
 a problem set (one problem, or the instances of a batch).
 
-For each candidate encoding the set is loaded and gbf_tune (include/gbf.h)
-times the launch configurations on the device; the fastest (encoding,
+Every candidate encoding (explicit lists, box successors with predecessor
+images, implicit boxes) is first screened with one solve at the library's
+defaults; for the `finalists` fastest the set is loaded and gbf_tune
+(include/gbf.h) times the launch configurations on the device (mode, lanes
+per pair, relax grid and block, compaction grid); the fastest (encoding,
 configuration) wins.  Results can be kept in a JSON cache keyed by the
 shape of the set (grid dims, inputs and value type of every instance), so a
 workload is tuned once.
@@ -13,9 +16,11 @@ import hashlib
 import json
 import os
 
-from . import load_problem, tune
+import time
 
-ENCODINGS = ("csr", "box+rev")
+from . import load_problem, solve_batch, tune
+
+ENCODINGS = ("csr", "box+rev", "box")
 
 
 def signature(probs) -> str:
@@ -35,6 +40,24 @@ def _measure(probs, encoding, reps, mode):
             g.free()
 
 
+def _screen(probs, encoding, mode):
+    """Solve time of the set in one encoding at the library's defaults (one
+    untimed and one timed call)."""
+    graphs = [load_problem(p, encoding=encoding) for p in probs]
+    try:
+        def run():
+            if len(graphs) == 1:
+                return graphs[0].solve(mode=mode)
+            return solve_batch(graphs, mode=mode)
+        run()
+        t0 = time.perf_counter()
+        run()
+        return 1e3 * (time.perf_counter() - t0)
+    finally:
+        for g in graphs:
+            g.free()
+
+
 def _load_cache(path):
     if path and os.path.exists(path):
         with open(path) as f:
@@ -42,20 +65,28 @@ def _load_cache(path):
     return {}
 
 
-def autotune(probs, encodings=ENCODINGS, reps=3, cache=None, log=None, mode="auto"):
-    """Returns {"encoding", "mode", "lanes", "grid", "ms"} for the set, over
-    every launch mode or within `mode`.  `cache`: path of a JSON file (read
-    and updated), or None."""
+def autotune(probs, encodings=ENCODINGS, reps=3, cache=None, log=None, mode="auto", finalists=2):
+    """Returns {"encoding", "mode", "lanes", "grid", "block", "compact_grid",
+    "ms"} for the set, over every launch mode or within `mode`.  `cache`:
+    path of a JSON file (read and updated), or None."""
     key = signature(probs) + ("" if mode == "auto" else f":{mode}")
     table = _load_cache(cache)
     if key in table:
         return table[key]
     best = None
+    cands = []
     for enc in encodings:
         if enc != "csr" and any(getattr(p, "box_lo", None) is None for p in probs):
             continue  # no boxes: only explicit successor lists
         if enc != "csr" and any(getattr(p, "g_edge", None) is not None for p in probs):
             continue  # per-edge costs are attached to explicit successor lists
+        cands.append(enc)
+    if len(cands) > finalists:
+        screen = {enc: _screen(probs, enc, mode) for enc in cands}
+        if log:
+            log("screen: " + ", ".join(f"{e} {t:.3f} ms" for e, t in screen.items()))
+        cands = sorted(cands, key=lambda e: screen[e])[:finalists]
+    for enc in cands:
         opts, ms = _measure(probs, enc, reps, mode)
         if log:
             log(f"tune {enc}: {opts} {ms:.3f} ms")

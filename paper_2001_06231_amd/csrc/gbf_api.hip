@@ -608,6 +608,7 @@ struct Plan {
     int ninst = 0;
     int64_t max_rounds = 0, max_states = 0;
     int enc_mask = 0, lanes = 4, mode = GBF_MODE_HOSTLOOP, grid = 0, dtype = 0;
+    int block = 0, compact_grid = 0;  // host loop: relax block (threads), compaction grid; 0 = defaults
     bool bucket = false;
     bool wide = false;  // 64-bit pair ids
     // bucket order: work budget (pair evaluations, rounds) after which the
@@ -703,6 +704,11 @@ static int plan_solve(Scratch& S, const Inst* insts, int ninst, int dtype, const
     P.lanes = (o.lanes == 1 || o.lanes == 2 || o.lanes == 4 || o.lanes == 8 || o.lanes == 16 || o.lanes == 32)
                   ? o.lanes
                   : 4;
+    if (o.block != 0 && (o.block < 64 || o.block > 1024 || o.block % 64 != 0))
+        return fail(GBF_EINVAL, "block must be 0 or a multiple of 64 from 64 to 1024");
+    if (o.compact_grid < 0) return fail(GBF_EINVAL, "compact_grid must be >= 0");
+    P.block = o.block;
+    P.compact_grid = o.compact_grid;
     P.mode = (P.bucket || P.wide) ? GBF_MODE_HOSTLOOP : o.mode;
     if (P.mode == GBF_MODE_SINGLE_BLOCK && P.ninst != 1)
         return fail(GBF_EINVAL, "single-block mode solves one instance");
@@ -782,7 +788,7 @@ static void read_host(const Scratch& S, const Plan& P, SolveOut& out, bool round
     out.sweeps = P.bucket ? host[8] : 0;
     out.mode = P.mode;
     out.grid = P.grid;
-    out.block = P.mode == GBF_MODE_HOSTLOOP ? 256 : 1024;
+    out.block = P.mode == GBF_MODE_HOSTLOOP ? (P.block > 0 ? P.block : kRelaxBlock) : 1024;
     out.lanes = P.lanes;
 }
 
@@ -827,11 +833,11 @@ static int enqueue_hostloop(Scratch& S, const Plan& P, const gbf_opts& o, hipStr
             out.switched = 1;
         }
         for (int64_t k = 0; k < nb; ++k) {
-            if (P.bucket) HIPC(launch_bucket_compact(R, (int)(r + k), 0, s));
-            else HIPC(launch_compact(R, (int)(r + k), 0, s, P.wide));
+            if (P.bucket) HIPC(launch_bucket_compact(R, (int)(r + k), P.compact_grid, s));
+            else HIPC(launch_compact(R, (int)(r + k), P.compact_grid, s, P.wide));
             const bool timed = o.profile && ev + 1 < (int)S.events.size();
             if (timed) HIPC(hipEventRecord(S.events[ev], s));
-            HIPC(launch_relax(S.dinst, R, (int)(r + k), P.grid, P.lanes, P.dtype, enc_mask, s, P.wide));
+            HIPC(launch_relax(S.dinst, R, (int)(r + k), P.grid, P.lanes, P.dtype, enc_mask, s, P.wide, P.block));
             if (timed) {
                 HIPC(hipEventRecord(S.events[ev + 1], s));
                 ev += 2;
@@ -1415,7 +1421,7 @@ extern "C" int gbf_tune(gbf_graph* const* graphs, int32_t count, const gbf_opts*
     o.v_memspace = GBF_DEVICE;
     const int cus = graphs[0]->cus;
     struct Cand {
-        int mode, lanes, grid;
+        int mode, lanes, grid, block, cgrid;
     };
     if (o.mode != GBF_MODE_AUTO && o.mode != GBF_MODE_HOSTLOOP && o.mode != GBF_MODE_PERSISTENT &&
         o.mode != GBF_MODE_SINGLE_BLOCK)
@@ -1424,23 +1430,29 @@ extern "C" int gbf_tune(gbf_graph* const* graphs, int32_t count, const gbf_opts*
     std::vector<Cand> cands;
     if (any || o.mode == GBF_MODE_HOSTLOOP)
         for (int lanes : {2, 4, 8})
-            for (int per_cu : {4, 8, 16}) cands.push_back({GBF_MODE_HOSTLOOP, lanes, per_cu * cus});
+            for (int per_cu : {4, 8, 16})
+                for (int block : {256, 512, 1024}) cands.push_back({GBF_MODE_HOSTLOOP, lanes, per_cu * cus, block, 0});
     if (o.order == GBF_ORDER_PLAIN && (any || o.mode == GBF_MODE_PERSISTENT))
-        for (int lanes : {2, 4, 8}) cands.push_back({GBF_MODE_PERSISTENT, lanes, 0});
+        for (int lanes : {2, 4, 8}) cands.push_back({GBF_MODE_PERSISTENT, lanes, 0, 0, 0});
     // one workgroup is only worth timing on small single instances
     if (o.order == GBF_ORDER_PLAIN && count == 1 && graphs[0]->n * graphs[0]->K <= 4 * kSingleBlockMaxPairs &&
         (any || o.mode == GBF_MODE_SINGLE_BLOCK))
-        for (int lanes : {2, 4, 8}) cands.push_back({GBF_MODE_SINGLE_BLOCK, lanes, 0});
+        for (int lanes : {2, 4, 8}) cands.push_back({GBF_MODE_SINGLE_BLOCK, lanes, 0, 0, 0});
     if (cands.empty()) return fail(GBF_EINVAL, "no candidate configuration for this mode and order");
     double best_t = 1e300;
     gbf_opts bo = o;
     bool found = false;
     std::vector<gbf_stats> st(count);
-    for (const Cand& c : cands) {
+    // second pass: the compaction grid of the best host-loop configuration
+    bool second = false;
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+        const Cand c = cands[ci];  // a copy: the second pass appends to cands
         gbf_opts t = o;
         t.mode = c.mode;
         t.lanes = c.lanes;
         t.grid = c.grid;
+        t.block = c.block;
+        t.compact_grid = c.cgrid;
         std::vector<double> ms;
         bool ok = true;
         for (int r = 0; r <= reps && ok; ++r) {
@@ -1456,6 +1468,10 @@ extern "C" int gbf_tune(gbf_graph* const* graphs, int32_t count, const gbf_opts*
             best_t = med;
             bo = t;
             found = true;
+        }
+        if (ci + 1 == cands.size() && !second && found && bo.mode == GBF_MODE_HOSTLOOP) {
+            second = true;
+            for (int cg : {256, 1024}) cands.push_back({GBF_MODE_HOSTLOOP, bo.lanes, bo.grid, bo.block, cg});
         }
     }
     if (!found) return fail(GBF_EHIP, "no candidate configuration ran");

@@ -71,6 +71,10 @@ int set_error(int code, const std::string& msg);
 constexpr int kMaxBatch = 1024;
 constexpr int kBarrierBytes = 4096;  // persistent mode: barrier words (see the grid barriers)
 constexpr int kMaxGrid = 8192;  // most blocks of any solver launch
+#ifndef GBF_RELAX_BLOCK
+#define GBF_RELAX_BLOCK 512  // default threads per block of the host-loop relax kernel (measured: 256 and 1024 3-5% slower)
+#endif
+constexpr int kRelaxBlock = GBF_RELAX_BLOCK;
 
 // Launch wrappers (all asynchronous on `s`).
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
@@ -97,7 +101,7 @@ hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s, bool
 hipError_t launch_bucket_compact(const Run& R, int round, int grid, hipStream_t s);
 // `lanes`: lanes per listed pair in the relax step (4, 8, 16 or 32)
 hipError_t launch_relax(const Inst* dI, const Run& R, int round, int grid, int lanes, int dtype, int enc_mask,
-                        hipStream_t s, bool wide = false);
+                        hipStream_t s, bool wide = false, int block = 0);
 // `attr_launch`: launch through hipLaunchKernelExC with the cooperative
 // attribute (the form that stream capture records as a graph node)
 hipError_t launch_persistent(const Inst* dI, const Run& R, int grid, int lanes, int dtype, int enc_mask,

@@ -89,10 +89,7 @@ __device__ __forceinline__ P ldx(const GBF_GLOBAL P* p) {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-#ifndef GBF_RELAX_BLOCK
-#define GBF_RELAX_BLOCK 512  // threads per block of the host-loop relax kernel (measured: 256 and 1024 3-5% slower)
-#endif
-constexpr int kRelaxBlock = GBF_RELAX_BLOCK;
+
 
 // Per-lane statistics (32-bit; folded into the wave's 64-bit LDS slot after
 // every round, so they cannot overflow).
@@ -1259,7 +1256,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_bucket(Run R, int round) {
 hipError_t launch_bucket_compact(const Run& R, int round, int grid, hipStream_t s) {
     k_bucket_select<<<1, 1024, 0, s>>>(R, round);
     const int64_t ntiles = (R.nchunks + kBlock - 1) / kBlock;
-    int g = (int)std::min<int64_t>(ntiles, grid > 0 ? grid : kCompactGrid);
+    int g = (int)std::min<int64_t>(ntiles, grid > 0 ? std::min(grid, kMaxGrid) : kCompactGrid);
     if (g < 1) g = 1;
     k_compact_bucket<<<g, kBlock, 0, s>>>(R, round);
     return hipGetLastError();
@@ -1267,7 +1264,7 @@ hipError_t launch_bucket_compact(const Run& R, int round, int grid, hipStream_t 
 
 hipError_t launch_compact(const Run& R, int round, int grid, hipStream_t s, bool wide) {
     const int64_t ntiles = (R.nchunks + kBlock - 1) / kBlock;
-    int g = (int)std::min<int64_t>(ntiles, grid > 0 ? grid : kCompactGrid);
+    int g = (int)std::min<int64_t>(ntiles, grid > 0 ? std::min(grid, kMaxGrid) : kCompactGrid);
     if (g < 1) g = 1;
     if (wide) k_compact<true><<<g, kBlock, 0, s>>>(R, round);
     else k_compact<false><<<g, kBlock, 0, s>>>(R, round);
@@ -1588,11 +1585,12 @@ __device__ __forceinline__ void relax_round(const Inst* __restrict__ It, const i
 }
 
 // The CSR, HYB and per-edge variants are built for 64 VGPRs: 8 waves per
-// SIMD, so that the default grid (8 blocks of 4 waves per CU) is resident
-// in one pass.  The variants that decode forward boxes need about twice
-// that and run at 4.
+// SIMD, so that the default grid (8 x 256 threads per CU) is resident in
+// one pass.  The variants that decode forward boxes need about twice that
+// and run at 4.  Blocks of any multiple of 64 threads up to 1024 (the
+// waves of a block are read from blockDim).
 template <class T, bool MULTI, int ENC, int G, bool WIDE = false>
-__global__ __launch_bounds__(kRelaxBlock) __attribute__((amdgpu_waves_per_eu(ENC == 2 || ENC == 3 ? 4 : 8)))
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(ENC == 2 || ENC == 3 ? 4 : 8)))
 void k_relax(const Inst* __restrict__ It, Run R, int round) {
     __shared__ int64_t s_bases[MULTI ? kMaxBatch : 1];
     const typename Ids<WIDE>::id_t count = Ids<WIDE>::counts(R)[round];
@@ -2154,14 +2152,18 @@ static RelaxFn pick_wide(int dtype, int enc_mask, int G) {
 }
 
 hipError_t launch_relax(const Inst* dI, const Run& R, int round, int grid, int lanes, int dtype, int enc_mask,
-                        hipStream_t s, bool wide) {
+                        hipStream_t s, bool wide, int block) {
     RelaxFn rf;
     PersistFn pf;
     if (wide) rf = pick_wide(dtype, enc_mask, lanes);
     else pick_all(R, dtype, enc_mask, lanes, &rf, &pf);
-    // `grid` counts kBlock-thread blocks; the relax kernel runs kRelaxBlock
+    // `grid` counts kBlock-thread blocks; the relax kernel runs `block`
+    // threads per block (any multiple of 64 up to 1024, default kRelaxBlock)
+    // in at most kMaxGrid blocks (one statistics slot each)
+    const int b = block > 0 ? block : kRelaxBlock;
     const int g = grid > 0 ? std::min(grid, kMaxGrid) : 1024;
-    rf<<<std::max(1, g * kBlock / kRelaxBlock), kRelaxBlock, 0, s>>>(dI, R, round);
+    const int nb = (int)std::min<int64_t>(kMaxGrid, std::max<int64_t>(1, (int64_t)g * kBlock / b));
+    rf<<<nb, b, 0, s>>>(dI, R, round);
     return hipGetLastError();
 }
 

@@ -73,3 +73,36 @@ def test_tune_within_a_mode():
     assert e.value.code == gbf.EINVAL
     g.free()
     g2.free()
+
+
+def test_relax_block_and_compaction_grid():
+    """The host-loop knobs the autotuner searches (relax block size, relax
+    grid, compaction grid) change the schedule only: every setting gives the
+    oracle's values, in one instance and in a batch; bad values are a clear
+    GBF_EINVAL."""
+    print("\n[case] relax block and compaction grid", flush=True)
+    import torch
+    prob = synth.grid4d(synth.instance_seed(60, 3), dims=(14, 11, 6, 4))
+    ref = oracle.solve(prob)
+    for enc in ("csr", "box+rev"):
+        g = gbf.load_problem(prob, encoding=enc)
+        for block in (64, 256, 512, 1024):
+            for grid, cg in ((0, 0), (8, 1), (4096, 7), (2048, 8192)):
+                st, s, V = g.solve(mode="hostloop", block=block, grid=grid, compact_grid=cg)
+                assert st == gbf.OK and np.array_equal(V, ref["V"]), (enc, block, grid, cg)
+                assert s["block_used"] == block
+        for bad in ({"block": 100}, {"block": 2048}, {"block": -64}, {"compact_grid": -1}):
+            with pytest.raises(gbf.GbfError) as e:
+                g.solve(mode="hostloop", **bad)
+            assert e.value.code == gbf.EINVAL, bad
+        g.free()
+    probs = [synth.grid4d(synth.instance_seed(60, 4 + i), dims=(9 + i, 8, 5, 3), K=8) for i in range(3)]
+    graphs = [gbf.load_problem(p, encoding="box+rev") for p in probs]
+    outs = [torch.empty(p.n, dtype=torch.int32, device="cuda") for p in probs]
+    for block in (128, 1024):
+        st, _, _ = gbf.solve_batch(graphs, outs, mode="hostloop", block=block, compact_grid=3)
+        assert st == gbf.OK
+        for p, v in zip(probs, outs):
+            assert np.array_equal(v.cpu().numpy(), oracle.solve(p)["V"]), block
+    for gr in graphs:
+        gr.free()

@@ -24,15 +24,18 @@ def test_choice_and_cache(tmp_path, monkeypatch):
                 {"csr": 5.0, "box+rev": 4.0}[enc])
 
     monkeypatch.setattr(T, "_measure", fake)
+    # screening at the defaults: the implicit boxes are slowest, so only the
+    # two others are tuned in full
+    monkeypatch.setattr(T, "_screen", lambda probs, enc, mode: {"csr": 6.0, "box+rev": 5.0, "box": 30.0}[enc])
     probs = [synth.grid2d_small()]
     cache = str(tmp_path / "tune.json")
     best = T.autotune(probs, cache=cache)
     assert best["encoding"] == "box+rev" and best["lanes"] == 2 and best["ms"] == 4.0
-    assert calls == ["csr", "box+rev"]
+    assert sorted(calls) == ["box+rev", "csr"]
     table = json.load(open(cache))
     assert table[T.signature(probs)] == best
     again = T.autotune(probs, cache=cache)
-    assert again == best and calls == ["csr", "box+rev"]  # served from the cache
+    assert again == best and sorted(calls) == ["box+rev", "csr"]  # served from the cache
 
 
 def test_lists_only_problem_skips_box(monkeypatch):
@@ -71,6 +74,7 @@ def test_mode_restricted_tuning_has_its_own_cache_entry(tmp_path, monkeypatch):
         return {"mode": "hostloop" if mode == "auto" else mode, "lanes": 2, "grid": 0}, 1.0
 
     monkeypatch.setattr(T, "_measure", fake)
+    monkeypatch.setattr(T, "_screen", lambda probs, enc, mode: {"csr": 1.0, "box+rev": 2.0, "box": 3.0}[enc])
     probs = [synth.grid2d_small()]
     cache = str(tmp_path / "tune.json")
     a = T.autotune(probs, cache=cache)
@@ -79,3 +83,28 @@ def test_mode_restricted_tuning_has_its_own_cache_entry(tmp_path, monkeypatch):
     assert set(seen) == {"auto", "persistent"}
     table = json.load(open(cache))
     assert table[T.signature(probs)] == a and table[T.signature(probs) + ":persistent"] == b
+
+
+def test_screening_keeps_the_finalists(monkeypatch):
+    """With three encodings and two finalists, the slowest at the defaults
+    is not tuned; with finalists=3 every encoding is."""
+    seen, screened = [], []
+
+    def screen(probs, enc, mode):
+        screened.append(enc)
+        return {"csr": 2.0, "box+rev": 1.0, "box": 9.0}[enc]
+
+    def fake(probs, enc, reps, mode):
+        seen.append(enc)
+        return {"mode": "hostloop", "lanes": 4, "grid": 2048, "block": 512, "compact_grid": 0}, {"csr": 2.0, "box+rev": 1.0, "box": 0.5}[enc]
+
+    monkeypatch.setattr(T, "_screen", screen)
+    monkeypatch.setattr(T, "_measure", fake)
+    probs = [synth.grid2d_small()]
+    best = T.autotune(probs)
+    assert sorted(screened) == ["box", "box+rev", "csr"] and sorted(seen) == ["box+rev", "csr"]
+    assert best["encoding"] == "box+rev"
+    seen.clear()
+    screened.clear()
+    best = T.autotune(probs, finalists=3)
+    assert screened == [] and sorted(seen) == ["box", "box+rev", "csr"] and best["encoding"] == "box"
