@@ -47,6 +47,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2001_06231_amd", "csrc", "gbf_kernels.hip
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "relax_traffic_grid4d_384k.txt")
 PER_EDGE_BYTES = {"csr": 8, "box->csr": 8, "box": 4, "box+rev": 4, "box:budget": 4, "csr_edge": 12}
 KERNEL_OF_MODE = {"persistent": "k_persistent", "single_block": "k_single", "hostloop": "k_relax"}
+REWARD_SEED = 7  # fire region of the chained reward workload
 
 
 def kernel_source_hash():
@@ -158,8 +159,17 @@ def cpu_job(spec):
     import numpy as np
 
     import oracle
+    import synth
     oracle.lib()
-    probs = [make_problem(k) for k in kinds]
+    probs = []
+    for k in kinds:
+        if k.startswith("reward:"):
+            # the second problem of the chained mission: its terminal cost is
+            # the oracle's value function of the first (solved off the clock)
+            p1 = make_problem(k[7:])
+            probs.append(synth.reward_problem(p1, oracle.solve(p1)["V"], REWARD_SEED))
+        else:
+            probs.append(make_problem(k))
     times, edges, pairs = [], [], []
     for _ in range(reps):
         t_sum, e_sum, p_sum = 0.0, 0, 0
@@ -187,6 +197,10 @@ CPU_SAMPLES = {
                                                   "single-precision operator (encoding-independent)"),
     "grid4d_384k_i32_csr_edge_costs": (["grid4d_i32_edge"], 1, None,
                                        "the full 4-D 40x40x24x10 int32 instance with per-edge costs, one solve"),
+    "grid4d_384k_i32_reward_chain": (["reward:grid4d_i32"], 1, None,
+                                     "the second problem of the chained mission on the 4-D 40x40x24x10 grid "
+                                     "(per-edge reward for the fire region, G2 = the oracle's V1 of the main "
+                                     "instance), one solve; the first problem is solved off the clock"),
     "batch64": ([f"batch:{i}" for i in range(0, 64, 4)], 1, None,
                 "16 of the 64 batch instances (every 4th: 4 2-D, 4 3-D, 8 4-D), one solve each; the rate is "
                 "their summed relaxations over their summed solve time"),
@@ -383,7 +397,7 @@ def run(args, pool=None):
     if not args.no_cpu:
         cpu_labels = ["main"] + ([] if args.no_extras else
                                  ["grid2d_64x64_i32_csr", "grid4d_384k_f32", "grid4d_384k_i32_csr_edge_costs",
-                                  "batch64", "learned"])
+                                  "grid4d_384k_i32_reward_chain", "batch64", "learned"])
         jobs["cpu"] = start_cpu_jobs(pool, cpu_labels)
     if not args.no_extras:
         for kind in ("grid2d", "grid4d_f32", "grid4d_i32_edge", "learned:1000"):
@@ -469,8 +483,10 @@ def run(args, pool=None):
         "device_bytes": int(stats[0]["device_bytes"]),
         "kernel_source_sha256_16": kernel_source_hash(),
     }
+    V1 = V.cpu().numpy()  # the main instance's value function: G2 of the chained reward workload
     graph.free()
     if not args.no_extras:
+        import synth
         from paper_2001_06231_amd import learn
         extras = {}
         p2 = jobs["grid2d"].get()
@@ -484,6 +500,13 @@ def run(args, pool=None):
         extras["grid4d_384k_f32_box"] = config_line(pf, "box")
         # the same graph with the running cost on the edges, g(x,u) + h(x,y,u)
         extras["grid4d_384k_i32_csr_edge_costs"] = config_line(pe, "csr")
+        # the chained mission (Sect. VI-A): fly to the fire region with the
+        # return problem's value function as terminal cost
+        pr = synth.reward_problem(prob, V1, REWARD_SEED)
+        extras["grid4d_384k_i32_reward_chain"] = config_line(pr, "csr")
+        extras["grid4d_384k_i32_reward_chain"].update(
+            {"fire_cells": int(pr.fire.sum()), "reward": int(pr.reward),
+             "negative_edges": int((pr.g_edge < 0).sum()), "first_problem_solve_ms": out["solve_ms"]})
         print("[bench] configs done", file=sys.stderr, flush=True)
         out["configs"] = extras
         out["batch64"] = batch_compare(jobs["batch"].get())
@@ -504,6 +527,7 @@ def run(args, pool=None):
             for k in ("grid4d_384k_i32_box+rev", "grid4d_384k_i32_box"):
                 attach_cpu(out["configs"][k], cpu, "main", info)
             attach_cpu(out["configs"]["grid4d_384k_i32_csr_edge_costs"], cpu, "grid4d_384k_i32_csr_edge_costs", info)
+            attach_cpu(out["configs"]["grid4d_384k_i32_reward_chain"], cpu, "grid4d_384k_i32_reward_chain", info)
             attach_cpu(out["batch64"], cpu, "batch64", info)
             if "plain" in out["learned"]:
                 attach_cpu(out["learned"], cpu, "learned", info)

@@ -642,6 +642,56 @@ def with_edge_costs(prob: Problem, seed: int, extra=(0, 4), keep_pair=True) -> P
     return q
 
 
+def fire_region(prob: Problem, seed: int, size: int = 6) -> np.ndarray:
+    """[n] bool: a planar block of cells (axes 0 and 1; size x size, at most
+    a third of each axis) over all headings and the upper half of the
+    speeds, away from the target: the stand-in for the paper's hot spot with
+    its water-drop speed range (Sect. VI-A)."""
+    N = prob.dims
+    size = max(2, min(size, N[0] // 3, N[1] // 3))
+    r = Stream(seed, 31)
+    tgt = np.asarray(prob.G) == 0 if prob.dtype == "i32" else np.asarray(prob.G) == 0.0
+    x = np.arange(prob.n, dtype=np.int64)
+    c0, c1 = x % N[0], (x // N[0]) % N[1]
+    c3 = x // (N[0] * N[1] * N[2])
+    for _ in range(1000):
+        f0 = int(r.integers(0, max(1, N[0] - size), 1)[0])
+        f1 = int(r.integers(0, max(1, N[1] - size), 1)[0])
+        reg = (c0 >= f0) & (c0 < f0 + size) & (c1 >= f1) & (c1 < f1 + size) & (c3 >= N[3] // 2)
+        if not (reg & tgt).any():
+            return reg & (np.asarray(prob.avoid) == 0)
+    raise ValueError("no fire region away from the target")
+
+
+def reward_problem(prob: Problem, V1: np.ndarray, seed: int, reward: int = 24) -> Problem:
+    """The second problem of a chained mission (Sect. VI-A: fly to the hot
+    spot, terminal cost G2 = V1 of the return problem), int32: the same
+    system and per-pair costs g, terminal cost G2 = V1, and per-edge costs
+    that reward entering the fire region and take the reward back on
+    leaving it, h(x,y,u) = R (1[x in fire] - 1[y in fire]).  The per-edge
+    part is a potential difference, so it telescopes along any path and adds
+    no negative cycle to the potential-form g; the paper's own reward (a
+    constant negative cost on every step into the region) would allow
+    negative cycles on a synthetic grid.  The fire mask is kept as
+    `fire`."""
+    import copy
+    assert prob.dtype == "i32"
+    prob.ensure_csr()
+    q = copy.copy(prob)
+    fire = fire_region(prob, seed)
+    ptr = np.asarray(prob.succ_ptr, dtype=np.int64)
+    idx = np.asarray(prob.succ_idx, dtype=np.int64)
+    src = np.repeat(np.arange(prob.npairs, dtype=np.int64) // prob.K, np.diff(ptr))
+    f = fire.astype(np.int64)
+    q.g_edge = (reward * (f[src] - f[idx])).astype(np.int32)
+    q.g = np.asarray(prob.g, dtype=np.int32).copy()
+    q.G = np.asarray(V1, dtype=np.int32).copy()
+    q.fire = fire
+    q.reward = reward
+    q.name = prob.name + "_reward"
+    return q
+
+
 def potential_small_edges(seed: int, n: int, K: int, max_succ: int = 3, dtype: str = "i32",
                           p_target: float = 0.3, zero_phi: bool = False) -> Problem:
     """Tiny random problem with per-edge costs in potential form (no

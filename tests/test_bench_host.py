@@ -68,3 +68,19 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, cwd=ROOT, timeout=120)
     assert r.returncode != 0 and "one GPU" in (r.stdout + r.stderr)
+
+
+def test_cpu_job_reward_chain(monkeypatch):
+    """The reward chain's CPU baseline times only the second problem, whose
+    terminal cost is the oracle's value function of the first."""
+    import numpy as np
+
+    import oracle
+    import synth
+    small = synth.grid4d(synth.instance_seed(2, 41), dims=(10, 9, 6, 4))
+    monkeypatch.setattr(bench, "make_problem", lambda kind: small)
+    label, r = bench.cpu_job(("reward", ["reward:grid4d_i32"], 1, None, None))
+    p2 = synth.reward_problem(small, oracle.solve(small)["V"], bench.REWARD_SEED)
+    want = oracle.solve(p2)["counters"]["edge_relax"]
+    assert label == "reward" and r["edge_relax"] == want and r["value"] > 0
+    assert np.array_equal(p2.G, oracle.solve(small)["V"])

@@ -223,6 +223,32 @@ def test_chained_solves():
     assert (r2["V"].astype(np.int64) <= r1["V"].astype(np.int64)).all()
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_reward_chain(mode):
+    """The chained reward workload (synth.reward_problem: G2 = V1 of the
+    return problem, per-edge reward for entering the fire region), the
+    second problem solved on the GPU with the oracle's V1 as G2: exact
+    against the oracle."""
+    p1 = synth.grid4d(synth.instance_seed(2, 41), dims=(16, 14, 8, 6))
+    r1 = oracle.solve(p1)
+    p2 = synth.reward_problem(p1, r1["V"], 101)
+    _case(f"reward chain 16x14x8x6 {mode}")
+    _exact(oracle.solve(p2), _solve(p2, mode=mode), f"reward-{mode}")
+
+
+def test_reward_chain_full_size():
+    """The same at 40x40x24x10, in the host-loop mode the bench times, with
+    G2 = the GPU's own V1 (the chain as the bench runs it; the GPU's V1 is
+    checked against the oracle's first)."""
+    p1 = synth.grid4d()
+    r1 = oracle.solve(p1)
+    _case("reward chain 40x40x24x10 hostloop")
+    st1 = _solve(p1, mode="hostloop")
+    _exact(r1, st1, "reward-full-1")
+    p2 = synth.reward_problem(p1, st1[2], 7)
+    _exact(oracle.solve(p2), _solve(p2, mode="hostloop"), "reward-full-2")
+
+
 @pytest.mark.parametrize("seed", range(16))
 def test_tiny_edges_arbitrary_sign(seed):
     """Per-edge costs of both signs, negative cycles possible: a diverging
