@@ -174,7 +174,7 @@ typedef struct gbf_opts {
                                plain solve, and twice its rounds; without
                                one, 16 evaluations per pair): past it, or
                                when from round 24 on the pair evaluations so
-                               far fall below half of that plain solve's at
+                               far fall below 0.6 of that plain solve's at
                                the same round (host-loop plain solves keep
                                that profile), the solve finishes in plain
                                order (gbf_stats.fallback 1).  0 = 100;
