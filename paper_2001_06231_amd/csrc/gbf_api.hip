@@ -228,8 +228,11 @@ static int ensure_scratch(Scratch& S, int64_t total_pairs, int64_t max_rounds, i
         S.host_bytes = hb;
     }
     while ((int)S.events.size() < nevents) {
+        // events 0 and 1 bracket a solve (1 is also waited on before the
+        // host reads results); the others only time launches, so they skip
+        // the system-scope fence (its cache write-back would be timed too)
         hipEvent_t e;
-        HIPC(hipEventCreate(&e));
+        HIPC(hipEventCreateWithFlags(&e, S.events.size() < 2 ? hipEventDefault : hipEventDisableSystemFence));
         S.events.push_back(e);
     }
     return GBF_OK;
