@@ -8,9 +8,11 @@
 // order.  Training: mean squared error on labelled samples, gradients by
 // the chain rule, Adam (Kingma & Ba 2015) on the fp32 master copy.
 //
-// The work is tiny next to a solve (about 8.8 kFLOP per cell), so it runs on
-// the vector ALUs: keeping the activations in fp32 makes the predicted keys
-// insensitive to an extra bf16 rounding of the hidden layers.
+// Inference (k_vhat, about 8.8 kFLOP per cell) runs layers 1 and 2 on the
+// matrix cores: layer 1 in fp32, layer 2 in bf16 with each hidden activation
+// split into two bf16 terms, so that the keys match the fp32 network's.
+// Training (k_grad, k_reduce) is a few kFLOP per sample and runs on the
+// vector ALUs in fp32.
 //
 // Parameter vector (4545 floats): W1 [64][4], b1 [64], W2 [64][64] (W2[j][k]
 // feeds h1[k] into unit j), b2 [64], W3 [64], b3.
