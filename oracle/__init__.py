@@ -29,6 +29,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gbf_oracle.c")
+_SRC_AC = os.path.join(_HERE, "aircraft.c")
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 OK, NEGCYCLE = 0, 1
@@ -52,7 +53,7 @@ def build() -> str:
     """Compile the oracle with gcc (no fast-math, no FP contraction)."""
     tmp = LIB_PATH + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                           "-shared", "-o", tmp, _SRC, "-lm"])
+                           "-shared", "-o", tmp, _SRC, _SRC_AC, "-lm"])
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -75,6 +76,19 @@ def _bind(L):
     L.oracle_dijkstra_i32.restype = ctypes.c_int
     L.oracle_residual_box_sample.argtypes = [P, i64, P, i64, P, P, P, P, P, P]
     L.oracle_residual_box_sample.restype = i64
+    d = ctypes.c_double
+    i32 = ctypes.c_int32
+    for nm in ("oracle_ac_sin", "oracle_ac_cos"):
+        getattr(L, nm).argtypes = [d]
+        getattr(L, nm).restype = d
+    L.oracle_ac_bank_rad.argtypes = [ctypes.c_int, ctypes.c_int, d]
+    L.oracle_ac_bank_rad.restype = d
+    L.oracle_ac_thrust.argtypes = [ctypes.c_int, ctypes.c_int, d]
+    L.oracle_ac_thrust.restype = d
+    L.oracle_ac_enclose.argtypes = [P, P, d, d, d, d, d, d, ctypes.c_int, P, P]
+    L.oracle_ac_enclose.restype = ctypes.c_int
+    L.oracle_ac_table.argtypes = [P, d, d, d, d, d, d, d, d, i32, i32, i32, d, d, P]
+    L.oracle_ac_table.restype = i64
     return L
 
 
@@ -82,20 +96,24 @@ def lib():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC):
+            if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(
+                    os.path.getmtime(_SRC), os.path.getmtime(_SRC_AC)):
                 build()
             _lib = _bind(ctypes.CDLL(LIB_PATH))
     return _lib
 
 
-def build_variant(src_text: str, path: str) -> str:
-    """Compiles a modified copy of the oracle's source (tests that plant a
-    mistake in the oracle use this to show that a pin catches it)."""
+def build_variant(src_text: str, path: str, which: str = "solver") -> str:
+    """Compiles a modified copy of one of the oracle's sources ("solver":
+    gbf_oracle.c, "aircraft": aircraft.c) with the other unchanged; tests
+    that plant a mistake in the oracle use this to show that a pin catches
+    it."""
     src = path + ".c"
     with open(src, "w") as f:
         f.write(src_text)
+    pair = [src, _SRC_AC] if which == "solver" else [_SRC, src]
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                           "-shared", "-o", path, src, "-lm"])
+                           "-shared", "-o", path] + pair + ["-lm"])
     return path
 
 
@@ -119,8 +137,8 @@ class use_variant:
         return False
 
 
-def source() -> str:
-    with open(_SRC) as f:
+def source(which: str = "solver") -> str:
+    with open(_SRC if which == "solver" else _SRC_AC) as f:
         return f.read()
 
 
