@@ -231,7 +231,8 @@ typedef struct gbf_stats {
     int32_t sweeps;         /* bucket order: ascending passes over the buckets */
     int32_t enc_used;       /* representation the handle holds: 0 CSR, 1 implicit
                                boxes, 2 boxes + reverse CSR (expand_box 2, or
-                               3 when the predecessor images fit the budget) */
+                               3 when the predecessor images fit the budget),
+                               3 aircraft abstraction (gbf_load_aircraft) */
     int32_t images_dropped; /* 1 = this solve released the predecessor images
                                (gbf_opts.mem_floor_mib) */
 } gbf_stats;
@@ -393,6 +394,72 @@ int gbf_mlp_bucket_keys(gbf_mlp* net, const int32_t dims[4], float tcx, float tc
                         uint16_t* key_out, float* vhat_out, float* vhat_min_out);
 /* Releases a network (NULL is allowed). */
 void gbf_mlp_free(gbf_mlp* net);
+
+/* ---- aircraft abstraction ------------------------------------------------
+ * The discrete abstraction of a sampled system (Sect. V-B) for the
+ * point-mass aircraft of Sect. VI-A,
+ *     x1' = x4 cos x3, x2' = x4 sin x3, x3' = p_L x4 sin(u2) / m,
+ *     x4' = (u1 - p_D x4^2) / m,
+ * computed on the device and solved without stored images.  The state space
+ * [0, x_max[0]] x [0, x_max[1]] x [-pi, pi] x [v_range[0], v_range[1]] is
+ * covered by dims[0..3] compact cells (the heading is periodic); cell ids are
+ * x = i1 + dims[0] (i2 + dims[1] (i3 + dims[2] i4)), pair ids x K + u.
+ * Inputs u = a n_bank + b are the vertices of an even subdivision of
+ * [0, thrust_max] x [-bank_max_deg, bank_max_deg] degrees: thrust
+ * a thrust_max / (n_thrust - 1), bank angle
+ * ((2 b - (n_bank - 1)) bank_max_deg / (n_bank - 1)) pi / 180.
+ * F(x,u) is the set of cells met by an enclosure of the attainable set of
+ * cell x after tau seconds under u (Sect. V-B over-approximates attainable
+ * sets by hyper-rectangles).  Enclosure: `steps` steps of the first-order
+ * interval Taylor method with a priori enclosures, in double precision
+ * with outward rounding; the positions do not enter the dynamics, so one
+ * enclosure per (heading cell, speed cell, input) serves every position.
+ * Predecessors come from reverse rows of that table (exact).
+ * Costs (fp32 values): a transition into a cell inside a reward box costs
+ * reward_cost, any other tau + u2^2 (u2 in radians); a pair whose
+ * enclosure leaves the grid on x1, x2 or the speed has infinite cost; a
+ * cell meeting an avoid box is an obstacle (V = inf).  G: the device array
+ * G (fp32 [n], e.g. the value function of a first problem, Sect. VI-A's
+ * G_2 = V_1), or, if NULL, 0 on cells inside a target box and inf
+ * elsewhere.  Boxes are closed, with integer bounds per axis: metres,
+ * degrees within [-180, 180] for the heading, m/s. */
+typedef struct gbf_ac_box {
+    int32_t lo[4];
+    int32_t hi[4];
+} gbf_ac_box;
+
+typedef struct gbf_aircraft {
+    int32_t dims[4];        /* >= 1; dims[2], dims[3] <= 255; n = product < 2^32 - 1 */
+    int32_t x_max[2];       /* > 0 */
+    int32_t v_range[2];     /* 0 < v_range[0] < v_range[1] */
+    double mass, p_D, p_L, tau;  /* > 0 (p_D, p_L >= 0) */
+    int32_t steps;          /* integration steps per sampling period, 1..64 */
+    int32_t n_thrust, n_bank;  /* >= 1, K = n_thrust * n_bank <= 255 */
+    double thrust_max, bank_max_deg;  /* >= 0; bank_max_deg < 90 */
+    const gbf_ac_box* target; int32_t n_target;  /* host arrays, <= 16 boxes each */
+    const gbf_ac_box* avoid; int32_t n_avoid;
+    const gbf_ac_box* reward; int32_t n_reward;
+    float reward_cost;      /* finite */
+    const float* G;         /* device [n] or NULL */
+} gbf_aircraft;
+
+/* The enclosure table: table (device int32 [dims[3] * dims[2] * K * 8]) gets,
+ * at ((i4 dims[2] + i3) K + u) * 8, the cells met by the enclosure of the
+ * cell (0, 0, i3, i4) moved by the input u: x1 and x2 cell offsets
+ * (lo, hi), heading cells (lo, hi, not reduced mod dims[2]), speed cells
+ * (lo, hi; outside [0, dims[3]) the set leaves the speed range).
+ * Synchronises the stream.  Errors: GBF_EINVAL (bad scenario, or an
+ * enclosure without an a priori enclosure: its ranges are then empty),
+ * GBF_ENOMEM, GBF_EHIP. */
+int gbf_aircraft_table(const gbf_aircraft* a, int32_t* table, void* hip_stream);
+/* Builds the abstraction on the device and returns a handle for gbf_solve
+ * (host-loop mode, plain order, one instance; 64-bit pair ids when
+ * n K >= 2^31) and gbf_extract_policy.  Device memory: about 6 bytes per
+ * state, 2 bytes per pair for the solver's frontiers, the table and its
+ * reverse rows; no per-pair images.  The scenario is read during the call
+ * only.  Errors: GBF_EINVAL (bad scenario; table offsets beyond +-127
+ * cells; an enclosure not found), GBF_ENOMEM, GBF_EHIP. */
+int gbf_load_aircraft(const gbf_aircraft* a, void* hip_stream, gbf_graph** out);
 
 /* Message for the last failing call of this thread ("" if none). */
 const char* gbf_last_error(void);

@@ -92,7 +92,8 @@ class _Stats(ctypes.Structure):
 
 EXPORTS = ("gbf_load_graph", "gbf_solve", "gbf_extract_policy", "gbf_solve_batch", "gbf_tune", "gbf_free_graph",
            "gbf_last_error", "gbf_shutdown", "gbf_solve_noalloc", "gbf_mlp_create", "gbf_mlp_set_params", "gbf_mlp_get_params", "gbf_mlp_samples",
-           "gbf_mlp_forward", "gbf_mlp_grad", "gbf_mlp_train_step", "gbf_mlp_bucket_keys", "gbf_mlp_free")
+           "gbf_mlp_forward", "gbf_mlp_grad", "gbf_mlp_train_step", "gbf_mlp_bucket_keys", "gbf_mlp_free",
+           "gbf_aircraft_table", "gbf_load_aircraft")
 MLP_NPARAMS = 4545
 
 _lock = threading.Lock()
@@ -117,6 +118,21 @@ def _shutdown():
             pass
     _lib.gbf_shutdown()
     _closed = True
+
+
+class _AcBox(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int32 * 4), ("hi", ctypes.c_int32 * 4)]
+
+
+class _Aircraft(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("x_max", ctypes.c_int32 * 2), ("v_range", ctypes.c_int32 * 2),
+                ("mass", ctypes.c_double), ("p_D", ctypes.c_double), ("p_L", ctypes.c_double),
+                ("tau", ctypes.c_double), ("steps", ctypes.c_int32), ("n_thrust", ctypes.c_int32),
+                ("n_bank", ctypes.c_int32), ("thrust_max", ctypes.c_double), ("bank_max_deg", ctypes.c_double),
+                ("target", ctypes.POINTER(_AcBox)), ("n_target", ctypes.c_int32),
+                ("avoid", ctypes.POINTER(_AcBox)), ("n_avoid", ctypes.c_int32),
+                ("reward", ctypes.POINTER(_AcBox)), ("n_reward", ctypes.c_int32),
+                ("reward_cost", ctypes.c_float), ("G", ctypes.c_void_p)]
 
 
 def lib():
@@ -166,6 +182,10 @@ def lib():
                 fn.restype = ctypes.c_int
             L.gbf_mlp_free.argtypes = [P]
             L.gbf_mlp_free.restype = None
+            L.gbf_aircraft_table.argtypes = [ctypes.POINTER(_Aircraft), P, P]
+            L.gbf_aircraft_table.restype = ctypes.c_int
+            L.gbf_load_aircraft.argtypes = [ctypes.POINTER(_Aircraft), P, ctypes.POINTER(P)]
+            L.gbf_load_aircraft.restype = ctypes.c_int
             _lib = L
             # registered after torch's own handlers, so it runs before them
             atexit.register(_shutdown)
@@ -343,6 +363,64 @@ def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=
     if rc != OK:
         raise _err(L, rc)
     return Graph(h, int(n), int(K), p.dtype, None)
+
+
+def _aircraft(scn, G=None):
+    """A gbf_aircraft struct for a scenario with the fields of
+    synth.aircraft.Scenario (and the arrays it points to)."""
+    a = _Aircraft()
+    for k in range(4):
+        a.dims[k] = int(scn.dims[k])
+    for k in range(2):
+        a.x_max[k] = int(scn.x_max[k])
+        a.v_range[k] = int(scn.v_range[k])
+    a.mass, a.p_D, a.p_L, a.tau = float(scn.mass), float(scn.p_D), float(scn.p_L), float(scn.tau)
+    a.steps, a.n_thrust, a.n_bank = int(scn.steps), int(scn.n_thrust), int(scn.n_bank)
+    a.thrust_max, a.bank_max_deg = float(scn.thrust_max), float(scn.bank_max_deg)
+    keep = []
+    for name in ("target", "avoid", "reward"):
+        boxes = list(getattr(scn, name))
+        arr = (_AcBox * max(1, len(boxes)))()
+        for i, (lo, hi) in enumerate(boxes):
+            for k in range(4):
+                arr[i].lo[k], arr[i].hi[k] = int(lo[k]), int(hi[k])
+        keep.append(arr)
+        setattr(a, name, ctypes.cast(arr, ctypes.POINTER(_AcBox)))
+        setattr(a, "n_" + name, len(boxes))
+    a.reward_cost = float(scn.reward_cost)
+    if G is not None:
+        ptr, sp = _ptr(G)
+        if sp != DEVICE or G.dtype.itemsize != 4 or G.numel() != int(np.prod(scn.dims)):
+            raise ValueError("G must be a float32 device tensor with one value per cell")
+        keep.append(G)
+        a.G = ptr
+    return a, keep
+
+
+def aircraft_table(scn, stream=None):
+    """gbf_aircraft_table: the enclosure table as an int32 device tensor
+    [dims[3], dims[2], K, 8]."""
+    import torch
+    L = lib()
+    a, keep = _aircraft(scn)
+    out = torch.empty((scn.dims[3], scn.dims[2], scn.n_thrust * scn.n_bank, 8), dtype=torch.int32, device="cuda")
+    rc = L.gbf_aircraft_table(ctypes.byref(a), out.data_ptr(), stream)
+    if rc != OK:
+        raise _err(L, rc)
+    return out
+
+
+def load_aircraft(scn, G=None, stream=None) -> Graph:
+    """gbf_load_aircraft: the abstraction of a scenario, built on the device.
+    G (float32 device tensor over the cells, e.g. the values of a first
+    problem) replaces the target sets as terminal cost."""
+    L = lib()
+    a, keep = _aircraft(scn, G)
+    h = ctypes.c_void_p()
+    rc = L.gbf_load_aircraft(ctypes.byref(a), stream, ctypes.byref(h))
+    if rc != OK:
+        raise _err(L, rc)
+    return Graph(h, int(np.prod(scn.dims)), int(scn.n_thrust * scn.n_bank), F32, None)
 
 
 def load_problem(prob, encoding="csr", stream=None, mem_budget=0, pair_ids64=False) -> Graph:

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -588,6 +589,184 @@ extern "C" int gbf_load_graph(const gbf_problem* p, void* hip_stream, gbf_graph*
     return GBF_OK;
 }
 
+// ------------------------------------------------------------------ aircraft
+// Checks a scenario and fills the kernels' numeric view of it.
+static int ac_spec(const gbf_aircraft* a, AcSpec& S, AcSets* sets) {
+    if (!a) return fail(GBF_EINVAL, "scenario is NULL");
+    int64_t n = 1;
+    for (int k = 0; k < 4; ++k) {
+        if (a->dims[k] < 1) return fail(GBF_EINVAL, "dims must be positive");
+        n *= a->dims[k];
+        S.dims[k] = a->dims[k];
+    }
+    if (a->dims[2] > 255 || a->dims[3] > 255) return fail(GBF_EINVAL, "dims[2] and dims[3] must be <= 255");
+    if (n >= ((int64_t)1 << 32) - 1) return fail(GBF_EINVAL, "the grid must have fewer than 2^32 - 1 cells");
+    if (a->x_max[0] <= 0 || a->x_max[1] <= 0) return fail(GBF_EINVAL, "x_max must be positive");
+    if (a->v_range[0] <= 0 || a->v_range[1] <= a->v_range[0]) return fail(GBF_EINVAL, "bad v_range");
+    if (!(a->mass > 0) || !(a->tau > 0) || !(a->p_D >= 0) || !(a->p_L >= 0) || !(a->thrust_max >= 0) ||
+        !(a->bank_max_deg >= 0 && a->bank_max_deg < 90) || !std::isfinite(a->mass) || !std::isfinite(a->tau) ||
+        !std::isfinite(a->p_D) || !std::isfinite(a->p_L) || !std::isfinite(a->thrust_max))
+        return fail(GBF_EINVAL, "bad model constants");
+    if (a->steps < 1 || a->steps > 64) return fail(GBF_EINVAL, "steps must be 1..64");
+    if (a->n_thrust < 1 || a->n_bank < 1 || a->n_thrust * a->n_bank > 255)
+        return fail(GBF_EINVAL, "need 1 <= n_thrust * n_bank <= 255");
+    if (!std::isfinite(a->reward_cost)) return fail(GBF_EINVAL, "reward_cost must be finite");
+    for (int k = 0; k < 2; ++k) S.x_max[k] = a->x_max[k], S.v_range[k] = a->v_range[k];
+    S.mass = a->mass;
+    S.p_D = a->p_D;
+    S.p_L = a->p_L;
+    S.tau = a->tau;
+    S.steps = a->steps;
+    S.n_thrust = a->n_thrust;
+    S.n_bank = a->n_bank;
+    S.thrust_max = a->thrust_max;
+    S.bank_max_deg = a->bank_max_deg;
+    if (sets) {
+        const gbf_ac_box* lists[3] = {a->target, a->avoid, a->reward};
+        const int32_t counts[3] = {a->n_target, a->n_avoid, a->n_reward};
+        std::memset(sets, 0, sizeof(*sets));
+        for (int k = 0; k < 3; ++k) {
+            if (counts[k] < 0 || counts[k] > kAcMaxBoxes || (counts[k] > 0 && !lists[k]))
+                return fail(GBF_EINVAL, "at most 16 boxes per set, with a non-NULL array");
+            sets->count[k] = counts[k];
+            for (int b = 0; b < counts[k]; ++b)
+                for (int c = 0; c < 4; ++c) {
+                    sets->box[k][b][c] = lists[k][b].lo[c];
+                    sets->box[k][b][4 + c] = lists[k][b].hi[c];
+                }
+        }
+    }
+    return GBF_OK;
+}
+
+// Bank angle of input column b in radians, as the kernels compute it.
+static double ac_bank_rad(const AcSpec& S, int b) {
+    if (S.n_bank == 1) return 0.0;
+    double t = (double)(2 * b - (S.n_bank - 1)) * S.bank_max_deg;
+    t = t / (double)(S.n_bank - 1);
+    return t * (3.141592653589793 / 180.0);
+}
+
+extern "C" int gbf_aircraft_table(const gbf_aircraft* a, int32_t* table, void* hip_stream) {
+    AcSpec S;
+    int rc = ac_spec(a, S, nullptr);
+    if (rc) return rc;
+    if (!table) return fail(GBF_EINVAL, "table is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    DevMem M;
+    unsigned long long* bad;
+    if ((rc = M.alloc((void**)&bad, 16))) return rc;
+    HIPC(launch_fill_u32((uint32_t*)bad, 0, 4, s));
+    HIPC(launch_ac_table(S, table, nullptr, bad, s));
+    unsigned long long hb[2] = {0, 0};
+    HIPC(hipMemcpyAsync(hb, bad, 16, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (hb[0]) return fail(GBF_EINVAL, std::to_string(hb[0]) + " enclosures without an a priori enclosure");
+    return GBF_OK;
+}
+
+extern "C" int gbf_load_aircraft(const gbf_aircraft* a, void* hip_stream, gbf_graph** out) {
+    if (!out) return fail(GBF_EINVAL, "out is NULL");
+    *out = nullptr;
+    AcSpec S;
+    AcSets sets;
+    int rc = ac_spec(a, S, &sets);
+    if (rc) return rc;
+    const int64_t n = (int64_t)S.dims[0] * S.dims[1] * S.dims[2] * S.dims[3];
+    const int K = S.n_thrust * S.n_bank;
+    const int64_t rows = (int64_t)S.dims[2] * S.dims[3] * K;
+    const int stage = a->n_reward > 0 ? 2 : 1;
+
+    std::unique_ptr<gbf_graph> gr(new gbf_graph());
+    gr->n = n;
+    gr->K = K;
+    gr->dtype = GBF_F32;
+    gr->enc = 3;
+    gr->stream = (hipStream_t)hip_stream;
+    HIPC(hipGetDevice(&gr->device));
+    HIPC(hipDeviceGetAttribute(&gr->cus, hipDeviceAttributeMultiprocessorCount, gr->device));
+    if (hipDeviceGetAttribute(&gr->clock_khz, hipDeviceAttributeWallClockRate, gr->device) != hipSuccess ||
+        gr->clock_khz <= 0)
+        gr->clock_khz = 100000;
+    hipStream_t s = gr->stream;
+    DevMem& M = gr->mem;
+    Inst& I = gr->inst;
+    I.n = n;
+    I.K = K;
+    I.enc = 3;
+    I.dtype = GBF_F32;
+    I.pair_base = 0;
+    I.max_rounds = n;
+    gr->wide = n * K >= ((int64_t)1 << 31);
+    I.wide = gr->wide ? 1 : 0;
+    for (int k = 0; k < 4; ++k) I.dims[k] = gr->dims[k] = S.dims[k];
+    I.strides[0] = 1;
+    I.strides[1] = I.dims[0];
+    I.strides[2] = I.dims[0] * I.dims[1];
+    I.strides[3] = I.dims[0] * I.dims[1] * I.dims[2];
+    I.ac_stage = stage;
+
+    int32_t *G, *gu;
+    uint8_t *avoid, *reward = nullptr;
+    void* V;
+    uint2* tab;
+    uint32_t* rptr;
+    unsigned long long* bad;
+    AcInst* dac;
+    if ((rc = M.alloc((void**)&G, n * 4)) || (rc = M.alloc((void**)&avoid, n)) || (rc = M.alloc(&V, n * 4)) ||
+        (rc = M.alloc((void**)&tab, rows * 8)) || (rc = M.alloc((void**)&rptr, (rows + 1) * 4)) ||
+        (rc = M.alloc((void**)&gu, K * 4)) || (rc = M.alloc((void**)&bad, 16)) ||
+        (rc = M.alloc((void**)&dac, sizeof(AcInst))))
+        return rc;
+    if (stage == 2 && (rc = M.alloc((void**)&reward, n))) return rc;
+    // the enclosure table and the cell sets
+    HIPC(launch_fill_u32((uint32_t*)bad, 0, 4, s));
+    HIPC(launch_ac_table(S, nullptr, tab, bad, s));
+    HIPC(launch_ac_sets(S, sets, a->G, G, avoid, reward, s));
+    // reverse rows: counts, scan, fill
+    HIPC(launch_fill_u32(rptr, 0, rows + 1, s));
+    HIPC(launch_ac_rev_count(S, tab, rptr, s));
+    HIPC(launch_ac_scan(rptr, rows, s));
+    unsigned long long hb[2] = {0, 0};
+    uint32_t total = 0;
+    HIPC(hipMemcpyAsync(hb, bad, 16, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(&total, rptr + rows, 4, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (hb[0]) return fail(GBF_EINVAL, std::to_string(hb[0]) + " enclosures without an a priori enclosure");
+    if (hb[1]) return fail(GBF_EINVAL, "table offsets beyond +-127 cells (cells too small for the sampling time)");
+    uint2* rent;
+    uint32_t* cursor;
+    if ((rc = M.alloc((void**)&rent, (size_t)total * 8)) || (rc = M.alloc((void**)&cursor, rows * 4))) return rc;
+    HIPC(launch_fill_u32(cursor, 0, rows, s));
+    HIPC(launch_ac_rev_fill(S, tab, rptr, cursor, rent, s));
+    // running costs per input: tau + u2^2 rounded to fp32
+    std::vector<int32_t> hgu(K);
+    for (int u = 0; u < K; ++u) {
+        const double b = ac_bank_rad(S, u % S.n_bank);
+        const float c = (float)(S.tau + b * b);
+        std::memcpy(&hgu[u], &c, 4);
+    }
+    HIPC(hipMemcpyAsync(gu, hgu.data(), K * 4, hipMemcpyHostToDevice, s));
+    AcInst A{};
+    A.tab = tab;
+    A.rptr = rptr;
+    A.rent = rent;
+    A.reward = reward;
+    A.gu = gu;
+    std::memcpy(&A.rc, &a->reward_cost, 4);
+    A.stage = stage;
+    HIPC(hipMemcpyAsync(dac, &A, sizeof(A), hipMemcpyHostToDevice, s));
+    HIPC(hipStreamSynchronize(s));  // the host copies above must finish before they go out of scope
+    M.release(cursor, rows * 4);
+    I.G = G;
+    I.g = nullptr;
+    I.avoid = avoid;
+    I.V = V;
+    I.ac = dac;
+    *out = gr.release();
+    return GBF_OK;
+}
+
 static void forget_batches_of(gbf_graph* g);
 
 extern "C" void gbf_free_graph(gbf_graph* g) {
@@ -622,6 +801,7 @@ struct Plan {
     int block = 0, compact_grid = 0;  // host loop: relax block (threads), compaction grid; 0 = defaults
     bool bucket = false;
     bool wide = false;  // 64-bit pair ids
+    int ac_stage = 0;   // aircraft abstraction: 1 or 2 (costs per pair or per transition)
     // bucket order: work budget (pair evaluations, rounds) after which the
     // remaining rounds list every dirty pair, i.e. continue in plain order
     int64_t budget_evals = INT64_MAX, budget_rounds = INT64_MAX;
@@ -661,9 +841,17 @@ static int plan_solve(Scratch& S, const Inst* insts, int ninst, int dtype, const
         total_pairs = std::max<int64_t>(total_pairs, I.pair_base + I.n * I.K);
         P.max_rounds = std::max<int64_t>(P.max_rounds, I.max_rounds);
         P.max_states = std::max<int64_t>(P.max_states, I.n);
-        P.enc_mask |= I.enc == 0 ? (I.ge ? 8 : 1) : I.enc == 1 ? 2 : 4;
+        P.enc_mask |= I.enc == 0 ? (I.ge ? 8 : 1) : I.enc == 1 ? 2 : I.enc == 3 ? 16 : 4;
     }
     P.wide = insts[0].wide != 0;
+    if (P.enc_mask & 16) {
+        // the aircraft abstraction: one instance, host loop, plain order
+        if (ninst != 1) return fail(GBF_EINVAL, "an aircraft abstraction is solved on its own, not in a batch");
+        if (o.order != GBF_ORDER_PLAIN) return fail(GBF_EINVAL, "an aircraft abstraction uses the plain order");
+        if (o.mode == GBF_MODE_PERSISTENT || o.mode == GBF_MODE_SINGLE_BLOCK)
+            return fail(GBF_EINVAL, "an aircraft abstraction runs in host-loop mode");
+        P.ac_stage = insts[0].ac_stage;
+    }
     if (P.wide) {
         // 64-bit pair ids: one instance, host loop, plain order
         if (ninst != 1) return fail(GBF_EINVAL, "a problem with 64-bit pair ids is solved on its own, not in a batch");
@@ -720,7 +908,7 @@ static int plan_solve(Scratch& S, const Inst* insts, int ninst, int dtype, const
     if (o.compact_grid < 0) return fail(GBF_EINVAL, "compact_grid must be >= 0");
     P.block = o.block;
     P.compact_grid = o.compact_grid;
-    P.mode = (P.bucket || P.wide) ? GBF_MODE_HOSTLOOP : o.mode;
+    P.mode = (P.bucket || P.wide || (P.enc_mask & 16)) ? GBF_MODE_HOSTLOOP : o.mode;
     if (P.mode == GBF_MODE_SINGLE_BLOCK && P.ninst != 1)
         return fail(GBF_EINVAL, "single-block mode solves one instance");
     if (P.mode == GBF_MODE_AUTO && P.ninst == 1 && total_pairs <= kSingleBlockMaxPairs)
@@ -767,7 +955,8 @@ static int enqueue_init(Scratch& S, const Plan& P, const Inst* insts, hipStream_
     HIPC(launch_fill_u32((uint32_t*)R.result, 0, 16, s));
     if (P.bucket) HIPC(launch_fill_u32((uint32_t*)R.occ, 0, 65536 / 4, s));
     for (int i = 0; i < P.ninst; ++i) HIPC(launch_init(S.dinst, insts[i], P.dtype, s));
-    HIPC(launch_seed(S.dinst, P.ninst, R, P.max_states, P.dtype, P.enc_mask, s, P.wide));
+    if (P.enc_mask == 16) HIPC(launch_ac_seed(S.dinst, R, P.max_states, s, P.wide));
+    else HIPC(launch_seed(S.dinst, P.ninst, R, P.max_states, P.dtype, P.enc_mask, s, P.wide));
     return GBF_OK;
 }
 
@@ -848,7 +1037,8 @@ static int enqueue_hostloop(Scratch& S, const Plan& P, const gbf_opts& o, hipStr
             else HIPC(launch_compact(R, (int)(r + k), P.compact_grid, s, P.wide));
             const bool timed = o.profile && ev + 1 < (int)S.events.size();
             if (timed) HIPC(hipEventRecord(S.events[ev], s));
-            HIPC(launch_relax(S.dinst, R, (int)(r + k), P.grid, P.lanes, P.dtype, enc_mask, s, P.wide, P.block));
+            if (enc_mask == 16) HIPC(launch_ac_relax(S.dinst, R, (int)(r + k), P.grid, s, P.wide, P.ac_stage));
+            else HIPC(launch_relax(S.dinst, R, (int)(r + k), P.grid, P.lanes, P.dtype, enc_mask, s, P.wide, P.block));
             if (timed) {
                 HIPC(hipEventRecord(S.events[ev + 1], s));
                 ev += 2;
@@ -1134,6 +1324,7 @@ extern "C" int gbf_solve_noalloc(gbf_graph* g, const gbf_opts* opts, void* V_out
     if (!g) return fail(GBF_EINVAL, "graph is NULL");
     gbf_opts o = opts ? *opts : default_opts();
     if (g->wide) return fail(GBF_EINVAL, "the no-allocation solve takes 32-bit pair ids only");
+    if (g->enc == 3) return fail(GBF_EINVAL, "an aircraft abstraction is solved with gbf_solve");
     if (o.order != GBF_ORDER_PLAIN) return fail(GBF_EINVAL, "the no-allocation solve uses the plain order");
     if (o.v_memspace != GBF_HOST && o.v_memspace != GBF_DEVICE) return fail(GBF_EINVAL, "bad v_memspace");
     o.profile = 0;  // per-launch timing needs events, which are allocated
@@ -1205,7 +1396,8 @@ extern "C" int gbf_extract_policy(gbf_graph* g, int32_t* policy_out, int32_t mem
     unsigned long long* bad = S.ctr + 6;
     HIPC(launch_fill_u32((uint32_t*)bad, 0, 2, s));
     int32_t* dst = memspace == GBF_DEVICE ? policy_out : (int32_t*)S.list;
-    HIPC(launch_policy(g->inst, g->dtype, dst, bad, s));
+    if (g->enc == 3) HIPC(launch_ac_policy(g->inst, dst, bad, s));
+    else HIPC(launch_policy(g->inst, g->dtype, dst, bad, s));
     if (memspace != GBF_DEVICE) HIPC(hipMemcpyAsync(policy_out, dst, g->n * 4, hipMemcpyDeviceToHost, s));
     unsigned long long* hb = (unsigned long long*)((char*)S.host + 64);
     HIPC(hipMemcpyAsync(hb, bad, 8, hipMemcpyDeviceToHost, s));
@@ -1306,6 +1498,9 @@ extern "C" int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gb
                                gbf_stats* st) {
     if (!graphs || count <= 0) return fail(GBF_EINVAL, "empty batch");
     if (count > kMaxBatch) return fail(GBF_EINVAL, "batch larger than " + std::to_string(kMaxBatch));
+    for (int i = 0; i < count; ++i)
+        if (graphs[i] && graphs[i]->enc == 3)
+            return fail(GBF_EINVAL, "an aircraft abstraction is solved with gbf_solve");
     gbf_opts o = opts ? *opts : default_opts();
     if (o.order != GBF_ORDER_PLAIN) return fail(GBF_EINVAL, "batched solves use the plain order");
     if (o.v_memspace != GBF_HOST && o.v_memspace != GBF_DEVICE) return fail(GBF_EINVAL, "bad v_memspace");
@@ -1424,8 +1619,10 @@ extern "C" int gbf_solve_batch(gbf_graph* const* graphs, int32_t count, const gb
 extern "C" int gbf_tune(gbf_graph* const* graphs, int32_t count, const gbf_opts* base, int32_t reps,
                         gbf_opts* best, double* best_ms) {
     if (!graphs || count <= 0 || !best) return fail(GBF_EINVAL, "NULL graphs or output, or empty set");
-    for (int i = 0; i < count; ++i)
+    for (int i = 0; i < count; ++i) {
         if (!graphs[i]) return fail(GBF_EINVAL, "NULL graph");
+        if (graphs[i]->enc == 3) return fail(GBF_EINVAL, "an aircraft abstraction has no launch options to tune");
+    }
     if (reps <= 0) reps = 3;
     gbf_opts o = base ? *base : default_opts();
     o.profile = 0;

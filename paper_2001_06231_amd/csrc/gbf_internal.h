@@ -8,6 +8,8 @@
 
 namespace gbf {
 
+struct AcInst;
+
 // One problem instance as the kernels see it.  Pair ids are global: pair p
 // of this instance has id pair_base + p, state x is instance-local.
 struct Inst {
@@ -36,6 +38,46 @@ struct Inst {
     int32_t index;          // position in the batch
     int32_t dtype;          // 0 int32, 1 fp32
     int32_t wide;           // 1 = 64-bit pair ids (Run.list64 / counts64; HYB: rptr64 / rrel)
+    const AcInst* ac;       // enc 3 (aircraft abstraction): its tables (device), else NULL
+    int32_t ac_stage;       // enc 3: 1 = costs per pair, 2 = per transition (reward cells)
+};
+
+// The aircraft abstraction (enc 3): F(x,u) and pred come from a table of
+// enclosures per (heading cell, speed cell, input) instead of per-pair
+// images; positions shift the table's boxes by whole cells.
+//   tab[(i4 * N3 + i3) * K + u], two words:
+//     .x = o1lo | o1hi << 8 | o2lo << 16 | o2hi << 24  (int8 cell offsets on x1, x2)
+//     .y = j3lo | n3 << 8 | j4lo << 16 | j4hi << 24   (uint8: first heading
+//          cell, mod N3, and the number of heading cells; speed cells;
+//          n3 = 0: the enclosure leaves the speed range or was not found)
+//   reverse rows, key (k4 * N3 + k3) * K + u: the entries whose box holds
+//   heading cell k3 and speed cell k4, as
+//     .x = the entry's offsets (as in tab), .y = i3 | i4 << 8 | u << 16.
+struct AcInst {
+    const uint2* tab;
+    const uint32_t* rptr;   // [N4 * N3 * K + 1]
+    const uint2* rent;
+    const uint8_t* reward;  // [n] transitions into these cells cost rc (problem 2), or NULL
+    const int32_t* gu;      // [K] running cost bits (fp32) per input
+    int32_t rc;             // reward cost bits (fp32)
+    int32_t stage;          // 1: costs per pair gu[u]; 2: per transition (gu[u] or rc)
+};
+
+// The numeric part of an aircraft scenario (see gbf_aircraft in gbf.h).
+struct AcSpec {
+    int32_t dims[4];
+    int32_t x_max[2], v_range[2];
+    double mass, p_D, p_L, tau;
+    int32_t steps, n_thrust, n_bank;
+    double thrust_max, bank_max_deg;
+};
+
+// Closed boxes with integer bounds per axis (x1, x2 metres, heading
+// degrees in [-180, 180], speed m/s): 0 target, 1 avoid, 2 reward.
+constexpr int kAcMaxBoxes = 16;
+struct AcSets {
+    int32_t count[3];
+    int32_t box[3][kAcMaxBoxes][8];  // lo[4], hi[4]
 };
 
 // Device-side solver state shared by all instances of one solve.
@@ -119,6 +161,26 @@ hipError_t launch_scan64(const uint32_t* in, uint64_t* out, int64_t n, uint64_t*
 hipError_t launch_rev_fill_box(const Inst& I, unsigned long long* cursor, int32_t* rel, hipStream_t s);
 hipError_t launch_sort_rows64(const uint64_t* rptr, int32_t* rel, int64_t n, hipStream_t s);
 hipError_t launch_decode(const Inst& I, int dtype, void* out, hipStream_t s);
+
+// Aircraft abstraction (gbf_aircraft.hip).
+// The enclosure table: `full` (or NULL) gets 8 int32 per entry (o1lo, o1hi,
+// o2lo, o2hi, j3lo, j3hi unwrapped, j4lo, j4hi), `packed` (or NULL) the
+// solver's form; bad[0] counts entries without an a priori enclosure,
+// bad[1] entries that do not fit the packed form.
+hipError_t launch_ac_table(const AcSpec& S, int32_t* full, uint2* packed, unsigned long long* bad, hipStream_t s);
+// G bits (fp32: 0 on target cells, +inf elsewhere; skipped if G_in is
+// given, which is copied instead), avoid and reward flags per state.
+hipError_t launch_ac_sets(const AcSpec& S, const AcSets& sets, const float* G_in, int32_t* G, uint8_t* avoid,
+                          uint8_t* reward, hipStream_t s);
+// Reverse rows of the packed table: counts into rptr[1..], scan, fill.
+// `cursor` has N4 * N3 * K words.
+hipError_t launch_ac_rev_count(const AcSpec& S, const uint2* tab, uint32_t* rptr, hipStream_t s);
+hipError_t launch_ac_rev_fill(const AcSpec& S, const uint2* tab, const uint32_t* rptr, uint32_t* cursor,
+                              uint2* rent, hipStream_t s);
+hipError_t launch_ac_scan(uint32_t* rptr, int64_t rows, hipStream_t s);
+hipError_t launch_ac_relax(const Inst* dI, const Run& R, int round, int grid, hipStream_t s, bool wide, int stage);
+hipError_t launch_ac_seed(const Inst* dI, const Run& R, int64_t n, hipStream_t s, bool wide);
+hipError_t launch_ac_policy(const Inst& I, int32_t* pol, unsigned long long* bad, hipStream_t s);
 hipError_t launch_policy(const Inst& I, int dtype, int32_t* pol, unsigned long long* bad, hipStream_t s);
 
 }  // namespace gbf
