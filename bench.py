@@ -163,7 +163,19 @@ def cpu_job(spec):
     oracle.lib()
     probs = []
     for k in kinds:
-        if k.startswith("reward:"):
+        if k.startswith("aircraft"):
+            # "aircraftS:<grid>": problem S of the aircraft mission, its
+            # explicit images built off the clock (problem 2 takes the
+            # oracle's V_1, also solved off the clock)
+            import oracle.aircraft as OA
+            import synth.aircraft as SA
+            stage, grid = int(k[8]), k.split(":")[1]
+            make = getattr(SA, grid)
+            G = None
+            if stage == 2:
+                G = oracle.solve(OA.problem(make(1)), precision="f32")["V"]
+            probs.append(OA.problem(make(stage), G=G))
+        elif k.startswith("reward:"):
             # the second problem of the chained mission: its terminal cost is
             # the oracle's value function of the first (solved off the clock)
             p1 = make_problem(k[7:])
@@ -205,6 +217,10 @@ CPU_SAMPLES = {
                 "16 of the 64 batch instances (every 4th: 4 2-D, 4 3-D, 8 4-D), one solve each; the rate is "
                 "their summed relaxations over their summed solve time"),
     "learned": (["learned:1000"], 1, None, "held-out instance 1000 (60x60x30x12, K=16), one solve"),
+    "aircraft_mission": (["aircraft1:medium", "aircraft2:medium"], 1, "f32",
+                         "the aircraft mission on the 24x12x24x12 grid (82,944 cells, 35 inputs, landing within 90 "
+                         "degrees): problem 1, then problem 2 with the oracle's V1, each on the oracle's own "
+                         "explicit images (built off the clock), single-precision operator, one solve each"),
 }
 
 
@@ -397,7 +413,8 @@ def run(args, pool=None):
     if not args.no_cpu:
         cpu_labels = ["main"] + ([] if args.no_extras else
                                  ["grid2d_64x64_i32_csr", "grid4d_384k_f32", "grid4d_384k_i32_csr_edge_costs",
-                                  "grid4d_384k_i32_reward_chain", "batch64", "learned"])
+                                  "grid4d_384k_i32_reward_chain", "batch64", "learned"]
+                                 + ([] if args.no_aircraft else ["aircraft_mission"]))
         jobs["cpu"] = start_cpu_jobs(pool, cpu_labels)
     if not args.no_extras:
         for kind in ("grid2d", "grid4d_f32", "grid4d_i32_edge", "learned:1000"):
@@ -516,6 +533,11 @@ def run(args, pool=None):
         else:
             out["learned"] = {"skipped": "no trained weights"}
         print("[bench] learned done", file=sys.stderr, flush=True)
+        if not args.no_aircraft:
+            import synth.aircraft as SA
+            out["configs"]["aircraft_mission_200x70x75x135_k35"] = aircraft_mission(
+                SA.PAPER_DIMS, samples=500, timed_solve=False,
+                log=lambda m: print(f"[bench] aircraft {m}", file=sys.stderr, flush=True))
     if "cpu" in jobs:
         cpu = dict(jobs["cpu"].get())
         print("[bench] cpu baselines done", file=sys.stderr, flush=True)
@@ -531,6 +553,8 @@ def run(args, pool=None):
             attach_cpu(out["batch64"], cpu, "batch64", info)
             if "plain" in out["learned"]:
                 attach_cpu(out["learned"], cpu, "learned", info)
+            if "aircraft_mission_200x70x75x135_k35" in out["configs"]:
+                attach_cpu(out["configs"]["aircraft_mission_200x70x75x135_k35"], cpu, "aircraft_mission", info)
     return out
 
 
@@ -657,6 +681,96 @@ def paper_scale_run(args):
     }
 
 
+def aircraft_mission(dims, cone=0, steps=4, samples=2000, timed_solve=True, log=None):
+    """The aircraft mission of the paper's example on the device-built
+    abstraction (gbf_load_aircraft): problem 1 (back to the runway), then
+    problem 2 (over the fire, G_2 = V_1), each loaded (enclosure table, cell
+    sets, reverse rows), solved once with per-launch events (roofline) and,
+    if timed_solve, once more for the solve time; the GPU's fixed-point
+    residual over every state, and the oracle's own check at sampled states
+    (its table and sets, one application of the operator)."""
+    import numpy as np
+    import torch
+
+    import oracle.aircraft as OA
+    import paper_2001_06231_amd as gbf
+    import synth.aircraft as SA
+
+    log = log or (lambda msg: None)
+    dims = tuple(int(v) for v in dims)
+    area = (SA.PAPER_AREA[0] * dims[0] // SA.PAPER_DIMS[0], SA.PAPER_AREA[1] * dims[1] // SA.PAPER_DIMS[1])
+    sets = "the paper's sets" if not cone and dims == SA.PAPER_DIMS else \
+        (f"landing within {cone} degrees at any speed" if cone else "sets scaled with the area")
+    out = {"workload": f"aircraft mission (problem 1, then problem 2 with G_2 = V_1) on a "
+                       f"{'x'.join(map(str, dims))} grid over {area[0]} m x {area[1]} m, 35 inputs, {sets}; "
+                       f"abstraction built on the device, images from the enclosure table",
+           "dims": list(dims), "area_m": list(area), "landing_cone_deg": cone or None, "steps_per_period": steps}
+    rng = np.random.default_rng(11)
+    G_dev = None
+    V_prev_host = None
+    for stage in (1, 2):
+        scn = SA.scenario(dims, area, stage=stage, cone=cone, steps=steps)
+        n, K = scn.n, scn.K
+        t0 = time.time()
+        gr = gbf.load_aircraft(scn, G=G_dev)
+        torch.cuda.synchronize()
+        load_s = time.time() - t0
+        log(f"problem {stage}: loaded n={n} pairs={n * K} in {load_s:.2f}s")
+        V = torch.empty(n, dtype=torch.float32, device="cuda")
+        status, st_prof, _ = gr.solve(V, profile=True)
+        log(f"problem {stage}: profiled solve {st_prof['solve_ms']:.0f} ms, {st_prof['rounds']} rounds")
+        st = st_prof
+        if timed_solve:
+            status, st, _ = gr.solve(V)
+            log(f"problem {stage}: solve {st['solve_ms']:.0f} ms")
+        pol = torch.empty(n, dtype=torch.int32, device="cuda")
+        _, res = gr.policy(pol)
+        rl = roofline([st_prof], n * K, PER_EDGE_BYTES["box"])
+        rl["kernel"] = "k_ac_relax"
+        Vh = V.cpu().numpy()
+        t0 = time.time()
+        T = OA.table(scn)
+        avoid = OA.cell_set(scn, scn.avoid, False)
+        reward = OA.cell_set(scn, scn.reward, True) if stage == 2 else np.zeros(1, dtype=bool)
+        Gh = (np.where(OA.cell_set(scn, scn.target, True), np.float32(0), np.float32(np.inf)).astype(np.float32)
+              if stage == 1 else V_prev_host)
+        fin = np.nonzero(np.isfinite(Vh))[0]
+        xs = np.concatenate([rng.integers(0, n, samples // 2),
+                             fin[rng.integers(0, fin.size, samples // 2)] if fin.size else []])
+        bad = OA.sampled_residual(scn, T, Vh, Gh, avoid, reward, xs.astype(np.int64))
+        check_s = time.time() - t0
+        log(f"problem {stage}: oracle check at {xs.size} states: {bad} mismatches in {check_s:.1f}s")
+        out[f"problem{stage}"] = {
+            "status": int(status), "enc_used": int(st["enc_used"]), "device_bytes": int(st["device_bytes"]),
+            "load_s": load_s, "solve_ms": st["solve_ms"], "rounds": int(st["rounds"]),
+            "pair_evals": int(st["pair_evals"]), "edge_relax": int(st["edge_relax"]),
+            "expansions": int(st["expansions"]), "marks": int(st["marks"]),
+            "edge_relax_per_s": st["edge_relax"] / (st["solve_ms"] * 1e-3), "roofline": rl,
+            "gpu_residual_states": int(res), "oracle_sample_states": int(xs.size),
+            "oracle_sample_mismatches": int(bad), "oracle_check_s": check_s,
+            "finite_states": int(fin.size), "V_max_finite": float(Vh[fin].max()) if fin.size else None,
+            "V_min": float(Vh[fin].min()) if fin.size else None}
+        if stage == 2:
+            out["problem2"]["states_improved_by_reward"] = int((Vh < V_prev_host).sum())
+        gr.free()
+        G_dev = V
+        V_prev_host = Vh
+    del G_dev
+    torch.cuda.empty_cache()
+    return out
+
+
+def aircraft_run(args):
+    """--aircraft: the mission on the grid given; prints one JSON object."""
+    def log(msg):
+        print(f"[aircraft] {msg}", file=sys.stderr, flush=True)
+
+    import torch
+    torch.cuda.set_device(0)
+    return aircraft_mission(args.aircraft_grid.split("x"), args.aircraft_cone, args.aircraft_steps,
+                            args.aircraft_samples, log=log)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -676,6 +790,16 @@ def main():
                     help="instead: the 141.75 M-cell, 35-input grid with 64-bit pair ids (~200 GB of device memory)")
     ap.add_argument("--paper-expand", type=int, default=2, help="expand_box for --paper-scale (2 = reverse CSR)")
     ap.add_argument("--paper-samples", type=int, default=1000000)
+    ap.add_argument("--aircraft", action="store_true",
+                    help="instead: the aircraft mission on the device-built abstraction")
+    ap.add_argument("--aircraft-grid", default="200x70x75x135",
+                    help="cells on x1, x2, heading, speed (the area scales with the first two)")
+    ap.add_argument("--aircraft-samples", type=int, default=2000)
+    ap.add_argument("--no-aircraft", action="store_true",
+                    help="leave the aircraft mission on the paper's grid out of the default run")
+    ap.add_argument("--aircraft-cone", type=int, default=0,
+                    help="landing headings within +-cone degrees at any speed (0 = the paper's landing set)")
+    ap.add_argument("--aircraft-steps", type=int, default=4, help="integration steps per sampling period")
     ap.add_argument("--workers", type=int, default=8,
                     help="worker processes for input generation and the CPU oracle (1 = none, e.g. under a "
                          "profiler)")
@@ -686,12 +810,15 @@ def main():
         sys.exit(2)
     # the worker processes are forked before the first GPU call
     pool = None
-    if args.workers > 1 and not args.paper_scale and (args.learned_eval or not args.no_extras or not args.no_cpu):
+    if args.workers > 1 and not args.paper_scale and not args.aircraft and (
+            args.learned_eval or not args.no_extras or not args.no_cpu):
         import multiprocessing as mp
         pool = mp.get_context("fork").Pool(args.workers)
     try:
         if args.paper_scale:
             print(json.dumps(paper_scale_run(args)), flush=True)
+        elif args.aircraft:
+            print(json.dumps(aircraft_run(args)), flush=True)
         elif args.learned_eval:
             print(json.dumps(learned_eval(args, pool)), flush=True)
         else:
