@@ -487,7 +487,6 @@ __global__ __launch_bounds__(256) void k_ac_relax(const Inst* __restrict__ It, R
     const Grid4 g = grid_of(I);
     const int K = I.K;
     Key* V = static_cast<Key*>(I.V);
-    uint8_t* next = R.dirty[(round + 1) & 1];
     const Id* list = WIDE ? (const Id*)R.list64 : (const Id*)R.list;
     const int lane = lane_id(), sub = lane & (kLanes - 1);
     Counts c;
@@ -531,12 +530,48 @@ __global__ __launch_bounds__(256) void k_ac_relax(const Inst* __restrict__ It, R
                 c.impr += improved;
             }
         }
-        unsigned long long bal = __ballot(improved);
-        while (bal) {
-            const int l = __ffsll((long long)bal) - 1;
-            bal &= bal - 1;
-            const uint32_t y = (uint32_t)__shfl((int)x, l, kWave);
-            expand<Id>(I, A, g, y, next, c);
+        // the expansion waits for the end of the round (k_ac_expand): marks
+        // only feed the next round, so one expansion per improved state and
+        // round gives the same next frontier as one per improvement
+        if (improved) gp(A.imp)[x] = 1;
+    }
+    flush(c, s_c, R.slots);
+}
+
+// The round's improved states, each expanded once by a whole wave; the
+// flags are cleared for the next round.  Lanes read 16 flags at a time.
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_ac_expand(const Inst* __restrict__ It, Run R, int round) {
+    using Id = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+    const Id count = WIDE ? (Id)R.counts64[round] : (Id)R.counts[round];
+    if (count == 0) return;
+    __shared__ unsigned long long s_c[6];
+    if (threadIdx.x < 6) s_c[threadIdx.x] = 0;
+    __syncthreads();
+    const Inst& I = It[0];
+    const AcInst A = *I.ac;
+    const Grid4 g = grid_of(I);
+    uint8_t* next = R.dirty[(round + 1) & 1];
+    Counts c;
+    const int64_t nchunk = (I.n + 15) / 16;
+    const int64_t nw = (nchunk + kWave - 1) / kWave;
+    for (int64_t w = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; w < nw;
+         w += (int64_t)gridDim.x * (blockDim.x / kWave)) {
+        const int64_t ch = w * kWave + lane_id();
+        uint4 f = make_uint4(0u, 0u, 0u, 0u);
+        uint4* flags = reinterpret_cast<uint4*>(A.imp);
+        if (ch < nchunk) f = flags[ch];
+        const bool any = (f.x | f.y | f.z | f.w) != 0u;
+        if (!__ballot(any)) continue;
+        if (any) flags[ch] = make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t word[4] = {f.x, f.y, f.z, f.w};
+        for (int b = 0; b < 16; ++b) {
+            unsigned long long bal = __ballot(((word[b >> 2] >> (8 * (b & 3))) & 0xffu) != 0u);
+            while (bal) {
+                const int l = __ffsll((long long)bal) - 1;
+                bal &= bal - 1;
+                expand<Id>(I, A, g, (uint32_t)((w * kWave + l) * 16 + b), next, c);
+            }
         }
     }
     flush(c, s_c, R.slots);
@@ -666,6 +701,13 @@ hipError_t launch_ac_relax(const Inst* dI, const Run& R, int round, int grid, hi
         if (stage2) k_ac_relax<TF32, false, true><<<nb, 256, 0, s>>>(dI, R, round);
         else k_ac_relax<TF32, false, false><<<nb, 256, 0, s>>>(dI, R, round);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_ac_expand(const Inst* dI, const Run& R, int round, int64_t n, hipStream_t s, bool wide) {
+    const int nb = blocks_for(((n + 15) / 16 + kWave - 1) / kWave, 4, 4096);
+    if (wide) k_ac_expand<true><<<nb, 256, 0, s>>>(dI, R, round);
+    else k_ac_expand<false><<<nb, 256, 0, s>>>(dI, R, round);
     return hipGetLastError();
 }
 

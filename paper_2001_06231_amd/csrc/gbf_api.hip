@@ -713,6 +713,9 @@ extern "C" int gbf_load_aircraft(const gbf_aircraft* a, void* hip_stream, gbf_gr
     uint32_t* rptr;
     unsigned long long* bad;
     AcInst* dac;
+    uint8_t* imp;
+    if ((rc = M.alloc((void**)&imp, (n + 15) / 16 * 16))) return rc;
+    HIPC(launch_fill_u32((uint32_t*)imp, 0, (n + 15) / 16 * 4, s));
     if ((rc = M.alloc((void**)&G, n * 4)) || (rc = M.alloc((void**)&avoid, n)) || (rc = M.alloc(&V, n * 4)) ||
         (rc = M.alloc((void**)&tab, rows * 8)) || (rc = M.alloc((void**)&rptr, (rows + 1) * 4)) ||
         (rc = M.alloc((void**)&gu, K * 4)) || (rc = M.alloc((void**)&bad, 16)) ||
@@ -753,6 +756,7 @@ extern "C" int gbf_load_aircraft(const gbf_aircraft* a, void* hip_stream, gbf_gr
     A.rent = rent;
     A.reward = reward;
     A.gu = gu;
+    A.imp = imp;  // zero here; every round's expansion clears what its relax step set
     std::memcpy(&A.rc, &a->reward_cost, 4);
     A.stage = stage;
     HIPC(hipMemcpyAsync(dac, &A, sizeof(A), hipMemcpyHostToDevice, s));
@@ -1037,8 +1041,12 @@ static int enqueue_hostloop(Scratch& S, const Plan& P, const gbf_opts& o, hipStr
             else HIPC(launch_compact(R, (int)(r + k), P.compact_grid, s, P.wide));
             const bool timed = o.profile && ev + 1 < (int)S.events.size();
             if (timed) HIPC(hipEventRecord(S.events[ev], s));
-            if (enc_mask == 16) HIPC(launch_ac_relax(S.dinst, R, (int)(r + k), P.grid, s, P.wide, P.ac_stage));
-            else HIPC(launch_relax(S.dinst, R, (int)(r + k), P.grid, P.lanes, P.dtype, enc_mask, s, P.wide, P.block));
+            if (enc_mask == 16) {
+                HIPC(launch_ac_relax(S.dinst, R, (int)(r + k), P.grid, s, P.wide, P.ac_stage));
+                HIPC(launch_ac_expand(S.dinst, R, (int)(r + k), P.max_states, s, P.wide));
+            } else {
+                HIPC(launch_relax(S.dinst, R, (int)(r + k), P.grid, P.lanes, P.dtype, enc_mask, s, P.wide, P.block));
+            }
             if (timed) {
                 HIPC(hipEventRecord(S.events[ev + 1], s));
                 ev += 2;

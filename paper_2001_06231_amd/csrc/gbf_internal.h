@@ -59,6 +59,7 @@ struct AcInst {
     const uint2* rent;
     const uint8_t* reward;  // [n] transitions into these cells cost rc (problem 2), or NULL
     const int32_t* gu;      // [K] running cost bits (fp32) per input
+    uint8_t* imp;           // [n rounded up to 16] 1 = the state improved in this round (cleared by the expansion)
     int32_t rc;             // reward cost bits (fp32)
     int32_t stage;          // 1: costs per pair gu[u]; 2: per transition (gu[u] or rc)
 };
@@ -180,6 +181,9 @@ hipError_t launch_ac_rev_fill(const AcSpec& S, const uint2* tab, const uint32_t*
 hipError_t launch_ac_scan(uint32_t* rptr, int64_t rows, hipStream_t s);
 hipError_t launch_ac_relax(const Inst* dI, const Run& R, int round, int grid, hipStream_t s, bool wide, int stage);
 hipError_t launch_ac_seed(const Inst* dI, const Run& R, int64_t n, hipStream_t s, bool wide);
+// After a round's relax step: every state flagged as improved is expanded
+// once into the next frontier and its flag cleared.
+hipError_t launch_ac_expand(const Inst* dI, const Run& R, int round, int64_t n, hipStream_t s, bool wide);
 hipError_t launch_ac_policy(const Inst& I, int32_t* pol, unsigned long long* bad, hipStream_t s);
 hipError_t launch_policy(const Inst& I, int dtype, int32_t* pol, unsigned long long* bad, hipStream_t s);
 
