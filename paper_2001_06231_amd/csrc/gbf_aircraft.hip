@@ -375,6 +375,10 @@ __global__ __launch_bounds__(1024) void k_ac_scan(uint32_t* p, int64_t n) {
 
 // ------------------------------------------------------------ the solver
 constexpr int kLanes = 8;      // lanes per listed pair
+#ifndef GBF_AC_MARK
+#define GBF_AC_MARK 4
+#endif
+constexpr int kMarkBatch = GBF_AC_MARK;  // predecessor marks in flight per lane
 constexpr int kSlotWords = 8;  // Run.slots: 8 counters per block, the first 6 used
 
 struct Grid4 {
@@ -443,14 +447,26 @@ __device__ __forceinline__ void expand(const Inst& I, const AcInst& A, const Gri
         const int a1 = max(max(k1 - o1hi, -o1lo), 0), b1 = min(min(k1 - o1lo, g.n1 - 1 - o1hi), g.n1 - 1);
         const int a2 = max(max(k2 - o2hi, -o2lo), 0), b2 = min(min(k2 - o2lo, g.n2 - 1 - o2hi), g.n2 - 1);
         const uint32_t hi = (uint32_t)g.n1 * (uint32_t)g.n2 * ((uint32_t)i3 + (uint32_t)g.n3 * (uint32_t)i4);
-        for (int x2 = a2; x2 <= b2; ++x2)
-            for (int x1 = a1; x1 <= b1; ++x1) {
-                const uint32_t x = (uint32_t)x1 + (uint32_t)g.n1 * (uint32_t)x2 + hi;
-                const Id q = (Id)x * (Id)K + (Id)u;
-                GBF_GLOBAL uint8_t* b = gp(dirty) + q;
-                if (*b == 0) *b = 1;
-                c.marks += 1;
+        const int w1 = b1 - a1 + 1, w2 = b2 - a2 + 1;
+        const int cnt = (w1 > 0 && w2 > 0) ? w1 * w2 : 0;
+        c.marks += (uint32_t)cnt;
+        // kMarkBatch window cells at a time: every byte load issues before
+        // the first wait (positions past the window repeat its last cell)
+        for (int w0 = 0; w0 < cnt; w0 += kMarkBatch) {
+            Id q[kMarkBatch];
+            uint8_t v[kMarkBatch];
+#pragma unroll
+            for (int k = 0; k < kMarkBatch; ++k) {
+                const int w = min(w0 + k, cnt - 1);
+                const int x2 = a2 + w / w1, x1 = a1 + w - (w / w1) * w1;
+                q[k] = (Id)((uint32_t)x1 + (uint32_t)g.n1 * (uint32_t)x2 + hi) * (Id)K + (Id)u;
             }
+#pragma unroll
+            for (int k = 0; k < kMarkBatch; ++k) v[k] = gp(dirty)[q[k]];
+#pragma unroll
+            for (int k = 0; k < kMarkBatch; ++k)
+                if (w0 + k < cnt && v[k] == 0) gp(dirty)[q[k]] = 1;
+        }
     }
 }
 
