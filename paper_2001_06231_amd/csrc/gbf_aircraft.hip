@@ -374,10 +374,27 @@ __global__ __launch_bounds__(1024) void k_ac_scan(uint32_t* p, int64_t n) {
 }
 
 // ------------------------------------------------------------ the solver
-constexpr int kLanes = 8;      // lanes per listed pair
+// Lanes per listed pair: problem 1 (costs per pair) and problem 2 (a
+// reward flag per successor as well).  Measured at the paper's grid: 4 and
+// 8 (problem 1: 6.1-6.4 s against 7.1-7.4 s with 8; problem 2: 2.25 s
+// against 2.39 s with 4).
+#ifndef GBF_AC_LANES1
+#define GBF_AC_LANES1 4
+#endif
+#ifndef GBF_AC_LANES2
+#define GBF_AC_LANES2 8
+#endif
 #ifndef GBF_AC_MARK
 #define GBF_AC_MARK 4
 #endif
+// Successor values in flight per lane.  Batches of 2 and 4 were measured
+// slower at the paper's grid (10.0 and 11.6 s for problem 1): the faster
+// gathers evaluate pairs before their successors' improvements of the same
+// round land, and the solve then makes 33-52% more pair evaluations.
+#ifndef GBF_AC_GATHER
+#define GBF_AC_GATHER 1
+#endif
+constexpr int kGatherBatch = GBF_AC_GATHER;
 constexpr int kMarkBatch = GBF_AC_MARK;  // predecessor marks in flight per lane
 constexpr int kSlotWords = 8;  // Run.slots: 8 counters per block, the first 6 used
 
@@ -484,7 +501,8 @@ __device__ __forceinline__ void flush(Counts& c, unsigned long long* s_c, unsign
 // box; the group's first lane forms the backup and updates W(x); the wave
 // then expands its improved states one after the other.
 template <class T, bool WIDE, bool STAGE2>
-__global__ __launch_bounds__(256) void k_ac_relax(const Inst* __restrict__ It, Run R, int round) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+void k_ac_relax(const Inst* __restrict__ It, Run R, int round) {
     using Id = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
     using Key = typename T::key_t;
     const Id count = WIDE ? (Id)R.counts64[round] : (Id)R.counts[round];
@@ -504,6 +522,7 @@ __global__ __launch_bounds__(256) void k_ac_relax(const Inst* __restrict__ It, R
     const int K = I.K;
     Key* V = static_cast<Key*>(I.V);
     const Id* list = WIDE ? (const Id*)R.list64 : (const Id*)R.list;
+    constexpr int kLanes = STAGE2 ? GBF_AC_LANES2 : GBF_AC_LANES1;
     const int lane = lane_id(), sub = lane & (kLanes - 1);
     Counts c;
     const Id waves = (Id)gridDim.x * (blockDim.x / kWave);
@@ -521,11 +540,27 @@ __global__ __launch_bounds__(256) void k_ac_relax(const Inst* __restrict__ It, R
         const int32_t gu = live ? A.gu[u] : 0;
         Key m = (Key)T::LOWEST;
         typename T::wide_t mw = T::WLOWEST;
-        for (uint32_t t = (uint32_t)sub; t < vol; t += kLanes) {
-            const uint32_t y = succ_cell(g, c1, c2, e, n1, n2, t);
-            const Key vy = V[y];
-            if (STAGE2) mw = T::wmax2(mw, T::edge(A.reward[y] ? A.rc : gu, vy));
-            else m = T::max2(m, vy);
+        // kGatherBatch cells per lane at a time, all their loads issued
+        // before the first wait (positions past the box repeat its last
+        // cell, which leaves the maximum unchanged)
+        for (uint32_t t0 = (uint32_t)sub; t0 < vol; t0 += kLanes * kGatherBatch) {
+            uint32_t y[kGatherBatch];
+#pragma unroll
+            for (int k = 0; k < kGatherBatch; ++k)
+                y[k] = succ_cell(g, c1, c2, e, n1, n2, min(t0 + (uint32_t)(k * kLanes), vol - 1u));
+            Key vy[kGatherBatch];
+#pragma unroll
+            for (int k = 0; k < kGatherBatch; ++k) vy[k] = gp(V)[y[k]];
+            if (STAGE2) {
+                uint8_t rw[kGatherBatch];
+#pragma unroll
+                for (int k = 0; k < kGatherBatch; ++k) rw[k] = gp(A.reward)[y[k]];
+#pragma unroll
+                for (int k = 0; k < kGatherBatch; ++k) mw = T::wmax2(mw, T::edge(rw[k] ? A.rc : gu, vy[k]));
+            } else {
+#pragma unroll
+                for (int k = 0; k < kGatherBatch; ++k) m = T::max2(m, vy[k]);
+            }
         }
 #pragma unroll
         for (int d = 1; d < kLanes; d <<= 1) {
