@@ -441,6 +441,7 @@ typedef struct gbf_aircraft {
     const gbf_ac_box* reward; int32_t n_reward;
     float reward_cost;      /* finite */
     const float* G;         /* device [n] or NULL */
+    int32_t pair_ids64;     /* 1 = 64-bit pair ids at any size; 0 = by size (n K >= 2^31) */
 } gbf_aircraft;
 
 /* The enclosure table: table (device int32 [dims[3] * dims[2] * K * 8]) gets,

@@ -132,7 +132,7 @@ class _Aircraft(ctypes.Structure):
                 ("target", ctypes.POINTER(_AcBox)), ("n_target", ctypes.c_int32),
                 ("avoid", ctypes.POINTER(_AcBox)), ("n_avoid", ctypes.c_int32),
                 ("reward", ctypes.POINTER(_AcBox)), ("n_reward", ctypes.c_int32),
-                ("reward_cost", ctypes.c_float), ("G", ctypes.c_void_p)]
+                ("reward_cost", ctypes.c_float), ("G", ctypes.c_void_p), ("pair_ids64", ctypes.c_int32)]
 
 
 def lib():
@@ -365,7 +365,7 @@ def load_graph(n, K, G, g, *, dtype="i32", encoding="csr", avoid=None, succ_ptr=
     return Graph(h, int(n), int(K), p.dtype, None)
 
 
-def _aircraft(scn, G=None):
+def _aircraft(scn, G=None, pair_ids64=False):
     """A gbf_aircraft struct for a scenario with the fields of
     synth.aircraft.Scenario (and the arrays it points to)."""
     a = _Aircraft()
@@ -388,6 +388,7 @@ def _aircraft(scn, G=None):
         setattr(a, name, ctypes.cast(arr, ctypes.POINTER(_AcBox)))
         setattr(a, "n_" + name, len(boxes))
     a.reward_cost = float(scn.reward_cost)
+    a.pair_ids64 = 1 if pair_ids64 else 0
     if G is not None:
         ptr, sp = _ptr(G)
         if sp != DEVICE or G.dtype.itemsize != 4 or G.numel() != int(np.prod(scn.dims)):
@@ -410,12 +411,13 @@ def aircraft_table(scn, stream=None):
     return out
 
 
-def load_aircraft(scn, G=None, stream=None) -> Graph:
+def load_aircraft(scn, G=None, stream=None, pair_ids64=False) -> Graph:
     """gbf_load_aircraft: the abstraction of a scenario, built on the device.
     G (float32 device tensor over the cells, e.g. the values of a first
-    problem) replaces the target sets as terminal cost."""
+    problem) replaces the target sets as terminal cost; pair_ids64 asks for
+    64-bit pair ids at any size."""
     L = lib()
-    a, keep = _aircraft(scn, G)
+    a, keep = _aircraft(scn, G, pair_ids64)
     h = ctypes.c_void_p()
     rc = L.gbf_load_aircraft(ctypes.byref(a), stream, ctypes.byref(h))
     if rc != OK:

@@ -611,6 +611,7 @@ static int ac_spec(const gbf_aircraft* a, AcSpec& S, AcSets* sets) {
     if (a->n_thrust < 1 || a->n_bank < 1 || a->n_thrust * a->n_bank > 255)
         return fail(GBF_EINVAL, "need 1 <= n_thrust * n_bank <= 255");
     if (!std::isfinite(a->reward_cost)) return fail(GBF_EINVAL, "reward_cost must be finite");
+    if (a->pair_ids64 != 0 && a->pair_ids64 != 1) return fail(GBF_EINVAL, "pair_ids64 must be 0 or 1");
     for (int k = 0; k < 2; ++k) S.x_max[k] = a->x_max[k], S.v_range[k] = a->v_range[k];
     S.mass = a->mass;
     S.p_D = a->p_D;
@@ -697,7 +698,7 @@ extern "C" int gbf_load_aircraft(const gbf_aircraft* a, void* hip_stream, gbf_gr
     I.dtype = GBF_F32;
     I.pair_base = 0;
     I.max_rounds = n;
-    gr->wide = n * K >= ((int64_t)1 << 31);
+    gr->wide = a->pair_ids64 == 1 || n * K >= ((int64_t)1 << 31);
     I.wide = gr->wide ? 1 : 0;
     for (int k = 0; k < 4; ++k) I.dims[k] = gr->dims[k] = S.dims[k];
     I.strides[0] = 1;

@@ -56,18 +56,19 @@ def _exact(label, V, pol, res, ref):
     assert badp.size == 0, (label, "policy differs at", badp[:10], pol[badp[:10]], ref["policy"][badp[:10]])
 
 
-@pytest.mark.parametrize("make", [SA.small, SA.medium], ids=["small", "medium"])
-def test_mission_parity(make):
+@pytest.mark.parametrize("make,wide", [(SA.small, False), (SA.medium, False), (SA.small, True)],
+                         ids=["small", "medium", "small_ids64"])
+def test_mission_parity(make, wide):
     import torch
     s1, s2 = make(1), make(2)
-    _case(f"mission {s1.name}")
+    _case(f"mission {s1.name} ids64={wide}")
     # GPU: Pi_1, then Pi_2 with its own V_1 as terminal cost
-    g1 = gbf.load_aircraft(s1)
+    g1 = gbf.load_aircraft(s1, pair_ids64=wide)
     V1 = torch.empty(s1.n, dtype=torch.float32, device="cuda")
     status, st1, _ = g1.solve(V1)
     assert status == gbf.OK and st1["enc_used"] == 3
     pol1, res1 = g1.policy()
-    g2 = gbf.load_aircraft(s2, G=V1)
+    g2 = gbf.load_aircraft(s2, G=V1, pair_ids64=wide)
     status, st2, V2 = g2.solve()
     assert status == gbf.OK
     pol2, res2 = g2.policy()
@@ -115,3 +116,33 @@ def test_rejects_bad_scenarios():
     with pytest.raises(gbf.GbfError):
         gbf.solve_batch([g, g])
     g.free()
+
+
+def test_paper_grid_sampled():
+    """The paper's grid (141.75 M cells, 35 inputs, 4.96 G pairs: 64-bit ids)
+    in the configuration the benchmark times: the GPU's residual over every
+    state, and the oracle's own operator (its table and sets) at sampled
+    states, for both problems."""
+    import torch
+    rng = np.random.default_rng(12)
+    G = None
+    Vprev = None
+    for stage in (1, 2):
+        scn = SA.scenario(stage=stage)
+        _case(f"paper grid problem {stage}")
+        g = gbf.load_aircraft(scn, G=G)
+        V = torch.empty(scn.n, dtype=torch.float32, device="cuda")
+        status, st, _ = g.solve(V)
+        assert status == gbf.OK and st["rounds"] > 50
+        _, res = g.policy(torch.empty(scn.n, dtype=torch.int32, device="cuda"))
+        assert res == 0
+        Vh = V.cpu().numpy()
+        fin = np.nonzero(np.isfinite(Vh))[0]
+        xs = np.concatenate([rng.integers(0, scn.n, 150), fin[rng.integers(0, fin.size, 150)]])
+        avoid = OA.cell_set(scn, scn.avoid, False)
+        reward = OA.cell_set(scn, scn.reward, True) if stage == 2 else np.zeros(1, dtype=bool)
+        Gh = np.where(OA.cell_set(scn, scn.target, True), np.float32(0), np.float32(np.inf)).astype(np.float32) \
+            if stage == 1 else Vprev
+        assert OA.sampled_residual(scn, OA.table(scn), Vh, Gh, avoid, reward, xs) == 0
+        g.free()
+        G, Vprev = V, Vh
