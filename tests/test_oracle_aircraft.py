@@ -232,3 +232,44 @@ def test_containment_pin_catches_planted_mistakes(mutant, tmp_path):
                 y = flow(np.where([(c >> a) & 1 for a in range(4)], hi, lo), u1, u2)
                 caught |= bool(np.any(y < olo - 1e-9) or np.any(y > ohi + 1e-9))
         assert caught, mutant
+
+
+def test_closed_loop_keeps_the_guarantee():
+    """The method's guarantee (Sect. V-B with the theorem on Algorithm 1):
+    the controller of the abstraction, applied to the real aircraft (its ODE
+    integrated independently, the input held for tau and chosen from the
+    cell the state is in), keeps it inside the area and off the obstacles
+    and reaches the target with an accumulated cost of at most V(x0).  An
+    enclosure that misses part of an attainable set would break this."""
+    scn = SA.small(1)
+    P = OA.problem(scn)
+    r = oracle.solve(P, precision="f32")
+    V, pol = r["V"], r["policy"]
+    N1, N2, N3, N4 = scn.dims
+    eta = np.array([scn.x_max[0] / N1, scn.x_max[1] / N2, 2 * math.pi / N3, 35.0 / N4])
+    lo = np.array([0.0, 0.0, -math.pi, 50.0])
+    gu = OA.pair_cost(scn)
+    rng = np.random.default_rng(8)
+    start = np.nonzero(np.isfinite(V) & ~P.target)[0]
+    assert start.size > 100
+    for x0 in rng.choice(start, 40, replace=False):
+        c = np.array([x0 % N1, (x0 // N1) % N2, (x0 // (N1 * N2)) % N3, x0 // (N1 * N2 * N3)])
+        s = lo + (c + rng.uniform(0.05, 0.95, 4)) * eta
+        cost = 0.0
+        for _ in range(400):
+            c = np.floor((s - lo) / eta).astype(int)
+            assert np.all(c >= 0) and c[0] < N1 and c[1] < N2 and c[3] < N4, ("left the area", x0, s)
+            x = int(c[0] + N1 * (c[1] + N2 * (c[2] + N3 * c[3])))
+            assert not P.avoid[x], ("obstacle", x0, s)
+            if pol[x] == oracle.HANDOVER:
+                break
+            u = int(pol[x])
+            assert u >= 0, ("no controller", x0, x)
+            cost += float(gu[u])
+            s = flow(s, OA.lib().oracle_ac_thrust(u // scn.n_bank, scn.n_thrust, scn.thrust_max),
+                     OA.bank_rad(scn, u % scn.n_bank), mass=scn.mass)
+            s[2] = (s[2] + math.pi) % (2 * math.pi) - math.pi
+        else:
+            raise AssertionError(("target not reached", x0))
+        assert P.target[x]
+        assert cost <= float(V[x0]) + 1e-4, (x0, cost, V[x0])
