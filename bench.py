@@ -708,6 +708,7 @@ def aircraft_mission(dims, cone=0, steps=4, samples=2000, timed_solve=True, log=
     rng = np.random.default_rng(11)
     G_dev = None
     V_prev_host = None
+    policies, values, scns = {}, {}, {}
     for stage in (1, 2):
         scn = SA.scenario(dims, area, stage=stage, cone=cone, steps=steps)
         n, K = scn.n, scn.K
@@ -752,12 +753,104 @@ def aircraft_mission(dims, cone=0, steps=4, samples=2000, timed_solve=True, log=
             "V_min": float(Vh[fin].min()) if fin.size else None}
         if stage == 2:
             out["problem2"]["states_improved_by_reward"] = int((Vh < V_prev_host).sum())
+        policies[stage] = pol.cpu().numpy()
+        values[stage] = Vh
+        scns[stage] = scn
         gr.free()
         G_dev = V
         V_prev_host = Vh
     del G_dev
     torch.cuda.empty_cache()
+    out["closed_loop"] = closed_loop(scns, values, policies, rng)
+    log(f"closed loop: {out['closed_loop']}")
     return out
+
+
+def closed_loop(scns, values, policies, rng, start=(840.0, 140.0, 0.0, 53.0)):
+    """The mission flown on the real aircraft: its ODE integrated by scipy
+    (DOP853) for tau per step, the input chosen by the controller of the cell
+    the state is in, held for the step; problem 2's controller until it
+    hands over (V2 = G2 = V1 there), then problem 1's until the runway.
+    Starts from the paper's start point (840 m, 140 m, heading 0, 53 m/s)
+    if the reward lowers its value (V2 < V1 there), else from the centre of
+    a random cell where it does (at the start point itself, inside the
+    runway-landing set, V2 = V1 = 0 for these seeded fires: the detour does
+    not pay).
+    Reports the path and whether it stayed safe, reached the runway, and
+    spent at most V2 of its start (the method's guarantee)."""
+    import math
+
+    import numpy as np
+    from scipy.integrate import solve_ivp
+
+    import oracle.aircraft as OA
+
+    s1, s2 = scns[1], scns[2]
+    N1, N2, N3, N4 = s1.dims
+    eta = np.array([s1.x_max[0] / N1, s1.x_max[1] / N2, 2 * math.pi / N3, (s1.v_range[1] - s1.v_range[0]) / N4])
+    lo = np.array([0.0, 0.0, -math.pi, float(s1.v_range[0])])
+    avoid = OA.cell_set(s1, s1.avoid, False)
+    target = OA.cell_set(s1, s1.target, True)
+    reward = OA.cell_set(s2, s2.reward, True) if s2.reward else np.zeros(s2.n, dtype=bool)
+
+    def cell(st):
+        c = np.floor((st - lo) / eta).astype(np.int64)
+        if c[0] < 0 or c[1] < 0 or c[3] < 0 or c[0] >= N1 or c[1] >= N2 or c[3] >= N4:
+            return -1
+        return int(c[0] + N1 * (c[1] + N2 * (c[2] % N3 + N3 * c[3])))
+
+    st = np.array([start[0], start[1], math.radians(start[2]), start[3]])
+    x0 = cell(st)
+    from_paper = x0 >= 0 and bool(values[2][x0] < values[1][x0])
+    if not from_paper:
+        fin = np.nonzero(values[2] < values[1])[0]
+        x0 = int(fin[rng.integers(0, fin.size)])
+        c = np.array([x0 % N1, (x0 // N1) % N2, (x0 // (N1 * N2)) % N3, x0 // (N1 * N2 * N3)])
+        st = lo + (c + 0.5) * eta
+    res = {"start": [round(float(v), 3) for v in st], "start_from_paper_point": bool(from_paper),
+           "V2_start": float(values[2][x0]), "V1_start": float(values[1][x0])}
+    cost, steps, stage, safe, handover, fire_steps = 0.0, [0, 0], 2, True, None, 0
+    gus = {k: OA.pair_cost(scns[k]) for k in (1, 2)}
+    for _ in range(2000):
+        x = cell(st)
+        if x < 0 or avoid[x]:
+            safe = False
+            break
+        u = int(policies[stage][x])
+        if u == -1:  # hand over: problem 2 to problem 1, or problem 1 at the runway
+            if stage == 2:
+                handover = [round(float(v), 3) for v in st]
+                stage = 1
+                continue
+            break
+        if u < 0:
+            safe = False
+            break
+        scn = scns[stage]
+        b = OA.bank_rad(scn, u % scn.n_bank)
+        u1 = OA.lib().oracle_ac_thrust(u // scn.n_bank, scn.n_thrust, scn.thrust_max)
+        g = float(gus[stage][u])
+
+        def f(t, y, u1=u1, b=b, m=scn.mass):
+            return [y[3] * math.cos(y[2]), y[3] * math.sin(y[2]), scn.p_L * y[3] * math.sin(b) / m,
+                    (u1 - scn.p_D * y[3] ** 2) / m]
+
+        st = solve_ivp(f, (0.0, scn.tau), list(st), method="DOP853", rtol=1e-10, atol=1e-10).y[:, -1]
+        st[2] = (st[2] + math.pi) % (2 * math.pi) - math.pi
+        if stage == 2:
+            y = cell(st)
+            cost += float(s2.reward_cost) if (y >= 0 and reward[y]) else g
+        else:
+            cost += g
+        steps[2 - stage] += 1
+        if stage == 2 and y >= 0 and reward[y]:
+            fire_steps += 1
+    x = cell(st)
+    res.update({"handover": handover, "end": [round(float(v), 3) for v in st], "steps_problem2": steps[0],
+                "steps_problem1": steps[1], "steps_in_fire": fire_steps, "cost": round(cost, 4), "safe": bool(safe),
+                "reached_runway": bool(x >= 0 and target[x]),
+                "cost_within_V2": bool(cost <= res["V2_start"] + 1e-3)})
+    return res
 
 
 def aircraft_run(args):
