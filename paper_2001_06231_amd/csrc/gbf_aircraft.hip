@@ -337,7 +337,7 @@ __global__ __launch_bounds__(256) void k_ac_rev(AcSpec S, const uint2* tab, cons
             for (int d = 0; d < t.n3; ++d) {
                 int k3 = t.j3 + d;
                 if (k3 >= N3) k3 -= N3;
-                const int64_t row = ((int64_t)k4 * N3 + k3) * K + u;
+                const int64_t row = (int64_t)k4 * N3 + k3;
                 if (FILL) {
                     const uint32_t at = rptr[row] + atomicAdd(cnt + row, 1u);
                     rent[at] = uint2{w.x, (uint32_t)i3 | (uint32_t)i4 << 8 | (uint32_t)u << 16};
@@ -348,8 +348,7 @@ __global__ __launch_bounds__(256) void k_ac_rev(AcSpec S, const uint2* tab, cons
     }
 }
 
-// scan in place over rows + 1 words (one block; the table has at most
-// 255 * 255 * 255 rows)
+// scan in place over rows + 1 words (one block; at most 255 * 255 rows)
 __global__ __launch_bounds__(1024) void k_ac_scan(uint32_t* p, int64_t n) {
     __shared__ uint32_t s[1024];
     const int64_t per = (n + 1023) / 1024;
@@ -370,6 +369,29 @@ __global__ __launch_bounds__(1024) void k_ac_scan(uint32_t* p, int64_t n) {
     for (int64_t i = a; i < b; ++i) {
         run += p[i];
         p[i] = run;
+    }
+}
+
+// Each reverse row sorted by source (speed cell, heading cell, input), one
+// thread per row (a row holds a few hundred entries): the entries of one
+// predecessor cell's inputs sit side by side, so the lanes that take them
+// mark neighbouring bytes x K + u of the frontier map.
+__global__ __launch_bounds__(256) void k_ac_sort(const uint32_t* rptr, uint2* rent, int64_t rows) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t a = rptr[r], b = rptr[r + 1];
+        for (uint32_t i = a + 1; i < b; ++i) {
+            const uint2 v = rent[i];
+            const uint32_t key = ((v.y >> 8) & 0xffu) << 16 | (v.y & 0xffu) << 8 | (v.y >> 16);
+            uint32_t j = i;
+            while (j > a) {
+                const uint2 w = rent[j - 1];
+                const uint32_t kw = ((w.y >> 8) & 0xffu) << 16 | (w.y & 0xffu) << 8 | (w.y >> 16);
+                if (kw <= key) break;
+                rent[j] = w;
+                --j;
+            }
+            rent[j] = v;
+        }
     }
 }
 
@@ -450,8 +472,8 @@ __device__ __forceinline__ void expand(const Inst& I, const AcInst& A, const Gri
     r /= (uint32_t)g.n2;
     const int k3 = (int)(r % (uint32_t)g.n3);
     const int k4 = (int)(r / (uint32_t)g.n3);
-    const int64_t row = ((int64_t)k4 * g.n3 + k3) * K;
-    const uint32_t r0 = A.rptr[row], r1 = A.rptr[row + K];
+    const int64_t row = (int64_t)k4 * g.n3 + k3;
+    const uint32_t r0 = A.rptr[row], r1 = A.rptr[row + 1];
     if (lane_id() == 0) c.expanded += 1;
     for (uint32_t t0 = r0; t0 < r1; t0 += kWave) {
         const uint32_t t = t0 + (uint32_t)lane_id();
@@ -739,6 +761,11 @@ hipError_t launch_ac_rev_fill(const AcSpec& S, const uint2* tab, const uint32_t*
 
 hipError_t launch_ac_scan(uint32_t* rptr, int64_t rows, hipStream_t s) {
     k_ac_scan<<<1, 1024, 0, s>>>(rptr, rows + 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_ac_sort(const uint32_t* rptr, uint2* rent, int64_t rows, hipStream_t s) {
+    k_ac_sort<<<blocks_for(rows, 256, 4096), 256, 0, s>>>(rptr, rent, rows);
     return hipGetLastError();
 }
 

@@ -675,7 +675,8 @@ extern "C" int gbf_load_aircraft(const gbf_aircraft* a, void* hip_stream, gbf_gr
     if (rc) return rc;
     const int64_t n = (int64_t)S.dims[0] * S.dims[1] * S.dims[2] * S.dims[3];
     const int K = S.n_thrust * S.n_bank;
-    const int64_t rows = (int64_t)S.dims[2] * S.dims[3] * K;
+    const int64_t rows = (int64_t)S.dims[2] * S.dims[3] * K;  // table entries
+    const int64_t rrows = (int64_t)S.dims[2] * S.dims[3];     // reverse rows
     const int stage = a->n_reward > 0 ? 2 : 1;
 
     std::unique_ptr<gbf_graph> gr(new gbf_graph());
@@ -718,7 +719,7 @@ extern "C" int gbf_load_aircraft(const gbf_aircraft* a, void* hip_stream, gbf_gr
     if ((rc = M.alloc((void**)&imp, (n + 15) / 16 * 16))) return rc;
     HIPC(launch_fill_u32((uint32_t*)imp, 0, (n + 15) / 16 * 4, s));
     if ((rc = M.alloc((void**)&G, n * 4)) || (rc = M.alloc((void**)&avoid, n)) || (rc = M.alloc(&V, n * 4)) ||
-        (rc = M.alloc((void**)&tab, rows * 8)) || (rc = M.alloc((void**)&rptr, (rows + 1) * 4)) ||
+        (rc = M.alloc((void**)&tab, rows * 8)) || (rc = M.alloc((void**)&rptr, (rrows + 1) * 4)) ||
         (rc = M.alloc((void**)&gu, K * 4)) || (rc = M.alloc((void**)&bad, 16)) ||
         (rc = M.alloc((void**)&dac, sizeof(AcInst))))
         return rc;
@@ -728,21 +729,22 @@ extern "C" int gbf_load_aircraft(const gbf_aircraft* a, void* hip_stream, gbf_gr
     HIPC(launch_ac_table(S, nullptr, tab, bad, s));
     HIPC(launch_ac_sets(S, sets, a->G, G, avoid, reward, s));
     // reverse rows: counts, scan, fill
-    HIPC(launch_fill_u32(rptr, 0, rows + 1, s));
+    HIPC(launch_fill_u32(rptr, 0, rrows + 1, s));
     HIPC(launch_ac_rev_count(S, tab, rptr, s));
-    HIPC(launch_ac_scan(rptr, rows, s));
+    HIPC(launch_ac_scan(rptr, rrows, s));
     unsigned long long hb[2] = {0, 0};
     uint32_t total = 0;
     HIPC(hipMemcpyAsync(hb, bad, 16, hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(&total, rptr + rows, 4, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(&total, rptr + rrows, 4, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     if (hb[0]) return fail(GBF_EINVAL, std::to_string(hb[0]) + " enclosures without an a priori enclosure");
     if (hb[1]) return fail(GBF_EINVAL, "table offsets beyond +-127 cells (cells too small for the sampling time)");
     uint2* rent;
     uint32_t* cursor;
-    if ((rc = M.alloc((void**)&rent, (size_t)total * 8)) || (rc = M.alloc((void**)&cursor, rows * 4))) return rc;
-    HIPC(launch_fill_u32(cursor, 0, rows, s));
+    if ((rc = M.alloc((void**)&rent, (size_t)total * 8)) || (rc = M.alloc((void**)&cursor, rrows * 4))) return rc;
+    HIPC(launch_fill_u32(cursor, 0, rrows, s));
     HIPC(launch_ac_rev_fill(S, tab, rptr, cursor, rent, s));
+    HIPC(launch_ac_sort(rptr, rent, rrows, s));
     // running costs per input: tau + u2^2 rounded to fp32
     std::vector<int32_t> hgu(K);
     for (int u = 0; u < K; ++u) {
@@ -762,7 +764,7 @@ extern "C" int gbf_load_aircraft(const gbf_aircraft* a, void* hip_stream, gbf_gr
     A.stage = stage;
     HIPC(hipMemcpyAsync(dac, &A, sizeof(A), hipMemcpyHostToDevice, s));
     HIPC(hipStreamSynchronize(s));  // the host copies above must finish before they go out of scope
-    M.release(cursor, rows * 4);
+    M.release(cursor, rrows * 4);
     I.G = G;
     I.g = nullptr;
     I.avoid = avoid;

@@ -50,12 +50,12 @@ struct Inst {
 //     .y = j3lo | n3 << 8 | j4lo << 16 | j4hi << 24   (uint8: first heading
 //          cell, mod N3, and the number of heading cells; speed cells;
 //          n3 = 0: the enclosure leaves the speed range or was not found)
-//   reverse rows, key (k4 * N3 + k3) * K + u: the entries whose box holds
-//   heading cell k3 and speed cell k4, as
+//   reverse rows, key k4 * N3 + k3: the entries whose box holds heading
+//   cell k3 and speed cell k4, sorted by (i4, i3, u), as
 //     .x = the entry's offsets (as in tab), .y = i3 | i4 << 8 | u << 16.
 struct AcInst {
     const uint2* tab;
-    const uint32_t* rptr;   // [N4 * N3 * K + 1]
+    const uint32_t* rptr;   // [N4 * N3 + 1]
     const uint2* rent;
     const uint8_t* reward;  // [n] transitions into these cells cost rc (problem 2), or NULL
     const int32_t* gu;      // [K] running cost bits (fp32) per input
@@ -173,12 +173,13 @@ hipError_t launch_ac_table(const AcSpec& S, int32_t* full, uint2* packed, unsign
 // given, which is copied instead), avoid and reward flags per state.
 hipError_t launch_ac_sets(const AcSpec& S, const AcSets& sets, const float* G_in, int32_t* G, uint8_t* avoid,
                           uint8_t* reward, hipStream_t s);
-// Reverse rows of the packed table: counts into rptr[1..], scan, fill.
-// `cursor` has N4 * N3 * K words.
+// Reverse rows of the packed table: counts into rptr[1..], scan, fill,
+// sort.  `cursor` has N4 * N3 words.
 hipError_t launch_ac_rev_count(const AcSpec& S, const uint2* tab, uint32_t* rptr, hipStream_t s);
 hipError_t launch_ac_rev_fill(const AcSpec& S, const uint2* tab, const uint32_t* rptr, uint32_t* cursor,
                               uint2* rent, hipStream_t s);
 hipError_t launch_ac_scan(uint32_t* rptr, int64_t rows, hipStream_t s);
+hipError_t launch_ac_sort(const uint32_t* rptr, uint2* rent, int64_t rows, hipStream_t s);
 hipError_t launch_ac_relax(const Inst* dI, const Run& R, int round, int grid, hipStream_t s, bool wide, int stage);
 hipError_t launch_ac_seed(const Inst* dI, const Run& R, int64_t n, hipStream_t s, bool wide);
 // After a round's relax step: every state flagged as improved is expanded
