@@ -804,6 +804,8 @@ def closed_loop(scns, values, policies, rng, start=(840.0, 140.0, 0.0, 53.0)):
     from_paper = x0 >= 0 and bool(values[2][x0] < values[1][x0])
     if not from_paper:
         fin = np.nonzero(values[2] < values[1])[0]
+        if fin.size == 0:  # the reward pays nowhere: any controllable cell off the runway
+            fin = np.nonzero(np.isfinite(values[2]) & ~target)[0]
         x0 = int(fin[rng.integers(0, fin.size)])
         c = np.array([x0 % N1, (x0 // N1) % N2, (x0 // (N1 * N2)) % N3, x0 // (N1 * N2 * N3)])
         st = lo + (c + 0.5) * eta

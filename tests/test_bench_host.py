@@ -84,3 +84,23 @@ def test_cpu_job_reward_chain(monkeypatch):
     want = oracle.solve(p2)["counters"]["edge_relax"]
     assert label == "reward" and r["edge_relax"] == want and r["value"] > 0
     assert np.array_equal(p2.G, oracle.solve(small)["V"])
+
+
+def test_closed_loop_flight_on_the_oracle_controller():
+    """bench.closed_loop flies the mission on the ODE with given controllers:
+    with the oracle's, every flight (from a cell where the reward lowers the
+    value, else from any controllable cell) stays safe, reaches the runway
+    and keeps within V2."""
+    import numpy as np
+
+    import oracle
+    import oracle.aircraft as OA
+    import synth.aircraft as SA
+    s1, s2 = SA.small(1), SA.small(2)
+    r1 = oracle.solve(OA.problem(s1), precision="f32")
+    r2 = oracle.solve(OA.problem(s2, G=r1["V"]), precision="f32")
+    for seed in range(3):
+        res = bench.closed_loop({1: s1, 2: s2}, {1: r1["V"], 2: r2["V"]}, {1: r1["policy"], 2: r2["policy"]},
+                                np.random.default_rng(seed))
+        assert res["safe"] and res["reached_runway"] and res["cost_within_V2"], res
+        assert res["V2_start"] <= res["V1_start"]
