@@ -520,8 +520,8 @@ __device__ __forceinline__ void flush(Counts& c, unsigned long long* s_c, unsign
 }
 
 // One round: every listed pair is evaluated by kLanes lanes, which split its
-// box; the group's first lane forms the backup and updates W(x); the wave
-// then expands its improved states one after the other.
+// box; the group's first lane forms the backup, updates W(x) and flags x as
+// improved for the round's expansion (k_ac_expand).
 template <class T, bool WIDE, bool STAGE2>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 void k_ac_relax(const Inst* __restrict__ It, Run R, int round) {
