@@ -862,6 +862,13 @@ def aircraft_run(args):
 
     import torch
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        # a plain 256 MiB device copy: reference for the HBM byte counters
+        x = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     return aircraft_mission(args.aircraft_grid.split("x"), args.aircraft_cone, args.aircraft_steps,
                             args.aircraft_samples, log=log)
 
