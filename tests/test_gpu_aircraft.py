@@ -29,7 +29,25 @@ def _case(msg):
     print(f"\n[case] {msg}", flush=True)
 
 
+def degenerate_one_input(stage):
+    """One input (no thrust, no bank) and one heading cell: every box wraps
+    the whole heading circle, and every pair leaves the speed range (only
+    the targets off the obstacles keep a finite value)."""
+    import dataclasses
+    s = SA.scenario((4, 3, 1, 6), (100, 60), stage=stage, cone=180)
+    return dataclasses.replace(s, n_thrust=1, n_bank=1)
+
+
+def degenerate_coarse(stage):
+    """One integration step per period, 2 x 3 inputs, 6x4x8x5 cells."""
+    import dataclasses
+    s = SA.scenario((6, 4, 8, 5), (150, 80), stage=stage, cone=90, steps=1)
+    return dataclasses.replace(s, n_thrust=2, n_bank=3)
+
+
 TABLES = {
+    "one_input_pi1": lambda: degenerate_one_input(1),
+    "coarse_pi2": lambda: degenerate_coarse(2),
     "small_pi1": lambda: SA.small(1),
     "small_pi2": lambda: SA.small(2),
     "paper_pi1": lambda: SA.scenario(stage=1),
@@ -56,8 +74,9 @@ def _exact(label, V, pol, res, ref):
     assert badp.size == 0, (label, "policy differs at", badp[:10], pol[badp[:10]], ref["policy"][badp[:10]])
 
 
-@pytest.mark.parametrize("make,wide", [(SA.small, False), (SA.medium, False), (SA.small, True)],
-                         ids=["small", "medium", "small_ids64"])
+@pytest.mark.parametrize("make,wide", [(SA.small, False), (SA.medium, False), (SA.small, True),
+                                       (degenerate_one_input, False), (degenerate_coarse, False)],
+                         ids=["small", "medium", "small_ids64", "one_input", "coarse"])
 def test_mission_parity(make, wide):
     import torch
     s1, s2 = make(1), make(2)
@@ -77,7 +96,8 @@ def test_mission_parity(make, wide):
     r2 = oracle.solve(OA.problem(s2, G=r1["V"]), precision="f32")
     _exact("pi1", V1.cpu().numpy(), pol1, res1, r1)
     _exact("pi2", V2, pol2, res2, r2)
-    assert st1["rounds"] >= 2 and np.isfinite(r1["V"]).sum() > 1000
+    if make in (SA.small, SA.medium):
+        assert st1["rounds"] >= 2 and np.isfinite(r1["V"]).sum() > 1000
     # G_2 = V_1 bounds the second problem's values (stopping at once is
     # always allowed)
     assert np.all(r2["V"] <= r1["V"])
