@@ -86,6 +86,31 @@ def roofline(stats, npairs, per_edge, small_lds=False):
             "launches_per_solve": launches / len(stats), "algorithmic_bytes_per_launch": nbytes}
 
 
+AC_SRC = os.path.join(ROOT, "paper_2001_06231_amd", "csrc", "gbf_aircraft.hip")
+AC_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "aircraft_traffic_200x70x75x135_k35.txt")
+
+
+def read_ac_traffic():
+    """HBM bytes per relax step (k_ac_relax + k_ac_expand) of the aircraft
+    mission's problem 1 on the paper's grid, raw counters, from the
+    committed summary; None if missing or taken on another source."""
+    if not os.path.exists(AC_TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(AC_TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    with open(AC_SRC, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()[:16]
+    if kv.get("aircraft_source_sha256_16") != h:
+        return None
+    try:
+        return float(kv["hbm_bytes_raw"]) / float(kv["relax_launches"])
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+
+
 def read_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary,
     or None if it is missing or was taken on a different kernel source."""
@@ -727,7 +752,11 @@ def aircraft_mission(dims, cone=0, steps=4, samples=2000, timed_solve=True, log=
         pol = torch.empty(n, dtype=torch.int32, device="cuda")
         _, res = gr.policy(pol)
         rl = roofline([st_prof], n * K, PER_EDGE_BYTES["box"])
-        rl["kernel"] = "k_ac_relax"
+        rl["kernel"] = "k_ac_relax+k_ac_expand"
+        if stage == 1 and dims == SA.PAPER_DIMS and not cone and steps == 4:
+            # raw counters (the copy's calibration factor does not carry over
+            # to these scattered accesses); per relax step
+            rl["traffic"] = read_ac_traffic()
         Vh = V.cpu().numpy()
         t0 = time.time()
         T = OA.table(scn)
