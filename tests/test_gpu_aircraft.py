@@ -166,3 +166,19 @@ def test_paper_grid_sampled():
         assert OA.sampled_residual(scn, OA.table(scn), Vh, Gh, avoid, reward, xs) == 0
         g.free()
         G, Vprev = V, Vh
+
+
+def test_bench_mission_helper():
+    """The benchmark's mission helper on a reduced grid (the paper's cell
+    sizes over 400 m x 160 m, a 60-degree landing cone): both problems,
+    their oracle checks at sampled states, and the closed-loop flight."""
+    import bench
+    _case("bench.aircraft_mission 32x14x75x27 cone 60")
+    out = bench.aircraft_mission((32, 14, 75, 27), cone=60, samples=200, timed_solve=False)
+    for k in ("problem1", "problem2"):
+        p = out[k]
+        assert p["status"] == gbf.OK and p["gpu_residual_states"] == 0, (k, p)
+        assert p["oracle_sample_mismatches"] == 0, (k, p)
+        assert p["roofline"]["kernel"] == "k_ac_relax+k_ac_expand"
+    cl = out["closed_loop"]
+    assert cl["safe"] and cl["cost_within_V2"], cl
